@@ -1,0 +1,187 @@
+/*
+ * hodlr.h -- C ABI of the MI355X HODLRdD library.
+ *
+ * HODLRdD (Khan, Kandappan, Ambikasaran, arXiv 2209.05819) approximates the
+ * N x N kernel matrix K(i,j) = F(x_i, x_j) of N points in d dimensions: the
+ * blocks of far-field and vertex-sharing hyper-cube pairs on every level of a
+ * 2^d tree are compressed with ACA, and the remaining adjacent leaf pairs are
+ * evaluated densely.  This library builds that representation on one AMD
+ * Instinct MI355X (gfx950) and applies it to vectors.
+ *
+ * Conventions for every entry point:
+ *   - Only plain C types cross this boundary.  Every call returns a
+ *     hodlr_status; none aborts.  On failure hodlr_last_error() returns a
+ *     message for the calling thread.
+ *   - "Tree order" is the order of the points sorted by (Morton key of their
+ *     finest-level cell, original index); "user order" is the caller's order.
+ *   - Box indices of a level are positions in that level's list of non-empty
+ *     boxes, which is sorted by Morton key.
+ *   - Streams are hipStream_t values passed as void*; NULL is the null stream.
+ */
+#ifndef HODLR_H
+#define HODLR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct hodlr_handle_s* hodlr_t;
+
+typedef enum {
+    HODLR_OK = 0,
+    HODLR_EINVAL = 1,       /* bad argument (size, tolerance, pointer, level) */
+    HODLR_ENOMEM = 2,       /* device allocation failed or exceeded mem_budget_bytes */
+    HODLR_EDEVICE = 3,      /* a HIP call failed */
+    HODLR_EDUPLICATE = 4,   /* two distinct points coincide under a singular kernel */
+    HODLR_ENONFINITE = 5,   /* NaN or Inf in the points */
+    HODLR_EUNSUPPORTED = 6  /* valid request this build does not handle */
+} hodlr_status;
+
+/* Kernel functions of the paper's sec. 3 list (F1 1/r, F2 log r, F5 r,
+ * F6 sin r, F7 1/sqrt(1+r), F8 exp(-r)), the 4D Laplace kernel 1/r^2 of
+ * sec. 6.2 and the Gaussian of sec. 6.3.  r = |x_i - x_j|_2 (natural log). */
+typedef enum {
+    HODLR_K_LOG = 0,         /* log r           */
+    HODLR_K_INV_R = 1,       /* 1 / r           */
+    HODLR_K_INV_R2 = 2,      /* 1 / r^2         */
+    HODLR_K_GAUSS = 3,       /* exp(-r^2 / h^2) */
+    HODLR_K_EXP = 4,         /* exp(-r / h)     */
+    HODLR_K_R = 5,           /* r               */
+    HODLR_K_SIN = 6,         /* sin r           */
+    HODLR_K_INV_SQRT1P = 7   /* 1 / sqrt(1 + r) */
+} hodlr_kernel_kind;
+
+/* K(i,j) = scale * f(r) for i != j and K(i,i) = diag, decided by the
+ * points' global indices (sec. 6.1 sets the diagonal of log r to 0). */
+typedef struct {
+    int kind;       /* hodlr_kernel_kind */
+    double h;       /* length scale of GAUSS and EXP (> 0) */
+    double scale;
+    double diag;
+} hodlr_kernel;
+
+typedef enum { HODLR_FP64 = 0, HODLR_FP32 = 1, HODLR_BF16 = 2 } hodlr_prec;
+
+typedef struct {
+    /* depth rule (sec. 5.2 / Alg. "HODLRdD Initialization"):
+     * 0 = smallest level whose fullest box holds <= leaf_size points;
+     * 1 = smallest kappa with leaf_size * 2^(d kappa) >= N */
+    int level_rule;
+    /* computational hyper-cube: [domain_lo, domain_lo + domain_side]^d when
+     * has_domain != 0 (points outside -> HODLR_EINVAL), else the bounding cube */
+    int has_domain;
+    double domain_lo[8];
+    double domain_side;
+    int storage;          /* hodlr_prec of the stored U/V factors (FP64 or FP32) */
+    /* 1: store one factor pair per unordered block pair {A,B} and apply
+     * K(B,A) = K(A,B)^T (the kernel is symmetric and both index sets are the
+     * same point set); 0: store a pair for every ordered block (A,B) */
+    int symmetric;
+    int max_rank;         /* cap on every ACA rank; 0 = min(|I|,|J|) */
+    int skip_aca;         /* 1: tree and lists only; factors come from hodlr_import_factors */
+    size_t mem_budget_bytes;  /* cap on device memory held by the handle; 0 = none */
+} hodlr_opts;
+
+/* Defaults: level_rule 0, bounding cube, FP64 storage, symmetric 1,
+ * max_rank 0, skip_aca 0, no budget. */
+void hodlr_default_opts(hodlr_opts* opts);
+
+/* Build the HODLRdD representation (Alg. "HODLRdD Initialization"): the
+ * hyper-cube and 2^d tree (sec. 5.2), the interaction lists of every level
+ * and the near lists of the leaves (sec. 5.3, table of notations and the
+ * HODLRdD admissibility definition), and the ACA factors of every admissible
+ * block (eq. keq1) to relative tolerance tol.
+ *   points    host pointer, N x d row-major FP64, user order; copied.
+ *   N >= 1, 1 <= d <= 8, leaf_size >= 1, 0 <= tol < 1.
+ *   kernel    host pointer; h > 0 for GAUSS and EXP.
+ *   opts      host pointer or NULL for the defaults.
+ *   stream    work is queued on it; the call returns after the build finished.
+ *   out       receives the handle (unchanged on failure).
+ * Errors: EINVAL, ENONFINITE, EDUPLICATE (coincident distinct points under
+ * LOG, INV_R or INV_R2), ENOMEM, EDEVICE. */
+hodlr_status hodlr_build(const double* points, int64_t N, int d, const hodlr_kernel* kernel,
+                         int leaf_size, double tol, const hodlr_opts* opts, void* stream,
+                         hodlr_t* out);
+
+/* Y = K~ X (Alg. "HODLRdD matrix-vector Product"): the low-rank blocks of
+ * every level plus the near field of the leaves, evaluated on the fly.
+ *   X, Y     device pointers, N x nrhs column-major in user order with
+ *            leading dimensions ldx, ldy >= N; element type x_prec
+ *            (FP64 or FP32) for both.  Y must not overlap X.
+ *   compute_prec  FP64: FP64 arithmetic throughout; FP32: FP32 near field
+ *            and FP32 accumulation (factors are read in their storage type).
+ *   Asynchronous on stream; owns a workspace inside the handle, so calls on
+ *   one handle must not overlap in time (serialize them on one stream).
+ * Errors: EINVAL (nrhs < 1, ld < N, bad prec, factors missing), EDEVICE. */
+hodlr_status hodlr_matvec(hodlr_t h, const void* X, int64_t ldx, int nrhs, int x_prec,
+                          void* Y, int64_t ldy, int compute_prec, void* stream);
+
+typedef struct {
+    int64_t N;
+    int d;
+    int kappa;            /* depth of the tree (leaves are level kappa) */
+    int lmax;             /* finest representable level of the Morton keys */
+    int symmetric;
+    int storage;
+    double domain_lo[8];
+    double domain_side;
+    int64_t nboxes[32];       /* non-empty boxes per level 0..kappa */
+    int64_t il_entries[32];   /* interaction-list entries per level */
+    int64_t stored_blocks[32];/* factor pairs held per level */
+    int32_t rank_min[32], rank_max[32];
+    double rank_mean[32];     /* over stored blocks */
+    int64_t factor_elems[32]; /* sum over stored blocks of r(|I|+|J|) */
+    int64_t near_entries;     /* near-list entries at the leaves */
+    int64_t near_pairs;       /* point pairs of the near field */
+    size_t device_bytes;      /* device memory held by the handle */
+    double build_ms[4];       /* tree, lists, ACA, packing */
+} hodlr_info;
+
+hodlr_status hodlr_get_info(hodlr_t h, hodlr_info* info);
+
+/* Tree export (host pointers): perm[N] maps tree position -> user index,
+ * keys[N] the sorted Morton keys.  Either may be NULL. */
+hodlr_status hodlr_export_tree(hodlr_t h, int64_t* perm, uint64_t* keys);
+
+/* Boxes of level l (0..kappa), host pointers: start[nb+1] offsets into tree
+ * order, key[nb] level keys, coord[nb*d] integer box coordinates.  Any may be NULL. */
+hodlr_status hodlr_export_boxes(hodlr_t h, int level, int64_t* start, uint64_t* key,
+                                int32_t* coord);
+
+/* Interaction list of level l (1..kappa) in CSR form over the level's boxes,
+ * columns ascending: ptr[nb+1], col[nnz].  *nnz receives the entry count;
+ * ptr/col may be NULL to query it. */
+hodlr_status hodlr_export_il(hodlr_t h, int level, int64_t* nnz, int64_t* ptr, int32_t* col);
+
+/* Near list of the leaves ({A} and boxes sharing a hyper-surface of
+ * dimension 1..d-1 with A), same CSR convention. */
+hodlr_status hodlr_export_near(hodlr_t h, int64_t* nnz, int64_t* ptr, int32_t* col);
+
+/* Factors of level l in the interaction list's CSR order, for every entry
+ * (A,B): U (|A| x r, column after column) and V (r x |B|, row after row),
+ * concatenated; FP64 host pointers.  ranks[nnz] receives r per entry;
+ * *u_elems / *v_elems receive the totals (U, V may be NULL to query).
+ * In symmetric mode the entry (B,A) is exported as the transpose of the
+ * stored pair of (A,B). */
+hodlr_status hodlr_export_factors(hodlr_t h, int level, int32_t* ranks, int64_t* u_elems,
+                                  int64_t* v_elems, double* U, double* V);
+
+/* Install factors of level l from host memory in the layout of
+ * hodlr_export_factors (replacing any present).  In symmetric mode only the
+ * entries (A,B) with A < B are read; the others are ignored.  Meant for
+ * testing the apply with externally computed factors. */
+hodlr_status hodlr_import_factors(hodlr_t h, int level, const int32_t* ranks, const double* U,
+                                  const double* V);
+
+void hodlr_destroy(hodlr_t h);
+
+/* Message of the calling thread's last failure ("" if none). */
+const char* hodlr_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,250 @@
+"""MI355X-native HODLRdD matrix-vector product.
+
+Thin ctypes binding of ``libhodlr.so`` (C ABI in ``include/hodlr.h``).  The
+functions below only marshal arguments: every step of the method (tree,
+interaction lists, ACA, apply, near field) runs in the library's HIP kernels.
+PyTorch supplies device memory and streams.  There is no CPU fallback: if the
+library is not built, every call raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libhodlr.so")
+
+FP64, FP32, BF16 = 0, 1, 2
+KERNELS = {"log": 0, "inv_r": 1, "inv_r2": 2, "gauss": 3, "exp": 4, "r": 5, "sin": 6,
+           "inv_sqrt1p": 7}
+STATUS = {0: "OK", 1: "EINVAL", 2: "ENOMEM", 3: "EDEVICE", 4: "EDUPLICATE", 5: "ENONFINITE",
+          6: "EUNSUPPORTED"}
+
+
+class HodlrError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Kernel(C.Structure):
+    _fields_ = [("kind", C.c_int), ("h", C.c_double), ("scale", C.c_double), ("diag", C.c_double)]
+
+
+class Opts(C.Structure):
+    _fields_ = [("level_rule", C.c_int), ("has_domain", C.c_int),
+                ("domain_lo", C.c_double * 8), ("domain_side", C.c_double),
+                ("storage", C.c_int), ("symmetric", C.c_int), ("max_rank", C.c_int),
+                ("skip_aca", C.c_int), ("mem_budget_bytes", C.c_size_t)]
+
+
+class Info(C.Structure):
+    _fields_ = [("N", C.c_int64), ("d", C.c_int), ("kappa", C.c_int), ("lmax", C.c_int),
+                ("symmetric", C.c_int), ("storage", C.c_int),
+                ("domain_lo", C.c_double * 8), ("domain_side", C.c_double),
+                ("nboxes", C.c_int64 * 32), ("il_entries", C.c_int64 * 32),
+                ("stored_blocks", C.c_int64 * 32), ("rank_min", C.c_int32 * 32),
+                ("rank_max", C.c_int32 * 32), ("rank_mean", C.c_double * 32),
+                ("factor_elems", C.c_int64 * 32), ("near_entries", C.c_int64),
+                ("near_pairs", C.c_int64), ("device_bytes", C.c_size_t),
+                ("build_ms", C.c_double * 4)]
+
+
+_lib = None
+_P = C.c_void_p
+_i64 = C.c_int64
+
+
+def lib():
+    """Load the HIP library (raises if it was not built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"HIP library {LIB_PATH} is not built; run "
+                               "paper_2209_05819_amd.build.build()")
+        L = C.CDLL(LIB_PATH)
+        L.hodlr_default_opts.argtypes = [C.POINTER(Opts)]
+        L.hodlr_build.argtypes = [_P, _i64, C.c_int, C.POINTER(Kernel), C.c_int, C.c_double,
+                                  C.POINTER(Opts), _P, C.POINTER(_P)]
+        L.hodlr_matvec.argtypes = [_P, _P, _i64, C.c_int, C.c_int, _P, _i64, C.c_int, _P]
+        L.hodlr_get_info.argtypes = [_P, C.POINTER(Info)]
+        L.hodlr_export_tree.argtypes = [_P, _P, _P]
+        L.hodlr_export_boxes.argtypes = [_P, C.c_int, _P, _P, _P]
+        L.hodlr_export_il.argtypes = [_P, C.c_int, C.POINTER(_i64), _P, _P]
+        L.hodlr_export_near.argtypes = [_P, C.POINTER(_i64), _P, _P]
+        L.hodlr_export_factors.argtypes = [_P, C.c_int, _P, C.POINTER(_i64), C.POINTER(_i64),
+                                           _P, _P]
+        L.hodlr_import_factors.argtypes = [_P, C.c_int, _P, _P, _P]
+        L.hodlr_destroy.argtypes = [_P]
+        L.hodlr_last_error.restype = C.c_char_p
+        for f in ("hodlr_build", "hodlr_matvec", "hodlr_get_info", "hodlr_export_tree",
+                  "hodlr_export_boxes", "hodlr_export_il", "hodlr_export_near",
+                  "hodlr_export_factors", "hodlr_import_factors"):
+            getattr(L, f).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _check(st: int):
+    if st != 0:
+        raise HodlrError(st, lib().hodlr_last_error().decode())
+
+
+def _np_ptr(a: np.ndarray):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+def default_opts() -> Opts:
+    o = Opts()
+    lib().hodlr_default_opts(C.byref(o))
+    return o
+
+
+def make_kernel(kind, h: float = 1.0, scale: float = 1.0, diag: float = 0.0) -> Kernel:
+    return Kernel(KERNELS[kind] if isinstance(kind, str) else int(kind), float(h), float(scale),
+                  float(diag))
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        import torch
+        return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    return C.c_void_p(int(stream))
+
+
+def hodlr_build(points: np.ndarray, kernel: Kernel, leaf_size: int, tol: float,
+                opts: Opts | None = None, stream=None) -> int:
+    P = np.ascontiguousarray(points, dtype=np.float64)
+    N, d = P.shape
+    out = C.c_void_p()
+    _check(lib().hodlr_build(_np_ptr(P), N, d, C.byref(kernel), int(leaf_size), float(tol),
+                             C.byref(opts) if opts is not None else None, _stream_ptr(stream),
+                             C.byref(out)))
+    return out.value
+
+
+def hodlr_matvec(h: int, X, Y, compute_prec: int = FP64, stream=None) -> None:
+    """Y = K~ X for torch tensors on the GPU: N x nrhs, column-major
+    (a (nrhs, N) contiguous tensor transposed, or a 1-D vector)."""
+    import torch
+    if X.dtype != Y.dtype or X.dtype not in (torch.float64, torch.float32):
+        raise TypeError("X and Y must both be float64 or float32")
+    if not (X.is_cuda and Y.is_cuda):
+        raise TypeError("X and Y must be device tensors")
+    xp = FP64 if X.dtype == torch.float64 else FP32
+    if X.dim() == 1:
+        N, nrhs, ldx, ldy = X.shape[0], 1, X.shape[0], Y.shape[0]
+    else:
+        N, nrhs = X.shape
+        if X.stride(0) != 1 or Y.stride(0) != 1:
+            raise ValueError("X and Y must be column-major (stride 1 along N)")
+        ldx, ldy = X.stride(1) if nrhs > 1 else N, Y.stride(1) if nrhs > 1 else N
+    _check(lib().hodlr_matvec(C.c_void_p(h), C.c_void_p(X.data_ptr()), ldx, nrhs, xp,
+                              C.c_void_p(Y.data_ptr()), ldy, compute_prec, _stream_ptr(stream)))
+
+
+def hodlr_get_info(h: int) -> Info:
+    info = Info()
+    _check(lib().hodlr_get_info(C.c_void_p(h), C.byref(info)))
+    return info
+
+
+def hodlr_export_tree(h: int, N: int):
+    perm = np.empty(N, dtype=np.int64)
+    keys = np.empty(N, dtype=np.uint64)
+    _check(lib().hodlr_export_tree(C.c_void_p(h), _np_ptr(perm), _np_ptr(keys)))
+    return perm, keys
+
+
+def hodlr_export_boxes(h: int, level: int, nb: int, d: int):
+    start = np.empty(nb + 1, dtype=np.int64)
+    key = np.empty(max(nb, 1), dtype=np.uint64)
+    coord = np.empty((max(nb, 1), d), dtype=np.int32)
+    _check(lib().hodlr_export_boxes(C.c_void_p(h), level, _np_ptr(start), _np_ptr(key),
+                                    _np_ptr(coord)))
+    return start, key[:nb], coord[:nb]
+
+
+def hodlr_export_il(h: int, level: int, nb: int):
+    nnz = C.c_int64()
+    _check(lib().hodlr_export_il(C.c_void_p(h), level, C.byref(nnz), None, None))
+    ptr = np.empty(nb + 1, dtype=np.int64)
+    col = np.empty(max(nnz.value, 1), dtype=np.int32)
+    _check(lib().hodlr_export_il(C.c_void_p(h), level, C.byref(nnz), _np_ptr(ptr), _np_ptr(col)))
+    return ptr, col[:nnz.value]
+
+
+def hodlr_export_near(h: int, nb: int):
+    nnz = C.c_int64()
+    _check(lib().hodlr_export_near(C.c_void_p(h), C.byref(nnz), None, None))
+    ptr = np.empty(nb + 1, dtype=np.int64)
+    col = np.empty(max(nnz.value, 1), dtype=np.int32)
+    _check(lib().hodlr_export_near(C.c_void_p(h), C.byref(nnz), _np_ptr(ptr), _np_ptr(col)))
+    return ptr, col[:nnz.value]
+
+
+def hodlr_export_factors(h: int, level: int, nnz: int):
+    ranks = np.empty(max(nnz, 1), dtype=np.int32)
+    nu, nv = C.c_int64(), C.c_int64()
+    _check(lib().hodlr_export_factors(C.c_void_p(h), level, _np_ptr(ranks), C.byref(nu),
+                                      C.byref(nv), None, None))
+    U = np.empty(max(nu.value, 1))
+    V = np.empty(max(nv.value, 1))
+    _check(lib().hodlr_export_factors(C.c_void_p(h), level, None, None, None, _np_ptr(U),
+                                      _np_ptr(V)))
+    return ranks[:nnz], U[:nu.value], V[:nv.value]
+
+
+def hodlr_import_factors(h: int, level: int, ranks, U, V) -> None:
+    r = np.ascontiguousarray(ranks, dtype=np.int32)
+    Ua = np.ascontiguousarray(U, dtype=np.float64)
+    Va = np.ascontiguousarray(V, dtype=np.float64)
+    _check(lib().hodlr_import_factors(C.c_void_p(h), level, _np_ptr(r), _np_ptr(Ua), _np_ptr(Va)))
+
+
+def hodlr_destroy(h: int) -> None:
+    if h:
+        lib().hodlr_destroy(C.c_void_p(h))
+
+
+class HODLR:
+    """Owning wrapper: build on construction, destroy when collected."""
+
+    def __init__(self, points, kernel: Kernel, leaf_size: int, tol: float, *, level_rule=0,
+                 domain=None, storage=FP64, symmetric=True, max_rank=0, skip_aca=False,
+                 mem_budget_bytes=0, stream=None):
+        o = default_opts()
+        o.level_rule = level_rule
+        if domain is not None:
+            o.has_domain = 1
+            lo = np.asarray(domain[0], dtype=np.float64)
+            for a in range(len(lo)):
+                o.domain_lo[a] = lo[a]
+            o.domain_side = float(domain[1])
+        o.storage = storage
+        o.symmetric = 1 if symmetric else 0
+        o.max_rank = int(max_rank)
+        o.skip_aca = 1 if skip_aca else 0
+        o.mem_budget_bytes = int(mem_budget_bytes)
+        self.points = np.ascontiguousarray(points, dtype=np.float64)
+        self.N, self.d = self.points.shape
+        self.h = hodlr_build(self.points, kernel, leaf_size, tol, o, stream)
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h:
+            hodlr_destroy(h)
+            self.h = None
+
+    def info(self) -> Info:
+        return hodlr_get_info(self.h)
+
+    def matvec(self, X, compute_prec: int = FP64, out=None, stream=None):
+        import torch
+        if out is None:
+            out = torch.empty_like(X) if X.dim() == 1 else torch.empty(
+                (X.shape[1], X.shape[0]), dtype=X.dtype, device=X.device).t()
+        hodlr_matvec(self.h, X, out, compute_prec, stream)
+        return out

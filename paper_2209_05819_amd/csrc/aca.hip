@@ -1,0 +1,649 @@
+// ACA compression of every stored interaction-list block (paper eq. keq1,
+// Alg. "HODLRdD Initialization"): partial-pivot cross approximation in FP64,
+// one workgroup per block.  Small blocks keep their factors in LDS for the
+// whole iteration; larger ones iterate in a global FP64 workspace.  Finished
+// factors are packed into per-chunk arenas in the storage precision.
+//
+// The iteration (the same rule as the reference CPU implementation):
+//   row residual of pivot row i*, column pivot j* = largest |entry| (lowest
+//   index on ties); a zero pivot marks the row tried and restarts from the
+//   lowest untried row; otherwise v = row / pivot, u = residual of column j*;
+//   the candidate term u v is dropped and the iteration ends when
+//   |u||v| <= tol * |S|_F with S the approximation including it; the next
+//   pivot row is the untried row with the largest |u_i|.
+#include <algorithm>
+#include <climits>
+
+#include "hodlr_impl.hpp"
+
+namespace hodlr {
+
+namespace {
+
+constexpr int T = 256;
+constexpr int NW = T / 64;
+
+struct AcaJob {
+    int32_t a0, m, b0, n;
+    int32_t kmax;   // min(m, n, max_rank)
+    int32_t cap;    // columns available in the workspace
+    int64_t ws;     // offset (in doubles) of the job's workspace
+    int64_t block;  // global block index
+};
+
+__device__ __forceinline__ double wave_sum(double v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// larger |value| wins, ties -> lower index
+__device__ __forceinline__ void wave_argmax(double& v, int& i) {
+    for (int o = 32; o > 0; o >>= 1) {
+        double ov = __shfl_xor(v, o, 64);
+        int oi = __shfl_xor(i, o, 64);
+        if (ov > v || (ov == v && oi < i)) {
+            v = ov;
+            i = oi;
+        }
+    }
+}
+
+__device__ __forceinline__ int wave_min(int v) {
+    for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+template <bool kLds>
+__global__ __launch_bounds__(T) void k_aca(const double* __restrict__ pts, int64_t N, int d,
+                                           KParams kp, double tol, const AcaJob* __restrict__ jobs,
+                                           double* __restrict__ wsbase, int32_t* __restrict__ ranks,
+                                           int32_t* __restrict__ overflow) {
+    extern __shared__ double dyn[];
+    __shared__ double red_v[NW], red_w[NW], red_x[NW];
+    __shared__ int red_i[NW], red_j[NW];
+    __shared__ int sh_k, sh_istar, sh_nused, sh_done, sh_jstar;
+    __shared__ double sh_S2, sh_piv;
+
+    const AcaJob J = jobs[blockIdx.x];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int m = J.m, n = J.n;
+    const int kcap = min(J.kmax, J.cap);
+    double* s_a = dyn;            // U[p][i*] then cross products
+    double* s_b = dyn + J.cap;    // V[p][j*]
+    double* ws = wsbase + J.ws;
+    double* U;
+    double* V;
+    unsigned char* used;
+    if (kLds) {
+        U = dyn + 2 * J.cap;
+        V = U + (int64_t)J.cap * m;
+        used = reinterpret_cast<unsigned char*>(V + (int64_t)J.cap * n);
+    } else {
+        U = ws;
+        V = ws + (int64_t)J.cap * m;
+        used = reinterpret_cast<unsigned char*>(V + (int64_t)J.cap * n);
+    }
+    const double* __restrict__ X = pts + J.a0;   // coordinate a of row i: X[a*N + i]
+    const double* __restrict__ Y = pts + J.b0;
+
+    for (int i = tid; i < m; i += T) used[i] = 0;
+    if (tid == 0) {
+        sh_k = 0;
+        sh_istar = 0;
+        sh_nused = 0;
+        sh_done = 0;
+        sh_S2 = 0.0;
+    }
+    __syncthreads();
+    int ovf = 0;
+    for (;;) {
+        const int k = sh_k;
+        const int istar = sh_istar;
+        if (k >= kcap) {
+            ovf = (k < J.kmax) ? 1 : 0;
+            break;
+        }
+        for (int p = tid; p < k; p += T) s_a[p] = U[(int64_t)p * m + istar];
+        double xi[kMaxD];
+        for (int a = 0; a < d; ++a) xi[a] = X[a * N + istar];
+        __syncthreads();
+        // residual of the pivot row, written as row k of V
+        double bv = -1.0;
+        int bi = INT_MAX;
+        double* Vk = V + (int64_t)k * n;
+        for (int j = tid; j < n; j += T) {
+            double r2 = 0.0;
+            for (int a = 0; a < d; ++a) {
+                double t = xi[a] - Y[a * N + j];
+                r2 += t * t;
+            }
+            double v = kfun(kp, r2);
+            for (int p = 0; p < k; ++p) v -= s_a[p] * V[(int64_t)p * n + j];
+            Vk[j] = v;
+            double av = fabs(v);
+            if (av > bv) {
+                bv = av;
+                bi = j;
+            }
+        }
+        wave_argmax(bv, bi);
+        if (lane == 0) {
+            red_v[wv] = bv;
+            red_i[wv] = bi;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            double b = red_v[0];
+            int ix = red_i[0];
+            for (int w = 1; w < NW; ++w)
+                if (red_v[w] > b || (red_v[w] == b && red_i[w] < ix)) {
+                    b = red_v[w];
+                    ix = red_i[w];
+                }
+            // no finite maximum (non-finite entries): treat the row as zero
+            if (ix < 0 || ix >= n) {
+                sh_jstar = 0;
+                sh_piv = 0.0;
+            } else {
+                sh_jstar = ix;
+                sh_piv = Vk[ix];
+            }
+            if (!used[istar]) {
+                used[istar] = 1;
+                sh_nused += 1;
+            }
+        }
+        __syncthreads();
+        const int jstar = sh_jstar;
+        const double piv = sh_piv;
+        if (piv == 0.0) {
+            if (sh_nused == m) break;
+            int mi = INT_MAX;
+            for (int i = tid; i < m; i += T)
+                if (!used[i]) {
+                    mi = i;
+                    break;
+                }
+            mi = wave_min(mi);
+            if (lane == 0) red_i[wv] = mi;
+            __syncthreads();
+            if (tid == 0) {
+                int b = red_i[0];
+                for (int w = 1; w < NW; ++w) b = min(b, red_i[w]);
+                // b < m: nused < m guarantees an untried row
+                if (b < 0 || b >= m) sh_done = 1;
+                sh_istar = (b < 0 || b >= m) ? 0 : b;
+            }
+            __syncthreads();
+            if (sh_done) break;
+            continue;
+        }
+        double nv2 = 0.0;
+        for (int j = tid; j < n; j += T) {
+            double v = Vk[j] / piv;
+            Vk[j] = v;
+            nv2 += v * v;
+        }
+        for (int p = tid; p < k; p += T) s_b[p] = V[(int64_t)p * n + jstar];
+        double yj[kMaxD];
+        for (int a = 0; a < d; ++a) yj[a] = Y[a * N + jstar];
+        __syncthreads();
+        // residual of the pivot column, written as column k of U
+        double nu2 = 0.0, bu = -1.0;
+        int bui = INT_MAX;
+        double* Uk = U + (int64_t)k * m;
+        for (int i = tid; i < m; i += T) {
+            double r2 = 0.0;
+            for (int a = 0; a < d; ++a) {
+                double t = X[a * N + i] - yj[a];
+                r2 += t * t;
+            }
+            double u = kfun(kp, r2);
+            for (int p = 0; p < k; ++p) u -= U[(int64_t)p * m + i] * s_b[p];
+            Uk[i] = u;
+            nu2 += u * u;
+            if (!used[i] && fabs(u) > bu) {
+                bu = fabs(u);
+                bui = i;
+            }
+        }
+        nu2 = wave_sum(nu2);
+        nv2 = wave_sum(nv2);
+        wave_argmax(bu, bui);
+        if (lane == 0) {
+            red_v[wv] = nu2;
+            red_w[wv] = nv2;
+            red_x[wv] = bu;
+            red_j[wv] = bui;
+        }
+        __syncthreads();
+        // cross terms (U_p . u)(V_p . v), p < k; wave w takes p = w, w + NW, ...
+        for (int p = wv; p < k; p += NW) {
+            double su = 0.0, sv = 0.0;
+            const double* Up = U + (int64_t)p * m;
+            const double* Vp = V + (int64_t)p * n;
+            for (int i = lane; i < m; i += 64) su += Up[i] * Uk[i];
+            for (int j = lane; j < n; j += 64) sv += Vp[j] * Vk[j];
+            su = wave_sum(su);
+            sv = wave_sum(sv);
+            if (lane == 0) s_a[p] = su * sv;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            double tnu = 0.0, tnv = 0.0, b = red_x[0];
+            int ix = red_j[0];
+            for (int w = 0; w < NW; ++w) {
+                tnu += red_v[w];
+                tnv += red_w[w];
+            }
+            for (int w = 1; w < NW; ++w)
+                if (red_x[w] > b || (red_x[w] == b && red_j[w] < ix)) {
+                    b = red_x[w];
+                    ix = red_j[w];
+                }
+            double cross = 0.0;
+            for (int p = 0; p < k; ++p) cross += s_a[p];
+            const double S2new = sh_S2 + 2.0 * cross + tnu * tnv;
+            if (k > 0 && sqrt(tnu * tnv) <= tol * sqrt(S2new)) {
+                sh_done = 1;
+            } else {
+                sh_S2 = S2new;
+                sh_k = k + 1;
+                // ix is out of range only if every untried |u_i| is non-finite
+                if (sh_nused == m || ix < 0 || ix >= m)
+                    sh_done = 1;
+                else
+                    sh_istar = ix;
+            }
+        }
+        __syncthreads();
+        if (sh_done) break;
+    }
+    __syncthreads();
+    const int r = sh_k;
+    if (kLds) {
+        // move the finished factors out of LDS: same layout as the workspace
+        double* gU = ws;
+        double* gV = ws + (int64_t)J.cap * m;
+        for (int64_t e = tid; e < (int64_t)r * m; e += T) gU[e] = U[e];
+        for (int64_t e = tid; e < (int64_t)r * n; e += T) gV[e] = V[e];
+    }
+    if (tid == 0) {
+        ranks[blockIdx.x] = r;
+        overflow[blockIdx.x] = ovf;
+    }
+}
+
+template <typename S>
+__device__ __forceinline__ S to_storage(double v);
+template <>
+__device__ __forceinline__ double to_storage<double>(double v) {
+    return v;
+}
+template <>
+__device__ __forceinline__ float to_storage<float>(double v) {
+    return (float)v;
+}
+
+// copy each job's first r columns of U and rows of V into the arena and
+// record the addresses in the block table
+template <typename S>
+__global__ void k_pack(const AcaJob* __restrict__ jobs, const double* __restrict__ wsbase,
+                       const int32_t* __restrict__ ranks, const int64_t* __restrict__ uoff,
+                       const int64_t* __restrict__ voff, S* __restrict__ arena_u,
+                       S* __restrict__ arena_v, BlockDesc* __restrict__ blocks) {
+    const AcaJob J = jobs[blockIdx.x];
+    const int r = ranks[blockIdx.x];
+    const double* gU = wsbase + J.ws;
+    const double* gV = gU + (int64_t)J.cap * J.m;
+    S* dU = arena_u + uoff[blockIdx.x];
+    S* dV = arena_v + voff[blockIdx.x];
+    for (int64_t e = threadIdx.x; e < (int64_t)r * J.m; e += blockDim.x) dU[e] = to_storage<S>(gU[e]);
+    for (int64_t e = threadIdx.x; e < (int64_t)r * J.n; e += blockDim.x) dV[e] = to_storage<S>(gV[e]);
+    if (threadIdx.x == 0) {
+        BlockDesc& b = blocks[J.block];
+        b.rank = r;
+        b.U = reinterpret_cast<uint64_t>(dU);
+        b.V = reinterpret_cast<uint64_t>(dV);
+    }
+}
+
+__global__ void k_sizes(const AcaJob* __restrict__ jobs, const int32_t* __restrict__ ranks,
+                        int64_t njobs, int64_t* __restrict__ su, int64_t* __restrict__ sv) {
+    int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (t >= njobs) return;
+    su[t] = (int64_t)ranks[t] * jobs[t].m;
+    sv[t] = (int64_t)ranks[t] * jobs[t].n;
+}
+
+size_t job_lds_bytes(const AcaJob& j) {
+    return sizeof(double) * (2 * (size_t)j.cap + (size_t)j.cap * (j.m + j.n)) + (size_t)j.m + 8;
+}
+
+size_t job_ws_doubles(const AcaJob& j) {
+    return (size_t)j.cap * (j.m + j.n) + ((size_t)j.m + 7) / 8;
+}
+
+size_t storage_size(int storage) { return storage == HODLR_FP32 ? 4 : 8; }
+
+struct ChunkResult {
+    std::vector<int32_t> ranks, overflow;
+};
+
+// compress one chunk of jobs, pack into a new arena
+void run_chunk(hodlr_t h, std::vector<AcaJob>& jobs, bool lds, size_t lds_bytes,
+               std::vector<int32_t>& ranks_out, std::vector<int32_t>& ovf_out, hipStream_t s) {
+    const int64_t nj = (int64_t)jobs.size();
+    size_t ws_total = 0;
+    for (auto& j : jobs) {
+        j.ws = (int64_t)ws_total;
+        ws_total += job_ws_doubles(j);
+    }
+    AcaJob* djobs = (AcaJob*)dalloc(h, sizeof(AcaJob) * nj);
+    double* ws = (double*)dalloc(h, sizeof(double) * std::max<size_t>(ws_total, 1));
+    int32_t* dr = (int32_t*)dalloc(h, sizeof(int32_t) * nj);
+    int32_t* dov = (int32_t*)dalloc(h, sizeof(int32_t) * nj);
+    HIP_CHECK(hipMemcpyAsync(djobs, jobs.data(), sizeof(AcaJob) * nj, hipMemcpyHostToDevice, s));
+    const double tol = h->tol;
+    if (lds) {
+        HIP_CHECK(hipFuncSetAttribute((const void*)k_aca<true>,
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes));
+        k_aca<true><<<(unsigned)nj, T, lds_bytes, s>>>(h->pts, h->N, h->d, h->kp, tol, djobs, ws,
+                                                       dr, dov);
+    } else {
+        size_t small = 0;
+        for (auto& j : jobs) small = std::max(small, sizeof(double) * 2 * (size_t)j.cap);
+        HIP_CHECK(hipFuncSetAttribute((const void*)k_aca<false>,
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)small));
+        k_aca<false><<<(unsigned)nj, T, small, s>>>(h->pts, h->N, h->d, h->kp, tol, djobs, ws,
+                                                    dr, dov);
+    }
+    HIP_CHECK(hipGetLastError());
+    ranks_out.resize(nj);
+    ovf_out.resize(nj);
+    HIP_CHECK(hipMemcpyAsync(ranks_out.data(), dr, sizeof(int32_t) * nj, hipMemcpyDeviceToHost, s));
+    HIP_CHECK(hipMemcpyAsync(ovf_out.data(), dov, sizeof(int32_t) * nj, hipMemcpyDeviceToHost, s));
+    HIP_CHECK(hipStreamSynchronize(s));
+    // pack the jobs that converged; overflowing ones are retried by the caller
+    std::vector<AcaJob> ok;
+    std::vector<int32_t> okr;
+    for (int64_t t = 0; t < nj; ++t)
+        if (!ovf_out[t]) {
+            ok.push_back(jobs[t]);
+            okr.push_back(ranks_out[t]);
+        }
+    const int64_t nk = (int64_t)ok.size();
+    if (nk > 0) {
+        HIP_CHECK(hipMemcpyAsync(djobs, ok.data(), sizeof(AcaJob) * nk, hipMemcpyHostToDevice, s));
+        HIP_CHECK(hipMemcpyAsync(dr, okr.data(), sizeof(int32_t) * nk, hipMemcpyHostToDevice, s));
+        int64_t* su = (int64_t*)dalloc(h, sizeof(int64_t) * nk);
+        int64_t* sv = (int64_t*)dalloc(h, sizeof(int64_t) * nk);
+        int64_t* ou = (int64_t*)dalloc(h, sizeof(int64_t) * nk);
+        int64_t* ov = (int64_t*)dalloc(h, sizeof(int64_t) * nk);
+        k_sizes<<<nblk(nk, 256), 256, 0, s>>>(djobs, dr, nk, su, sv);
+        HIP_CHECK(hipGetLastError());
+        exclusive_scan_i64(su, ou, nk, s);
+        exclusive_scan_i64(sv, ov, nk, s);
+        int64_t tu = 0, tv = 0;
+        for (int64_t t = 0; t < nk; ++t) {
+            tu += (int64_t)okr[t] * ok[t].m;
+            tv += (int64_t)okr[t] * ok[t].n;
+        }
+        const size_t es = storage_size(h->opts.storage);
+        char* arena = (char*)dalloc(h, es * (size_t)std::max<int64_t>(tu + tv, 1));
+        h->arenas.push_back(arena);
+        if (h->opts.storage == HODLR_FP32)
+            k_pack<float><<<(unsigned)nk, 256, 0, s>>>(djobs, ws, dr, ou, ov, (float*)arena,
+                                                       (float*)arena + tu, h->blocks);
+        else
+            k_pack<double><<<(unsigned)nk, 256, 0, s>>>(djobs, ws, dr, ou, ov, (double*)arena,
+                                                        (double*)arena + tu, h->blocks);
+        HIP_CHECK(hipGetLastError());
+        HIP_CHECK(hipStreamSynchronize(s));
+        dfree(h, su);
+        dfree(h, sv);
+        dfree(h, ou);
+        dfree(h, ov);
+    }
+    dfree(h, djobs);
+    dfree(h, ws);
+    dfree(h, dr);
+    dfree(h, dov);
+}
+
+}  // namespace
+
+void compress_all(hodlr_t h, hipStream_t s) {
+    int dev_lds = 0;
+    HIP_CHECK(hipDeviceGetAttribute(&dev_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, h->device));
+    const size_t static_lds = 1024;
+    const size_t lds_limit = (size_t)std::min(dev_lds, 64 * 1024) - static_lds;
+    size_t freeb = 0, totalb = 0;
+    HIP_CHECK(hipMemGetInfo(&freeb, &totalb));
+    const size_t ws_budget = std::max<size_t>(std::min<size_t>(freeb / 4, (size_t)16 << 30), 64 << 20);
+    const int maxr = h->opts.max_rank > 0 ? h->opts.max_rank : INT_MAX;
+
+    std::vector<AcaJob> lds_jobs, glob_jobs;
+    for (int64_t b = 0; b < h->nblocks; ++b) {
+        const BlockDesc& bd = h->hblocks[b];
+        AcaJob j{};
+        j.a0 = bd.a0;
+        j.m = bd.m;
+        j.b0 = bd.b0;
+        j.n = bd.n;
+        j.kmax = std::min(std::min(bd.m, bd.n), maxr);
+        j.block = b;
+        j.cap = j.kmax;
+        if (j.kmax <= kAcaMaxRank && job_lds_bytes(j) <= lds_limit) {
+            lds_jobs.push_back(j);
+        } else {
+            j.cap = std::min(j.kmax, 256);
+            glob_jobs.push_back(j);
+        }
+    }
+    std::vector<int32_t> rk, ov;
+    // LDS-resident blocks, in chunks bounded by the workspace budget
+    for (size_t i = 0; i < lds_jobs.size();) {
+        std::vector<AcaJob> chunk;
+        size_t bytes = 0, lmax = 0;
+        while (i < lds_jobs.size() &&
+               (chunk.empty() || bytes + 8 * job_ws_doubles(lds_jobs[i]) <= ws_budget)) {
+            bytes += 8 * job_ws_doubles(lds_jobs[i]);
+            lmax = std::max(lmax, job_lds_bytes(lds_jobs[i]));
+            chunk.push_back(lds_jobs[i++]);
+        }
+        run_chunk(h, chunk, true, lmax, rk, ov, s);
+    }
+    // workspace blocks: a first pass with a modest rank cap, retries with more room
+    while (!glob_jobs.empty()) {
+        std::vector<AcaJob> retry;
+        for (size_t i = 0; i < glob_jobs.size();) {
+            std::vector<AcaJob> chunk;
+            size_t bytes = 0;
+            while (i < glob_jobs.size() &&
+                   (chunk.empty() || bytes + 8 * job_ws_doubles(glob_jobs[i]) <= ws_budget)) {
+                bytes += 8 * job_ws_doubles(glob_jobs[i]);
+                chunk.push_back(glob_jobs[i++]);
+            }
+            run_chunk(h, chunk, false, 0, rk, ov, s);
+            for (size_t t = 0; t < chunk.size(); ++t)
+                if (ov[t]) {
+                    AcaJob j = chunk[t];
+                    if (j.cap >= std::min(j.kmax, kAcaMaxRank))
+                        fail(HODLR_EUNSUPPORTED,
+                             "an ACA rank exceeds the device compressor's limit of 1024; "
+                             "set max_rank");
+                    j.cap = std::min(std::min(j.kmax, kAcaMaxRank), j.cap * 4);
+                    retry.push_back(j);
+                }
+        }
+        glob_jobs.swap(retry);
+    }
+    for (int l = 1; l <= h->kappa; ++l) h->lev[l].has_factors = true;
+    finalize_factors(h, s);
+}
+
+// ranks -> projection offsets; host copy of the block table
+__global__ void k_rank_of(const BlockDesc* __restrict__ b, int64_t n, int64_t* __restrict__ r) {
+    int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (t < n) r[t] = b[t].rank;
+}
+__global__ void k_set_toff(BlockDesc* __restrict__ b, int64_t n, const int64_t* __restrict__ off) {
+    int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (t < n) b[t].toff = off[t];
+}
+
+void finalize_factors(hodlr_t h, hipStream_t s) {
+    const int64_t nb = h->nblocks;
+    if (nb > 0) {
+        int64_t* r = (int64_t*)dalloc(h, sizeof(int64_t) * nb);
+        int64_t* o = (int64_t*)dalloc(h, sizeof(int64_t) * nb);
+        k_rank_of<<<nblk(nb, 256), 256, 0, s>>>(h->blocks, nb, r);
+        HIP_CHECK(hipGetLastError());
+        exclusive_scan_i64(r, o, nb, s);
+        k_set_toff<<<nblk(nb, 256), 256, 0, s>>>(h->blocks, nb, o);
+        HIP_CHECK(hipGetLastError());
+        HIP_CHECK(hipMemcpyAsync(h->hblocks.data(), h->blocks, sizeof(BlockDesc) * nb,
+                                 hipMemcpyDeviceToHost, s));
+        HIP_CHECK(hipStreamSynchronize(s));
+        dfree(h, r);
+        dfree(h, o);
+    }
+    int64_t tt = 0;
+    for (int64_t b = 0; b < nb; ++b) tt += std::max(h->hblocks[b].rank, 0);
+    h->t_total = tt;
+    plan_apply(h);
+}
+
+// ---------------------------------------------------------------------------
+// factor import / export in the interaction list's CSR order
+// ---------------------------------------------------------------------------
+namespace {
+struct HostCsr {
+    std::vector<int64_t> ptr, eref;
+    std::vector<int32_t> col;
+};
+HostCsr host_csr(hodlr_t h, int level, hipStream_t s) {
+    const LevelData& Lv = h->lev[level];
+    HostCsr c;
+    c.ptr.resize(Lv.nb + 1);
+    c.col.resize(std::max<int64_t>(Lv.nnz, 1));
+    c.eref.resize(std::max<int64_t>(Lv.nnz, 1));
+    HIP_CHECK(hipMemcpyAsync(c.ptr.data(), Lv.il_ptr, sizeof(int64_t) * (Lv.nb + 1),
+                             hipMemcpyDeviceToHost, s));
+    if (Lv.nnz) {
+        HIP_CHECK(hipMemcpyAsync(c.col.data(), Lv.il_col, sizeof(int32_t) * Lv.nnz,
+                                 hipMemcpyDeviceToHost, s));
+        HIP_CHECK(hipMemcpyAsync(c.eref.data(), Lv.eref, sizeof(int64_t) * Lv.nnz,
+                                 hipMemcpyDeviceToHost, s));
+    }
+    HIP_CHECK(hipStreamSynchronize(s));
+    return c;
+}
+}  // namespace
+
+void import_level(hodlr_t h, int level, const int32_t* ranks, const double* U, const double* V,
+                  hipStream_t s) {
+    LevelData& Lv = h->lev[level];
+    HostCsr c = host_csr(h, level, s);
+    const std::vector<int32_t>& st = Lv.hstart;
+    // validate and size the arena (forward entries only)
+    int64_t tu = 0, tv = 0;
+    for (int64_t A = 0; A < Lv.nb; ++A)
+        for (int64_t e = c.ptr[A]; e < c.ptr[A + 1]; ++e) {
+            const int64_t B = c.col[e];
+            const int64_t m = st[A + 1] - st[A], n = st[B + 1] - st[B];
+            if (ranks[e] < 0 || ranks[e] > std::min(m, n))
+                fail(HODLR_EINVAL, "imported rank out of range");
+            if ((c.eref[e] & 1) == 0) {
+                tu += ranks[e] * m;
+                tv += ranks[e] * n;
+            }
+        }
+    if ((tu + tv) > 0 && (!U || !V)) fail(HODLR_EINVAL, "factor arrays missing");
+    const size_t es = storage_size(h->opts.storage);
+    std::vector<char> hbuf(es * (size_t)std::max<int64_t>(tu + tv, 1));
+    char* arena = (char*)dalloc(h, hbuf.size());
+    h->arenas.push_back(arena);
+    int64_t ou = 0, ov = 0, pu = 0, pv = 0;
+    for (int64_t A = 0; A < Lv.nb; ++A)
+        for (int64_t e = c.ptr[A]; e < c.ptr[A + 1]; ++e) {
+            const int64_t B = c.col[e];
+            const int64_t m = st[A + 1] - st[A], n = st[B + 1] - st[B];
+            const int64_t r = ranks[e];
+            if ((c.eref[e] & 1) == 0) {
+                BlockDesc& bd = h->hblocks[c.eref[e] >> 1];
+                bd.rank = (int32_t)r;
+                bd.U = reinterpret_cast<uint64_t>(arena + es * pu);
+                bd.V = reinterpret_cast<uint64_t>(arena + es * (tu + pv));
+                for (int64_t t = 0; t < r * m; ++t) {
+                    if (es == 4)
+                        ((float*)hbuf.data())[pu + t] = (float)U[ou + t];
+                    else
+                        ((double*)hbuf.data())[pu + t] = U[ou + t];
+                }
+                for (int64_t t = 0; t < r * n; ++t) {
+                    if (es == 4)
+                        ((float*)hbuf.data())[tu + pv + t] = (float)V[ov + t];
+                    else
+                        ((double*)hbuf.data())[tu + pv + t] = V[ov + t];
+                }
+                pu += r * m;
+                pv += r * n;
+            }
+            ou += r * m;
+            ov += r * n;
+        }
+    HIP_CHECK(hipMemcpyAsync(arena, hbuf.data(), hbuf.size(), hipMemcpyHostToDevice, s));
+    if (Lv.nblk)
+        HIP_CHECK(hipMemcpyAsync(h->blocks + Lv.blk0, h->hblocks.data() + Lv.blk0,
+                                 sizeof(BlockDesc) * Lv.nblk, hipMemcpyHostToDevice, s));
+    HIP_CHECK(hipStreamSynchronize(s));
+    Lv.has_factors = true;
+    bool all = true;
+    for (int l = 1; l <= h->kappa; ++l) all = all && h->lev[l].has_factors;
+    if (all) finalize_factors(h, s);
+}
+
+void export_level(hodlr_t h, int level, int32_t* ranks, int64_t* u_elems, int64_t* v_elems,
+                  double* U, double* V, hipStream_t s) {
+    LevelData& Lv = h->lev[level];
+    if (!Lv.has_factors) fail(HODLR_EINVAL, "level has no factors");
+    HostCsr c = host_csr(h, level, s);
+    const std::vector<int32_t>& st = Lv.hstart;
+    const size_t es = storage_size(h->opts.storage);
+    int64_t ou = 0, ov = 0;
+    std::vector<char> tmp;
+    for (int64_t A = 0; A < Lv.nb; ++A)
+        for (int64_t e = c.ptr[A]; e < c.ptr[A + 1]; ++e) {
+            const int64_t B = c.col[e];
+            const int64_t m = st[A + 1] - st[A], n = st[B + 1] - st[B];
+            const BlockDesc& bd = h->hblocks[c.eref[e] >> 1];
+            const bool tr = (c.eref[e] & 1) != 0;
+            const int64_t r = bd.rank;
+            if (ranks) ranks[e] = (int32_t)r;
+            // a transposed entry's U is the stored V and its V the stored U
+            const uint64_t srcU = tr ? bd.V : bd.U;
+            const uint64_t srcV = tr ? bd.U : bd.V;
+            if (U && r * m) {
+                tmp.resize(es * r * m);
+                HIP_CHECK(hipMemcpy(tmp.data(), reinterpret_cast<void*>(srcU), es * r * m,
+                                    hipMemcpyDeviceToHost));
+                for (int64_t t = 0; t < r * m; ++t)
+                    U[ou + t] = es == 4 ? (double)((float*)tmp.data())[t] : ((double*)tmp.data())[t];
+            }
+            if (V && r * n) {
+                tmp.resize(es * r * n);
+                HIP_CHECK(hipMemcpy(tmp.data(), reinterpret_cast<void*>(srcV), es * r * n,
+                                    hipMemcpyDeviceToHost));
+                for (int64_t t = 0; t < r * n; ++t)
+                    V[ov + t] = es == 4 ? (double)((float*)tmp.data())[t] : ((double*)tmp.data())[t];
+            }
+            ou += r * m;
+            ov += r * n;
+        }
+    if (u_elems) *u_elems = ou;
+    if (v_elems) *v_elems = ov;
+}
+
+}  // namespace hodlr

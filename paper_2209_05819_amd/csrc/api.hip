@@ -1,0 +1,283 @@
+// C ABI of the library (declared in include/hodlr.h): argument checks,
+// handle lifetime, device-memory accounting and error reporting.  No
+// exception crosses this boundary.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+
+#include "hodlr_impl.hpp"
+
+namespace {
+thread_local std::string g_last_error;
+
+hodlr_status set_error(hodlr_status c, const std::string& m) {
+    g_last_error = m;
+    return c;
+}
+
+template <typename F>
+hodlr_status guarded(F&& f) {
+    try {
+        g_last_error.clear();
+        f();
+        return HODLR_OK;
+    } catch (const hodlr::Error& e) {
+        return set_error(e.code, e.msg);
+    } catch (const std::bad_alloc&) {
+        return set_error(HODLR_ENOMEM, "host allocation failed");
+    } catch (...) {
+        return set_error(HODLR_EDEVICE, "unexpected internal error");
+    }
+}
+
+double ms_since(std::chrono::steady_clock::time_point t0) {
+    return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+}
+
+void free_all(hodlr_t h) {
+    for (auto& kv : h->allocs) (void)hipFree(kv.first);
+    h->allocs.clear();
+}
+}  // namespace
+
+namespace hodlr {
+
+void* dalloc(hodlr_t h, size_t bytes) {
+    bytes = std::max<size_t>(bytes, 16);
+    if (h->opts.mem_budget_bytes && h->device_bytes + bytes > h->opts.mem_budget_bytes)
+        fail(HODLR_ENOMEM, "device memory budget exceeded");
+    void* p = nullptr;
+    if (hipMalloc(&p, bytes) != hipSuccess || !p) {
+        (void)hipGetLastError();
+        fail(HODLR_ENOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed");
+    }
+    h->allocs[p] = bytes;
+    h->device_bytes += bytes;
+    return p;
+}
+
+void dfree(hodlr_t h, void* p) {
+    if (!p) return;
+    auto it = h->allocs.find(p);
+    if (it == h->allocs.end()) return;
+    h->device_bytes -= it->second;
+    h->allocs.erase(it);
+    (void)hipFree(p);
+}
+
+}  // namespace hodlr
+
+extern "C" {
+
+void hodlr_default_opts(hodlr_opts* o) {
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+    o->level_rule = 0;
+    o->has_domain = 0;
+    o->domain_side = 1.0;
+    o->storage = HODLR_FP64;
+    o->symmetric = 1;
+    o->max_rank = 0;
+    o->skip_aca = 0;
+    o->mem_budget_bytes = 0;
+}
+
+hodlr_status hodlr_build(const double* points, int64_t N, int d, const hodlr_kernel* kernel,
+                         int leaf_size, double tol, const hodlr_opts* opts, void* stream,
+                         hodlr_t* out) {
+    if (!points || !kernel || !out) return set_error(HODLR_EINVAL, "null pointer argument");
+    if (N < 1 || N > INT32_MAX) return set_error(HODLR_EINVAL, "N must be in [1, 2^31)");
+    if (d < 1 || d > 8) return set_error(HODLR_EINVAL, "d must be in [1, 8]");
+    if (leaf_size < 1) return set_error(HODLR_EINVAL, "leaf_size must be >= 1");
+    if (!(tol >= 0.0 && tol < 1.0)) return set_error(HODLR_EINVAL, "tol must be in [0, 1)");
+    if (kernel->kind < HODLR_K_LOG || kernel->kind > HODLR_K_INV_SQRT1P)
+        return set_error(HODLR_EINVAL, "unknown kernel kind");
+    if ((kernel->kind == HODLR_K_GAUSS || kernel->kind == HODLR_K_EXP) && !(kernel->h > 0.0))
+        return set_error(HODLR_EINVAL, "kernel length scale h must be > 0");
+    hodlr_opts o;
+    hodlr_default_opts(&o);
+    if (opts) o = *opts;
+    if (o.level_rule != 0 && o.level_rule != 1) return set_error(HODLR_EINVAL, "bad level_rule");
+    if (o.storage != HODLR_FP64 && o.storage != HODLR_FP32)
+        return set_error(o.storage == HODLR_BF16 ? HODLR_EUNSUPPORTED : HODLR_EINVAL,
+                         "storage must be FP64 or FP32");
+    if (o.has_domain && !(o.domain_side > 0.0 && std::isfinite(o.domain_side)))
+        return set_error(HODLR_EINVAL, "domain_side must be > 0");
+    if (o.max_rank < 0) return set_error(HODLR_EINVAL, "max_rank must be >= 0");
+
+    hodlr_t h = new (std::nothrow) hodlr_handle_s();
+    if (!h) return set_error(HODLR_ENOMEM, "host allocation failed");
+    h->N = N;
+    h->d = d;
+    h->kern = *kernel;
+    h->leaf = leaf_size;
+    h->tol = tol;
+    h->opts = o;
+    h->kp.kind = kernel->kind;
+    h->kp.h = kernel->h;
+    h->kp.inv_h = kernel->h > 0 ? 1.0 / kernel->h : 0.0;
+    h->kp.inv_h2 = kernel->h > 0 ? 1.0 / (kernel->h * kernel->h) : 0.0;
+    h->kp.scale = kernel->scale;
+    h->kp.diag = kernel->diag;
+    hipStream_t s = (hipStream_t)stream;
+    hodlr_status st = guarded([&] {
+        HIP_CHECK(hipGetDevice(&h->device));
+        auto t0 = std::chrono::steady_clock::now();
+        hodlr::build_tree(h, points, s);
+        h->build_ms[0] = ms_since(t0);
+        t0 = std::chrono::steady_clock::now();
+        hodlr::build_lists(h, s);
+        hodlr::build_block_table(h, s);
+        h->build_ms[1] = ms_since(t0);
+        t0 = std::chrono::steady_clock::now();
+        if (!o.skip_aca) {
+            hodlr::compress_all(h, s);
+        } else if (h->kappa == 0) {
+            hodlr::finalize_factors(h, s);
+        }
+        h->build_ms[2] = ms_since(t0);
+    });
+    if (st != HODLR_OK) {
+        (void)hipStreamSynchronize(s);
+        free_all(h);
+        delete h;
+        return st;
+    }
+    *out = h;
+    return HODLR_OK;
+}
+
+hodlr_status hodlr_matvec(hodlr_t h, const void* X, int64_t ldx, int nrhs, int x_prec, void* Y,
+                          int64_t ldy, int compute_prec, void* stream) {
+    if (!h || !X || !Y) return set_error(HODLR_EINVAL, "null pointer argument");
+    if (nrhs < 1) return set_error(HODLR_EINVAL, "nrhs must be >= 1");
+    if (ldx < h->N || ldy < h->N) return set_error(HODLR_EINVAL, "leading dimension < N");
+    if (x_prec != HODLR_FP64 && x_prec != HODLR_FP32)
+        return set_error(HODLR_EINVAL, "x_prec must be FP64 or FP32");
+    if (compute_prec != HODLR_FP64 && compute_prec != HODLR_FP32)
+        return set_error(HODLR_EINVAL, "compute_prec must be FP64 or FP32");
+    for (int l = 1; l <= h->kappa; ++l)
+        if (!h->lev[l].has_factors) return set_error(HODLR_EINVAL, "factors missing");
+    if (!h->near_items) return set_error(HODLR_EINVAL, "factors missing");
+    return guarded([&] {
+        hodlr::matvec(h, X, ldx, nrhs, x_prec, Y, ldy, compute_prec, (hipStream_t)stream);
+    });
+}
+
+hodlr_status hodlr_get_info(hodlr_t h, hodlr_info* info) {
+    if (!h || !info) return set_error(HODLR_EINVAL, "null pointer argument");
+    std::memset(info, 0, sizeof(*info));
+    info->N = h->N;
+    info->d = h->d;
+    info->kappa = h->kappa;
+    info->lmax = h->lmax;
+    info->symmetric = h->opts.symmetric;
+    info->storage = h->opts.storage;
+    for (int a = 0; a < h->d; ++a) info->domain_lo[a] = h->lo[a];
+    info->domain_side = h->side;
+    for (int l = 0; l <= h->kappa; ++l) {
+        info->nboxes[l] = h->lev[l].nb;
+        info->il_entries[l] = h->lev[l].nnz;
+        info->stored_blocks[l] = h->lev[l].nblk;
+        int32_t rmin = INT32_MAX, rmax = 0;
+        double rs = 0;
+        int64_t fe = 0;
+        for (int64_t b = h->lev[l].blk0; b < h->lev[l].blk0 + h->lev[l].nblk; ++b) {
+            const auto& bd = h->hblocks[b];
+            rmin = std::min(rmin, bd.rank);
+            rmax = std::max(rmax, bd.rank);
+            rs += bd.rank;
+            fe += (int64_t)std::max(bd.rank, 0) * (bd.m + bd.n);
+        }
+        info->rank_min[l] = h->lev[l].nblk ? rmin : 0;
+        info->rank_max[l] = rmax;
+        info->rank_mean[l] = h->lev[l].nblk ? rs / h->lev[l].nblk : 0.0;
+        info->factor_elems[l] = fe;
+    }
+    info->near_entries = h->near_nnz;
+    info->near_pairs = h->near_pairs;
+    info->device_bytes = h->device_bytes;
+    for (int i = 0; i < 4; ++i) info->build_ms[i] = h->build_ms[i];
+    return HODLR_OK;
+}
+
+hodlr_status hodlr_export_tree(hodlr_t h, int64_t* perm, uint64_t* keys) {
+    if (!h) return set_error(HODLR_EINVAL, "null handle");
+    return guarded([&] {
+        if (perm) {
+            std::vector<int32_t> p(h->N);
+            HIP_CHECK(hipMemcpy(p.data(), h->perm, sizeof(int32_t) * h->N, hipMemcpyDeviceToHost));
+            for (int64_t i = 0; i < h->N; ++i) perm[i] = p[i];
+        }
+        if (keys)
+            HIP_CHECK(hipMemcpy(keys, h->keys, sizeof(uint64_t) * h->N, hipMemcpyDeviceToHost));
+    });
+}
+
+hodlr_status hodlr_export_boxes(hodlr_t h, int level, int64_t* start, uint64_t* key,
+                                int32_t* coord) {
+    if (!h) return set_error(HODLR_EINVAL, "null handle");
+    if (level < 0 || level > h->kappa) return set_error(HODLR_EINVAL, "level out of range");
+    return guarded([&] {
+        const auto& Lv = h->lev[level];
+        if (start)
+            for (int64_t b = 0; b <= Lv.nb; ++b) start[b] = Lv.hstart[b];
+        if (key) HIP_CHECK(hipMemcpy(key, Lv.key, sizeof(uint64_t) * Lv.nb, hipMemcpyDeviceToHost));
+        if (coord)
+            HIP_CHECK(hipMemcpy(coord, Lv.coord, sizeof(int32_t) * Lv.nb * h->d,
+                                hipMemcpyDeviceToHost));
+    });
+}
+
+hodlr_status hodlr_export_il(hodlr_t h, int level, int64_t* nnz, int64_t* ptr, int32_t* col) {
+    if (!h) return set_error(HODLR_EINVAL, "null handle");
+    if (level < 1 || level > h->kappa) return set_error(HODLR_EINVAL, "level out of range");
+    return guarded([&] {
+        const auto& Lv = h->lev[level];
+        if (nnz) *nnz = Lv.nnz;
+        if (ptr)
+            HIP_CHECK(hipMemcpy(ptr, Lv.il_ptr, sizeof(int64_t) * (Lv.nb + 1), hipMemcpyDeviceToHost));
+        if (col && Lv.nnz)
+            HIP_CHECK(hipMemcpy(col, Lv.il_col, sizeof(int32_t) * Lv.nnz, hipMemcpyDeviceToHost));
+    });
+}
+
+hodlr_status hodlr_export_near(hodlr_t h, int64_t* nnz, int64_t* ptr, int32_t* col) {
+    if (!h) return set_error(HODLR_EINVAL, "null handle");
+    return guarded([&] {
+        const auto& Lv = h->lev[h->kappa];
+        if (nnz) *nnz = h->near_nnz;
+        if (ptr)
+            HIP_CHECK(hipMemcpy(ptr, h->near_ptr, sizeof(int64_t) * (Lv.nb + 1),
+                                hipMemcpyDeviceToHost));
+        if (col && h->near_nnz)
+            HIP_CHECK(hipMemcpy(col, h->near_col, sizeof(int32_t) * h->near_nnz,
+                                hipMemcpyDeviceToHost));
+    });
+}
+
+hodlr_status hodlr_export_factors(hodlr_t h, int level, int32_t* ranks, int64_t* u_elems,
+                                  int64_t* v_elems, double* U, double* V) {
+    if (!h) return set_error(HODLR_EINVAL, "null handle");
+    if (level < 1 || level > h->kappa) return set_error(HODLR_EINVAL, "level out of range");
+    return guarded([&] { hodlr::export_level(h, level, ranks, u_elems, v_elems, U, V, nullptr); });
+}
+
+hodlr_status hodlr_import_factors(hodlr_t h, int level, const int32_t* ranks, const double* U,
+                                  const double* V) {
+    if (!h || !ranks) return set_error(HODLR_EINVAL, "null pointer argument");
+    if (level < 1 || level > h->kappa) return set_error(HODLR_EINVAL, "level out of range");
+    return guarded([&] { hodlr::import_level(h, level, ranks, U, V, nullptr); });
+}
+
+void hodlr_destroy(hodlr_t h) {
+    if (!h) return;
+    (void)hipDeviceSynchronize();
+    free_all(h);
+    delete h;
+}
+
+const char* hodlr_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,181 @@
+// Internal declarations of the MI355X HODLRdD library (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/hodlr.h"
+
+namespace hodlr {
+
+struct Error {
+    hodlr_status code;
+    std::string msg;
+};
+
+[[noreturn]] inline void fail(hodlr_status c, const std::string& m) { throw Error{c, m}; }
+
+#define HIP_CHECK(expr)                                                                      \
+    do {                                                                                     \
+        hipError_t e_ = (expr);                                                              \
+        if (e_ != hipSuccess)                                                                \
+            ::hodlr::fail(HODLR_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+constexpr int kMaxD = 8;
+constexpr int kMaxLevels = 32;
+constexpr int kAcaMaxRank = 1024;   // per-block ACA rank limit of the device compressor
+
+// Kernel function parameters as the device sees them.
+struct KParams {
+    int kind;
+    double h;
+    double inv_h;
+    double inv_h2;
+    double scale;
+    double diag;
+};
+
+// r2 = |x - y|^2; returns scale * f(r).  FP64 and FP32 variants.
+__device__ __forceinline__ double kfun(const KParams& k, double r2) {
+    double f;
+    switch (k.kind) {
+    case HODLR_K_LOG: f = 0.5 * log(r2); break;
+    case HODLR_K_INV_R: f = 1.0 / sqrt(r2); break;
+    case HODLR_K_INV_R2: f = 1.0 / r2; break;
+    case HODLR_K_GAUSS: f = exp(-r2 * k.inv_h2); break;
+    case HODLR_K_EXP: f = exp(-sqrt(r2) * k.inv_h); break;
+    case HODLR_K_R: f = sqrt(r2); break;
+    case HODLR_K_SIN: f = sin(sqrt(r2)); break;
+    default: f = 1.0 / sqrt(1.0 + sqrt(r2)); break;
+    }
+    return k.scale * f;
+}
+
+__device__ __forceinline__ float kfun(const KParams& k, float r2) {
+    float f;
+    switch (k.kind) {
+    case HODLR_K_LOG: f = 0.5f * __logf(r2); break;
+    case HODLR_K_INV_R: f = rsqrtf(r2); break;
+    case HODLR_K_INV_R2: f = 1.0f / r2; break;
+    case HODLR_K_GAUSS: f = __expf(-r2 * (float)k.inv_h2); break;
+    case HODLR_K_EXP: f = __expf(-sqrtf(r2) * (float)k.inv_h); break;
+    case HODLR_K_R: f = sqrtf(r2); break;
+    case HODLR_K_SIN: f = sinf(sqrtf(r2)); break;
+    default: f = rsqrtf(1.0f + sqrtf(r2)); break;
+    }
+    return (float)k.scale * f;
+}
+
+// One stored low-rank block: rows = box A (|A| = m, tree offset a0),
+// columns = box B (|B| = n, tree offset b0).  U is m x r column by column,
+// V is r x n row by row, both in the storage type at byte addresses U, V.
+struct BlockDesc {
+    int32_t a0, m, b0, n;
+    int32_t rank, level;
+    int64_t toff;       // offset of this block's projections in the t/s buffers
+    uint64_t U, V;      // device addresses
+};
+
+struct LevelData {
+    int64_t nb = 0;
+    int32_t* start = nullptr;    // device, nb+1
+    uint64_t* key = nullptr;     // device, nb
+    int32_t* coord = nullptr;    // device, nb*d
+    int64_t* il_ptr = nullptr;   // device, nb+1
+    int32_t* il_col = nullptr;   // device, nnz
+    int64_t nnz = 0;
+    int64_t* eref = nullptr;     // device, per IL entry: (stored block << 1) | transposed
+    int64_t blk0 = 0, nblk = 0;  // range in the global block table
+    std::vector<int32_t> hstart; // host copy of start
+    bool has_factors = false;
+};
+
+struct WorkItem {   // launch planning record: a block (or box) and a sub-range
+    int32_t id;
+    int32_t lo;
+    int32_t cnt;
+    int32_t level;
+};
+
+}  // namespace hodlr
+
+struct hodlr_handle_s {
+    int64_t N = 0;
+    int d = 0;
+    hodlr_kernel kern{};
+    hodlr::KParams kp{};
+    int leaf = 0;
+    double tol = 0;
+    hodlr_opts opts{};
+    int device = 0;
+    int kappa = 0, lmax = 0;
+    double lo[8]{}, side = 1.0;
+    double* pts = nullptr;       // device, SoA tree order: pts[a*N + p]
+    int32_t* perm = nullptr;     // device, tree position -> user index
+    uint64_t* keys = nullptr;    // device, sorted Morton keys
+    hodlr::LevelData lev[hodlr::kMaxLevels];
+    int64_t* near_ptr = nullptr;
+    int32_t* near_col = nullptr;
+    int64_t near_nnz = 0;
+    int64_t near_pairs = 0;
+    // stored blocks (all levels)
+    hodlr::BlockDesc* blocks = nullptr;   // device
+    std::vector<hodlr::BlockDesc> hblocks;
+    int64_t nblocks = 0;
+    int64_t t_total = 0;                  // sum of ranks
+    std::vector<void*> arenas;            // factor storage allocations
+    // launch plans
+    hodlr::WorkItem* proj_items = nullptr;
+    int64_t n_proj_items = 0;
+    hodlr::WorkItem* exp_items = nullptr;  // grouped by level
+    std::vector<int64_t> exp_lvl_off;      // [kappa+2)
+    hodlr::WorkItem* near_items = nullptr;
+    int64_t n_near_items = 0;
+    // matvec workspace
+    void* ws = nullptr;
+    size_t ws_bytes = 0;
+    size_t device_bytes = 0;
+    double build_ms[4]{};
+    std::unordered_map<void*, size_t> allocs;
+};
+
+namespace hodlr {
+
+// device memory held by a handle (tracked for the budget)
+void* dalloc(hodlr_t h, size_t bytes);
+void dfree(hodlr_t h, void* p);
+
+// tree.hip
+void build_tree(hodlr_t h, const double* points_host, hipStream_t s);
+// lists.hip
+void build_lists(hodlr_t h, hipStream_t s);
+void build_block_table(hodlr_t h, hipStream_t s);
+// aca.hip
+void compress_all(hodlr_t h, hipStream_t s);
+// apply.hip
+void plan_apply(hodlr_t h);
+void matvec(hodlr_t h, const void* X, int64_t ldx, int nrhs, int x_prec, void* Y, int64_t ldy,
+            int compute_prec, hipStream_t s);
+// factors.cpp-like helpers in aca.hip
+void import_level(hodlr_t h, int level, const int32_t* ranks, const double* U, const double* V,
+                  hipStream_t s);
+void export_level(hodlr_t h, int level, int32_t* ranks, int64_t* u_elems, int64_t* v_elems,
+                  double* U, double* V, hipStream_t s);
+void finalize_factors(hodlr_t h, hipStream_t s);
+
+// prim.hip: device-wide primitives
+void sort_pairs_u64(const uint64_t* kin, uint64_t* kout, const int32_t* vin, int32_t* vout,
+                    int64_t n, int end_bit, hipStream_t s);
+void exclusive_scan_i32(const int32_t* in, int32_t* out, int64_t n, hipStream_t s);
+void exclusive_scan_i64(const int64_t* in, int64_t* out, int64_t n, hipStream_t s);
+void segmented_sort_i32(const int32_t* in, int32_t* out, int64_t nnz, int64_t nseg,
+                        const int64_t* offsets, hipStream_t s);
+
+inline unsigned nblk(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
+
+}  // namespace hodlr

@@ -1,0 +1,69 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads and exports
+every entry point its header declares, and the ctypes structures match."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "hodlr.h")
+
+
+def _declared():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(hodlr_[a-z_]+)\s*\(", txt)))
+
+
+def test_header_declares_the_boundary():
+    names = _declared()
+    for n in ("hodlr_build", "hodlr_matvec", "hodlr_destroy", "hodlr_last_error",
+              "hodlr_export_tree", "hodlr_export_il", "hodlr_import_factors"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    import paper_2209_05819_amd as P
+    if not os.path.exists(P.LIB_PATH):
+        pytest.skip("library not built")
+    L = C.CDLL(P.LIB_PATH)
+    missing = [n for n in _declared() if not hasattr(L, n)]
+    assert not missing
+
+
+def test_struct_layouts_match_header():
+    import paper_2209_05819_amd as P
+    # sizes implied by the C declarations on x86-64
+    assert C.sizeof(P.Kernel) == 32
+    assert C.sizeof(P.Opts) == 4 * 2 + 8 * 8 + 8 + 4 * 4 + 8
+    assert P.Info.build_ms.offset + 32 == C.sizeof(P.Info)
+
+
+def test_default_opts_and_errors_without_gpu():
+    import paper_2209_05819_amd as P
+    if not os.path.exists(P.LIB_PATH):
+        pytest.skip("library not built")
+    o = P.default_opts()
+    assert o.symmetric == 1 and o.storage == P.FP64 and o.level_rule == 0
+    L = P.lib()
+    # argument errors are reported before any device work
+    st = L.hodlr_build(None, 10, 3, None, 8, 1e-6, None, None, None)
+    assert st == 1 and b"null" in L.hodlr_last_error()
+    import numpy as np
+    pts = np.zeros((4, 9))
+    k = P.make_kernel("inv_r")
+    out = C.c_void_p()
+    st = L.hodlr_build(pts.ctypes.data_as(C.c_void_p), 4, 9, C.byref(k), 8, 1e-6, None, None,
+                       C.byref(out))
+    assert st == 1 and b"d must be" in L.hodlr_last_error()
+    st = L.hodlr_matvec(None, None, 0, 1, 0, None, 0, 0, None)
+    assert st == 1
+
+
+def test_product_path_fails_loudly_without_library(tmp_path, monkeypatch):
+    import paper_2209_05819_amd as P
+    monkeypatch.setattr(P, "LIB_PATH", str(tmp_path / "missing.so"))
+    monkeypatch.setattr(P, "_lib", None)
+    with pytest.raises(RuntimeError, match="not built"):
+        P.lib()

@@ -1,0 +1,249 @@
+#!/usr/bin/env python3
+"""HODLRdD matvec throughput on one MI355X.
+
+Workload: 2^18 points i.i.d. uniform in [-1,1]^3, kernel 1/r (diagonal 0),
+leaf size 64, ACA tolerance 1e-10, one N(0,1) right-hand side.  The library
+builds the representation once (tree, lists, ACA: setup, reported apart) and
+a step is one full matvec: permutation, projections, expansions of every
+level, near field evaluated on the fly, permutation back.
+
+Two precisions are timed on the same inputs: FP64 (factors and arithmetic)
+and mixed (FP32 factors, FP32 arithmetic).  `value` is the FP64 throughput;
+the mixed figures are in `mixed`.  Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def _events(torch, n):
+    return [torch.cuda.Event(enable_timing=True) for _ in range(n)]
+
+
+def time_matvecs(P, torch, H, X, Y, prec, warmup, steps):
+    """Warm-up, then `steps` matvecs each bracketed by the 5 stage events."""
+    for _ in range(warmup):
+        P.hodlr_matvec(H.h, X, Y, prec)
+    torch.cuda.synchronize()
+    evs = [_events(torch, 5) for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for e in evs:
+        P.hodlr_matvec_events(H.h, X, Y, e, prec)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    per = np.array([[e[i].elapsed_time(e[i + 1]) for i in range(4)] for e in evs])  # ms
+    lat = np.array([e[0].elapsed_time(e[4]) for e in evs])
+    return wall, per, lat
+
+
+def factor_bytes(info, elem):
+    return sum(info.factor_elems[l] for l in range(1, info.kappa + 1)) * elem
+
+
+def rel_err_rows(y, ref, rows):
+    return float(np.linalg.norm(y[rows] - ref) / np.linalg.norm(ref))
+
+
+def cpu_baseline(w, pts, q, sample_rows_budget_s=30.0):
+    """The oracle timed on the host: its matvec over the target rows of one
+    level-1 box (all levels' blocks of those rows), after compressing exactly
+    the blocks those rows need."""
+    import oracle
+    oracle.build(force=False)
+    k = oracle.kernel(w.kernel, diag=w.diag)
+    t0 = time.perf_counter()
+    o = oracle.OracleHODLR(pts, w.leaf, 0, domain=w.domain)
+    start, _, _ = o.boxes(1)
+    r0, r1 = int(start[0]), int(start[1])
+    o.compress(k, w.tol, rows=(r0, r1))
+    t_setup = time.perf_counter() - t0
+    times = []
+    b = None
+    for _ in range(3):
+        t1 = time.perf_counter()
+        b = o.matvec(k, q, rows=(r0, r1))
+        times.append(time.perf_counter() - t1)
+        if sum(times) > sample_rows_budget_s:
+            break
+    tm = float(np.median(times))
+    rows = o.perm()[r0:r1]
+    return {
+        "value": (r1 - r0) * 1 / tm,
+        "unit": "N*nrhs/s",
+        "cores": oracle.num_threads(),
+        "kind": "oracle",
+        "sample": f"oracle matvec (FP64, every ordered block) over the {r1 - r0} target rows of "
+                  f"level-1 box 0 (all levels' blocks of those rows), median of {len(times)}; "
+                  f"setup (tree, lists, ACA of those blocks) {t_setup:.1f} s not timed",
+        "seconds_per_matvec": tm,
+    }, rows, b[rows]
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="uniform3d_invr_n262144")
+    ap.add_argument("--n", type=int, default=0, help="override N (smaller runs)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--level-rule", type=int, default=0)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain device copy of known size (counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(the sharding design is described in DESIGN.md); run with --gpus 1.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_2209_05819_amd as P
+    from paper_2209_05819_amd import workloads as W
+
+    w = W.WORKLOADS[args.workload]
+    if args.n:
+        w = W.scaled(w, args.n)
+    pts = w.points()
+    q = w.rhs()[:, 0].copy()
+    N = w.N
+    kern = P.make_kernel(w.kernel, h=w.h, diag=w.diag)
+    print(f"[bench] workload {w.name} N={N} d={w.d}", file=sys.stderr, flush=True)
+
+    t0 = time.perf_counter()
+    H64 = P.HODLR(pts, kern, w.leaf, w.tol, domain=w.domain, level_rule=args.level_rule)
+    torch.cuda.synchronize()
+    build64 = time.perf_counter() - t0
+    info = H64.info()
+    print(f"[bench] FP64 build {build64:.2f} s kappa={info.kappa}", file=sys.stderr, flush=True)
+
+    X = torch.tensor(q, dtype=torch.float64, device="cuda")
+    Y = torch.empty_like(X)
+    wall, per, lat = time_matvecs(P, torch, H64, X, Y, P.FP64, args.warmup, args.steps)
+    y64 = Y.cpu().numpy()
+    ms_step = wall / args.steps * 1e3
+    stage_ms = per.mean(axis=0)
+    print(f"[bench] FP64 {ms_step:.3f} ms/step stages {np.round(stage_ms, 3).tolist()}",
+          file=sys.stderr, flush=True)
+
+    fb64 = factor_bytes(info, 8)
+    dominant = 1
+    names = {1: "k_lr_fused+k_project"}
+    # one pass over every stored factor element, plus the vectors it touches
+    vec_bytes = 8 * (2 * N)
+    achieved = (fb64 + vec_bytes) / (stage_ms[dominant] * 1e-3) / 1e9
+    matvec_gbs = (fb64 + vec_bytes) / (lat.mean() * 1e-3) / 1e9
+
+    mixed = None
+    if not args.no_mixed:
+        t0 = time.perf_counter()
+        H32 = P.HODLR(pts, kern, w.leaf, w.tol, domain=w.domain, level_rule=args.level_rule,
+                      storage=P.FP32)
+        torch.cuda.synchronize()
+        build32 = time.perf_counter() - t0
+        info32 = H32.info()
+        Y32 = torch.empty_like(X)
+        wall32, per32, lat32 = time_matvecs(P, torch, H32, X, Y32, P.FP32, args.warmup, args.steps)
+        y32 = Y32.cpu().numpy()
+        fb32 = factor_bytes(info32, 4)
+        st32 = per32.mean(axis=0)
+        dom32 = 1
+        mixed = {
+            "value": N / (wall32 / args.steps),
+            "ms_per_step": wall32 / args.steps * 1e3,
+            "p50_ms": float(np.percentile(lat32, 50)),
+            "p99_ms": float(np.percentile(lat32, 99)),
+            "dtype": "f32 factors, f32 arithmetic",
+            "stage_ms": [round(float(v), 4) for v in st32],
+            "factor_bytes": int(fb32),
+            "build_s": round(build32, 2),
+            "speedup_vs_fp64": (N / (wall32 / args.steps)) / (N / (wall / args.steps)),
+            "roofline": {"bound": "hbm", "kernel": names[dom32],
+                         "achieved": (fb32 + 4 * 2 * N) / (st32[dom32] * 1e-3) / 1e9,
+                         "peak": HBM_PEAK_GBS, "unit": "GB/s"},
+        }
+        mixed["roofline"]["frac"] = mixed["roofline"]["achieved"] / HBM_PEAK_GBS
+        del H32
+
+    # accuracy on sampled rows against the plain definition (direct sum)
+    import oracle
+    oracle.build(force=False)
+    g = W.rng(203)
+    rows = np.sort(g.choice(N, size=min(N, 1024), replace=False))
+    bd = oracle.direct(pts, oracle.kernel(w.kernel, diag=w.diag), q, rows=rows)
+    err64 = rel_err_rows(y64, bd, rows)
+    if mixed is not None:
+        mixed["rel_err"] = rel_err_rows(y32, bd, rows)
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu, crow, cb = cpu_baseline(w, pts, q)
+        cpu_err = float(np.linalg.norm(y64[crow] - cb) / np.linalg.norm(cb))
+        cpu["gpu_vs_oracle_rel_err"] = cpu_err
+
+    if args.copy_calibration:
+        # plain device copy of 1 GiB, for scaling the HBM traffic counters
+        a = torch.empty(1 << 27, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+
+    out = {
+        "metric": "HODLRdD matvec N*nrhs/s at stated rel err, FP64 vs mixed; p50/p99 latency",
+        "value": N / (wall / args.steps),
+        "unit": "N*nrhs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": w.name, "N": N, "d": w.d, "kernel": "1/r, diag 0" if w.kernel ==
+                   "inv_r" else w.kernel, "leaf": w.leaf, "aca_tol": w.tol, "nrhs": 1,
+                   "level_rule": "max-count" if args.level_rule == 0 else "closed-form",
+                   "storage": "one factor pair per unordered block pair"},
+        "p50_ms": float(np.percentile(lat, 50)),
+        "p99_ms": float(np.percentile(lat, 99)),
+        "rel_err": err64,
+        "rel_err_ref": "direct sum on 1024 sampled rows (seed 203)",
+        "stage_ms": [round(float(v), 4) for v in stage_ms],
+        "stages": ["permute_in", "fused_blocks+split_projection", "split_expansion",
+                   "gather+near_field+permute_out"],
+        "build_s": round(build64, 2),
+        "build_ms_tree_lists_aca": [round(info.build_ms[i], 1) for i in range(3)],
+        "kappa": info.kappa,
+        "stored_blocks": int(sum(info.stored_blocks[l] for l in range(1, info.kappa + 1))),
+        "rank_max": int(max([info.rank_max[l] for l in range(1, info.kappa + 1)] or [0])),
+        "factor_bytes": int(fb64),
+        "near_pairs": int(info.near_pairs),
+        "roofline": {"bound": "hbm", "kernel": names[dominant], "achieved": achieved,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": None},
+        "matvec_roofline": {"achieved": matvec_gbs, "frac": matvec_gbs / HBM_PEAK_GBS,
+                            "bytes": int(fb64 + vec_bytes)},
+        "mixed": mixed,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -119,6 +119,16 @@ hodlr_status hodlr_build(const double* points, int64_t N, int d, const hodlr_ker
 hodlr_status hodlr_matvec(hodlr_t h, const void* X, int64_t ldx, int nrhs, int x_prec,
                           void* Y, int64_t ldy, int compute_prec, void* stream);
 
+/* hodlr_matvec that also records five caller-created hipEvent_t (passed as
+ * void*, nevents == 5) on the stream: before the product, and after each of
+ * its four stages (permutation into tree order; projections t = V x of every
+ * stored block; expansion U t into every box of every level; near field
+ * evaluated on the fly plus permutation back).  For timing; same results and
+ * errors as hodlr_matvec (EINVAL if events is NULL or nevents != 5). */
+hodlr_status hodlr_matvec_events(hodlr_t h, const void* X, int64_t ldx, int nrhs, int x_prec,
+                                 void* Y, int64_t ldy, int compute_prec, void* stream,
+                                 void* const* events, int nevents);
+
 typedef struct {
     int64_t N;
     int d;

@@ -69,6 +69,8 @@ def lib():
         L.hodlr_build.argtypes = [_P, _i64, C.c_int, C.POINTER(Kernel), C.c_int, C.c_double,
                                   C.POINTER(Opts), _P, C.POINTER(_P)]
         L.hodlr_matvec.argtypes = [_P, _P, _i64, C.c_int, C.c_int, _P, _i64, C.c_int, _P]
+        L.hodlr_matvec_events.argtypes = [_P, _P, _i64, C.c_int, C.c_int, _P, _i64, C.c_int, _P,
+                                          C.POINTER(_P), C.c_int]
         L.hodlr_get_info.argtypes = [_P, C.POINTER(Info)]
         L.hodlr_export_tree.argtypes = [_P, _P, _P]
         L.hodlr_export_boxes.argtypes = [_P, C.c_int, _P, _P, _P]
@@ -79,7 +81,8 @@ def lib():
         L.hodlr_import_factors.argtypes = [_P, C.c_int, _P, _P, _P]
         L.hodlr_destroy.argtypes = [_P]
         L.hodlr_last_error.restype = C.c_char_p
-        for f in ("hodlr_build", "hodlr_matvec", "hodlr_get_info", "hodlr_export_tree",
+        for f in ("hodlr_build", "hodlr_matvec", "hodlr_matvec_events", "hodlr_get_info",
+                  "hodlr_export_tree",
                   "hodlr_export_boxes", "hodlr_export_il", "hodlr_export_near",
                   "hodlr_export_factors", "hodlr_import_factors"):
             getattr(L, f).restype = C.c_int
@@ -143,6 +146,37 @@ def hodlr_matvec(h: int, X, Y, compute_prec: int = FP64, stream=None) -> None:
         ldx, ldy = X.stride(1) if nrhs > 1 else N, Y.stride(1) if nrhs > 1 else N
     _check(lib().hodlr_matvec(C.c_void_p(h), C.c_void_p(X.data_ptr()), ldx, nrhs, xp,
                               C.c_void_p(Y.data_ptr()), ldy, compute_prec, _stream_ptr(stream)))
+
+
+def _mv_args(X, Y):
+    import torch
+    if X.dtype != Y.dtype or X.dtype not in (torch.float64, torch.float32):
+        raise TypeError("X and Y must both be float64 or float32")
+    if not (X.is_cuda and Y.is_cuda):
+        raise TypeError("X and Y must be device tensors")
+    xp = FP64 if X.dtype == torch.float64 else FP32
+    if X.dim() == 1:
+        return xp, 1, X.shape[0], Y.shape[0]
+    N, nrhs = X.shape
+    if X.stride(0) != 1 or Y.stride(0) != 1:
+        raise ValueError("X and Y must be column-major (stride 1 along N)")
+    return xp, nrhs, (X.stride(1) if nrhs > 1 else N), (Y.stride(1) if nrhs > 1 else N)
+
+
+def hodlr_matvec_events(h: int, X, Y, events, compute_prec: int = FP64, stream=None) -> None:
+    """hodlr_matvec recording 5 torch.cuda.Event (enable_timing=True) at the
+    stage boundaries on the stream."""
+    xp, nrhs, ldx, ldy = _mv_args(X, Y)
+    if stream is None:
+        import torch
+        stream = torch.cuda.current_stream().cuda_stream
+    for e in events:
+        if e.cuda_event == 0:   # torch creates the event lazily
+            e.record()
+    arr = (C.c_void_p * 5)(*[C.c_void_p(e.cuda_event) for e in events])
+    _check(lib().hodlr_matvec_events(C.c_void_p(h), C.c_void_p(X.data_ptr()), ldx, nrhs, xp,
+                                     C.c_void_p(Y.data_ptr()), ldy, compute_prec,
+                                     C.c_void_p(int(stream)), arr, len(events)))
 
 
 def hodlr_get_info(h: int) -> Info:

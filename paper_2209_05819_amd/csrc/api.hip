@@ -148,8 +148,10 @@ hodlr_status hodlr_build(const double* points, int64_t N, int d, const hodlr_ker
     return HODLR_OK;
 }
 
-hodlr_status hodlr_matvec(hodlr_t h, const void* X, int64_t ldx, int nrhs, int x_prec, void* Y,
-                          int64_t ldy, int compute_prec, void* stream) {
+namespace {
+hodlr_status matvec_checked(hodlr_t h, const void* X, int64_t ldx, int nrhs, int x_prec, void* Y,
+                            int64_t ldy, int compute_prec, void* stream, void* const* events,
+                            int nevents) {
     if (!h || !X || !Y) return set_error(HODLR_EINVAL, "null pointer argument");
     if (nrhs < 1) return set_error(HODLR_EINVAL, "nrhs must be >= 1");
     if (ldx < h->N || ldy < h->N) return set_error(HODLR_EINVAL, "leading dimension < N");
@@ -157,12 +159,27 @@ hodlr_status hodlr_matvec(hodlr_t h, const void* X, int64_t ldx, int nrhs, int x
         return set_error(HODLR_EINVAL, "x_prec must be FP64 or FP32");
     if (compute_prec != HODLR_FP64 && compute_prec != HODLR_FP32)
         return set_error(HODLR_EINVAL, "compute_prec must be FP64 or FP32");
+    if (events && nevents != 5) return set_error(HODLR_EINVAL, "events must hold 5 entries");
     for (int l = 1; l <= h->kappa; ++l)
         if (!h->lev[l].has_factors) return set_error(HODLR_EINVAL, "factors missing");
     if (!h->near_items) return set_error(HODLR_EINVAL, "factors missing");
     return guarded([&] {
-        hodlr::matvec(h, X, ldx, nrhs, x_prec, Y, ldy, compute_prec, (hipStream_t)stream);
+        hodlr::matvec(h, X, ldx, nrhs, x_prec, Y, ldy, compute_prec,
+                      reinterpret_cast<hipEvent_t const*>(events), (hipStream_t)stream);
     });
+}
+}  // namespace
+
+hodlr_status hodlr_matvec(hodlr_t h, const void* X, int64_t ldx, int nrhs, int x_prec, void* Y,
+                          int64_t ldy, int compute_prec, void* stream) {
+    return matvec_checked(h, X, ldx, nrhs, x_prec, Y, ldy, compute_prec, stream, nullptr, 0);
+}
+
+hodlr_status hodlr_matvec_events(hodlr_t h, const void* X, int64_t ldx, int nrhs, int x_prec,
+                                 void* Y, int64_t ldy, int compute_prec, void* stream,
+                                 void* const* events, int nevents) {
+    if (!events) return set_error(HODLR_EINVAL, "null events");
+    return matvec_checked(h, X, ldx, nrhs, x_prec, Y, ldy, compute_prec, stream, events, nevents);
 }
 
 hodlr_status hodlr_get_info(hodlr_t h, hodlr_info* info) {

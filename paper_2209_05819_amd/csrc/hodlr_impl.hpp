@@ -79,6 +79,23 @@ struct BlockDesc {
     int32_t rank, level;
     int64_t toff;       // offset of this block's projections in the t/s buffers
     uint64_t U, V;      // device addresses
+    int64_t cfwd;       // contribution segment of U (V x_B) to the rows of A
+    int64_t cbwd;       // contribution segment of V^T (U^T x_A) to the rows of B (symmetric)
+};
+
+// rows [lo, lo+cnt) of leaf box `leaf` (first row leaf0) and its near-field
+// source ranges nrng[nb0 .. nb0+nn)
+struct NearItem {
+    int32_t leaf, lo, cnt, leaf0;
+    int64_t nb0;
+    int32_t nn, pad;
+};
+
+// contribution segments a leaf's rows receive at one level: ne segments of
+// len values each, the leaf's first row at contrib[base] of the first one
+struct SegRef {
+    int64_t base;
+    int32_t len, ne;
 };
 
 struct LevelData {
@@ -130,12 +147,18 @@ struct hodlr_handle_s {
     int64_t t_total = 0;                  // sum of ranks
     std::vector<void*> arenas;            // factor storage allocations
     // launch plans
-    hodlr::WorkItem* proj_items = nullptr;
+    hodlr::BlockDesc* class_blocks = nullptr;  // copies of the descriptors, by size class
+    std::vector<int64_t> class_off;        // class c: [class_off[c], class_off[c+1])
+    hodlr::WorkItem* proj_items = nullptr; // row ranges of the blocks too large for one wave
     int64_t n_proj_items = 0;
-    hodlr::WorkItem* exp_items = nullptr;  // grouped by level
-    std::vector<int64_t> exp_lvl_off;      // [kappa+2)
-    hodlr::WorkItem* near_items = nullptr;
+    hodlr::WorkItem* exp_items = nullptr;  // 64-row chunks of those blocks (level = side)
+    int64_t n_exp_items = 0;
+    hodlr::NearItem* near_items = nullptr; // 64-row chunks of the leaves
     int64_t n_near_items = 0;
+    int2* near_rng = nullptr;              // tree-order ranges of the near-list boxes
+    hodlr::SegRef* leaf_seg = nullptr;     // [leaf][level-1] contribution segments
+    int64_t contrib_total = 0;             // contribution elements per right-hand side
+    int64_t nleaf = 0;
     // matvec workspace
     void* ws = nullptr;
     size_t ws_bytes = 0;
@@ -159,8 +182,10 @@ void build_block_table(hodlr_t h, hipStream_t s);
 void compress_all(hodlr_t h, hipStream_t s);
 // apply.hip
 void plan_apply(hodlr_t h);
+// ev: nullptr or 5 events recorded before the stages and after each of
+// permute-in, projection, expansion and near field + permute-out
 void matvec(hodlr_t h, const void* X, int64_t ldx, int nrhs, int x_prec, void* Y, int64_t ldy,
-            int compute_prec, hipStream_t s);
+            int compute_prec, hipEvent_t const* ev, hipStream_t s);
 // factors.cpp-like helpers in aca.hip
 void import_level(hodlr_t h, int level, const int32_t* ranks, const double* U, const double* V,
                   hipStream_t s);

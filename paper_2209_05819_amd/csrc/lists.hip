@@ -162,6 +162,8 @@ __global__ void k_fill_blocks(const int32_t* __restrict__ row, const int32_t* __
     b.toff = 0;
     b.U = 0;
     b.V = 0;
+    b.cfwd = -1;
+    b.cbwd = -1;
     blocks[blk0 + bid[e]] = b;
     eref[e] = (blk0 + bid[e]) << 1;
 }

@@ -100,7 +100,8 @@ def main():
     ap.add_argument("--n", type=int, default=0, help="override N (smaller runs)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
-    ap.add_argument("--level-rule", type=int, default=0)
+    ap.add_argument("--level-rule", type=int, default=1,
+                    help="1: depth from the closed form (balanced tree); 0: fullest box rule")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain device copy of known size (counter calibration)")
     args = ap.parse_args()

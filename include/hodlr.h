@@ -85,7 +85,7 @@ typedef struct {
     size_t mem_budget_bytes;  /* cap on device memory held by the handle; 0 = none */
 } hodlr_opts;
 
-/* Defaults: level_rule 0, bounding cube, FP64 storage, symmetric 1,
+/* Defaults: level_rule 1, bounding cube, FP64 storage, symmetric 1,
  * max_rank 0, skip_aca 0, no budget. */
 void hodlr_default_opts(hodlr_opts* opts);
 

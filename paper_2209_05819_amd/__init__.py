@@ -246,7 +246,7 @@ def hodlr_destroy(h: int) -> None:
 class HODLR:
     """Owning wrapper: build on construction, destroy when collected."""
 
-    def __init__(self, points, kernel: Kernel, leaf_size: int, tol: float, *, level_rule=0,
+    def __init__(self, points, kernel: Kernel, leaf_size: int, tol: float, *, level_rule=1,
                  domain=None, storage=FP64, symmetric=True, max_rank=0, skip_aca=False,
                  mem_budget_bytes=0, stream=None):
         o = default_opts()

@@ -308,12 +308,14 @@ __global__ void k_pack(const AcaJob* __restrict__ jobs, const double* __restrict
     }
 }
 
+// every factor starts on a 16-byte boundary: sizes rounded up to `align` elements
 __global__ void k_sizes(const AcaJob* __restrict__ jobs, const int32_t* __restrict__ ranks,
-                        int64_t njobs, int64_t* __restrict__ su, int64_t* __restrict__ sv) {
+                        int64_t njobs, int align, int64_t* __restrict__ su,
+                        int64_t* __restrict__ sv) {
     int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (t >= njobs) return;
-    su[t] = (int64_t)ranks[t] * jobs[t].m;
-    sv[t] = (int64_t)ranks[t] * jobs[t].n;
+    su[t] = ((int64_t)ranks[t] * jobs[t].m + align - 1) / align * align;
+    sv[t] = ((int64_t)ranks[t] * jobs[t].n + align - 1) / align * align;
 }
 
 size_t job_lds_bytes(const AcaJob& j) {
@@ -325,6 +327,12 @@ size_t job_ws_doubles(const AcaJob& j) {
 }
 
 size_t storage_size(int storage) { return storage == HODLR_FP32 ? 4 : 8; }
+
+// factor sizes rounded to 16 bytes, so every U and V starts 16-byte aligned
+int64_t padded(int64_t elems, size_t es) {
+    const int64_t a = 16 / (int64_t)es;
+    return (elems + a - 1) / a * a;
+}
 
 struct ChunkResult {
     std::vector<int32_t> ranks, overflow;
@@ -380,17 +388,18 @@ void run_chunk(hodlr_t h, std::vector<AcaJob>& jobs, bool lds, size_t lds_bytes,
         int64_t* sv = (int64_t*)dalloc(h, sizeof(int64_t) * nk);
         int64_t* ou = (int64_t*)dalloc(h, sizeof(int64_t) * nk);
         int64_t* ov = (int64_t*)dalloc(h, sizeof(int64_t) * nk);
-        k_sizes<<<nblk(nk, 256), 256, 0, s>>>(djobs, dr, nk, su, sv);
+        const size_t es = storage_size(h->opts.storage);
+        k_sizes<<<nblk(nk, 256), 256, 0, s>>>(djobs, dr, nk, (int)(16 / es), su, sv);
         HIP_CHECK(hipGetLastError());
         exclusive_scan_i64(su, ou, nk, s);
         exclusive_scan_i64(sv, ov, nk, s);
         int64_t tu = 0, tv = 0;
         for (int64_t t = 0; t < nk; ++t) {
-            tu += (int64_t)okr[t] * ok[t].m;
-            tv += (int64_t)okr[t] * ok[t].n;
+            tu += padded((int64_t)okr[t] * ok[t].m, es);
+            tv += padded((int64_t)okr[t] * ok[t].n, es);
         }
-        const size_t es = storage_size(h->opts.storage);
-        char* arena = (char*)dalloc(h, es * (size_t)std::max<int64_t>(tu + tv, 1));
+        // 16 bytes of slack: kernels may read whole 16-byte words at the end
+        char* arena = (char*)dalloc(h, es * (size_t)(tu + tv) + 16);
         h->arenas.push_back(arena);
         if (h->opts.storage == HODLR_FP32)
             k_pack<float><<<(unsigned)nk, 256, 0, s>>>(djobs, ws, dr, ou, ov, (float*)arena,
@@ -547,6 +556,7 @@ void import_level(hodlr_t h, int level, const int32_t* ranks, const double* U, c
     LevelData& Lv = h->lev[level];
     HostCsr c = host_csr(h, level, s);
     const std::vector<int32_t>& st = Lv.hstart;
+    const size_t es = storage_size(h->opts.storage);
     // validate and size the arena (forward entries only)
     int64_t tu = 0, tv = 0;
     for (int64_t A = 0; A < Lv.nb; ++A)
@@ -556,13 +566,12 @@ void import_level(hodlr_t h, int level, const int32_t* ranks, const double* U, c
             if (ranks[e] < 0 || ranks[e] > std::min(m, n))
                 fail(HODLR_EINVAL, "imported rank out of range");
             if ((c.eref[e] & 1) == 0) {
-                tu += ranks[e] * m;
-                tv += ranks[e] * n;
+                tu += padded(ranks[e] * m, es);
+                tv += padded(ranks[e] * n, es);
             }
         }
     if ((tu + tv) > 0 && (!U || !V)) fail(HODLR_EINVAL, "factor arrays missing");
-    const size_t es = storage_size(h->opts.storage);
-    std::vector<char> hbuf(es * (size_t)std::max<int64_t>(tu + tv, 1));
+    std::vector<char> hbuf(es * (size_t)(tu + tv) + 16, 0);
     char* arena = (char*)dalloc(h, hbuf.size());
     h->arenas.push_back(arena);
     int64_t ou = 0, ov = 0, pu = 0, pv = 0;
@@ -588,8 +597,8 @@ void import_level(hodlr_t h, int level, const int32_t* ranks, const double* U, c
                     else
                         ((double*)hbuf.data())[tu + pv + t] = V[ov + t];
                 }
-                pu += r * m;
-                pv += r * n;
+                pu += padded(r * m, es);
+                pv += padded(r * n, es);
             }
             ou += r * m;
             ov += r * n;

@@ -73,7 +73,7 @@ extern "C" {
 void hodlr_default_opts(hodlr_opts* o) {
     if (!o) return;
     std::memset(o, 0, sizeof(*o));
-    o->level_rule = 0;
+    o->level_rule = 1;
     o->has_domain = 0;
     o->domain_side = 1.0;
     o->storage = HODLR_FP64;

@@ -98,8 +98,8 @@ __global__ __launch_bounds__(64) void k_lr_fused(const BlockDesc* __restrict__ b
     __shared__ C tw[RMAX][NR], sw[RMAX][NR];
     const BlockDesc b = blocks[blockIdx.x];
     const int lane = threadIdx.x;
-    const S* __restrict__ U = reinterpret_cast<const S*>(b.U);
-    const S* __restrict__ V = reinterpret_cast<const S*>(b.V);
+    const gptr_t<S> U = as_global<S>(b.U);
+    const gptr_t<S> V = as_global<S>(b.V);
     const int nc = min(NR, nrhs - c0);
     const int r = b.rank, m = b.m, n = b.n;
     const C* __restrict__ xA = x + (int64_t)c0 * N + b.a0;
@@ -189,20 +189,96 @@ __global__ __launch_bounds__(64) void k_lr_fused(const BlockDesc* __restrict__ b
 // independently: t_k = V[k,:] x_B, s_k = U[:,k] x_A, then c_A += U[:,k] t_k
 // and c_B += V[k,:]^T s_k.  A workgroup of W waves streams the terms in
 // batches of KB, each lane holding CH rows of A and CH columns of B (so
-// |A|, |B| <= 64 W CH): the batch's factor values stay in registers between
-// the dot products and the accumulation, so every factor byte is read from
-// memory exactly once.
+// |A|, |B| <= 64 W CH): a batch's factor values stay in registers between the
+// dot products and the accumulation, so every factor byte is read from
+// memory exactly once.  Two register buffers alternate: the loads of the next
+// batch are in flight while the current one is reduced and accumulated.
+template <typename S, typename C, int W, int CH, int KB>
+struct StreamBatch {
+    C u[KB][CH], v[KB][CH];
+};
+
+template <typename S, typename C, int W, int CH, int KB>
+__device__ __forceinline__ void stream_load(StreamBatch<S, C, W, CH, KB>& bt, gptr_t<S> U,
+                                            gptr_t<S> V, int k0, int r, int m, int n,
+                                            int base) {
+    const int kr = r - k0;   // may be <= 0: nothing is loaded
+    gptr_t<S> Vk = V + k0 * n;
+    gptr_t<S> Uk = U + k0 * m;
+#pragma unroll
+    for (int kk = 0; kk < KB; ++kk)
+#pragma unroll
+        for (int c = 0; c < CH; ++c) {
+            const int i = base + c * 64;
+            bt.v[kk][c] = (kk < kr && i < n) ? (C)Vk[kk * n + i] : (C)0;
+            bt.u[kk][c] = (kk < kr && i < m) ? (C)Uk[kk * m + i] : (C)0;
+        }
+}
+
+template <typename S, typename C, int W, int CH, int KB>
+__device__ __forceinline__ void stream_step(const StreamBatch<S, C, W, CH, KB>& bt, int sym,
+                                            const C (&xa)[CH], const C (&xb)[CH], C (&ca)[CH],
+                                            C (&cb)[CH], C (*part)[2][KB]) {
+    constexpr int Q = Log2<KB>::v;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    C pt[KB], ps[KB];
+#pragma unroll
+    for (int kk = 0; kk < KB; ++kk) {
+        pt[kk] = ps[kk] = 0;
+#pragma unroll
+        for (int c = 0; c < CH; ++c) {
+            pt[kk] += bt.v[kk][c] * xb[c];
+            ps[kk] += bt.u[kk][c] * xa[c];
+        }
+    }
+    const C tv = multi_reduce<C, KB>(pt);
+    const C sv = sym ? multi_reduce<C, KB>(ps) : (C)0;
+    C tk[KB], sk[KB];
+    if (W == 1) {
+#pragma unroll
+        for (int kk = 0; kk < KB; ++kk) {
+            tk[kk] = __shfl(tv, kk << (6 - Q), 64);
+            sk[kk] = __shfl(sv, kk << (6 - Q), 64);
+        }
+    } else {
+        const int row = lane >> (6 - Q);
+        if ((lane & ((1 << (6 - Q)) - 1)) == 0) {
+            part[wv][0][row] = tv;
+            part[wv][1][row] = sv;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < KB; ++kk) {
+            C a = 0, s2 = 0;
+#pragma unroll
+            for (int w = 0; w < W; ++w) {
+                a += part[w][0][kk];
+                s2 += part[w][1][kk];
+            }
+            tk[kk] = a;
+            sk[kk] = s2;
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int kk = 0; kk < KB; ++kk)
+#pragma unroll
+        for (int c = 0; c < CH; ++c) {
+            ca[c] += bt.u[kk][c] * tk[kk];
+            cb[c] += bt.v[kk][c] * sk[kk];
+        }
+}
+
 template <typename S, typename C, int W, int CH, int KB>
 __global__ __launch_bounds__(64 * W) void k_lr_stream(const BlockDesc* __restrict__ blocks, int sym,
                                                       const C* __restrict__ x,
                                                       C* __restrict__ contrib) {
-    constexpr int Q = Log2<KB>::v;
     __shared__ C part[W][2][KB];
     const BlockDesc b = blocks[blockIdx.x];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int r = b.rank, m = b.m, n = b.n;
-    const S* __restrict__ U = reinterpret_cast<const S*>(b.U);
-    const S* __restrict__ V = reinterpret_cast<const S*>(b.V);
+    const gptr_t<S> U = as_global<S>(b.U);
+    const gptr_t<S> V = as_global<S>(b.V);
     const int base = wv * 64 * CH + lane;
     C xa[CH], xb[CH], ca[CH], cb[CH];
 #pragma unroll
@@ -212,64 +288,14 @@ __global__ __launch_bounds__(64 * W) void k_lr_stream(const BlockDesc* __restric
         xb[c] = i < n ? x[b.b0 + i] : (C)0;
         ca[c] = cb[c] = 0;
     }
-    const int row = lane >> (6 - Q);
-    const bool writer = (lane & ((1 << (6 - Q)) - 1)) == 0;
-    for (int k0 = 0; k0 < r; k0 += KB) {
-        const int kr = min(KB, r - k0);
-        C uu[KB][CH], vv[KB][CH];
-#pragma unroll
-        for (int kk = 0; kk < KB; ++kk)
-#pragma unroll
-            for (int c = 0; c < CH; ++c) {
-                const int i = base + c * 64;
-                vv[kk][c] = (kk < kr && i < n) ? (C)V[(int64_t)(k0 + kk) * n + i] : (C)0;
-                uu[kk][c] = (kk < kr && i < m) ? (C)U[(int64_t)(k0 + kk) * m + i] : (C)0;
-            }
-        C pt[KB], ps[KB];
-#pragma unroll
-        for (int kk = 0; kk < KB; ++kk) {
-            pt[kk] = ps[kk] = 0;
-#pragma unroll
-            for (int c = 0; c < CH; ++c) {
-                pt[kk] += vv[kk][c] * xb[c];
-                ps[kk] += uu[kk][c] * xa[c];
-            }
-        }
-        const C tv = multi_reduce<C, KB>(pt);
-        const C sv = sym ? multi_reduce<C, KB>(ps) : (C)0;
-        C tk[KB], sk[KB];
-        if (W == 1) {
-#pragma unroll
-            for (int kk = 0; kk < KB; ++kk) {
-                tk[kk] = __shfl(tv, kk << (6 - Q), 64);
-                sk[kk] = __shfl(sv, kk << (6 - Q), 64);
-            }
-        } else {
-            if (writer) {
-                part[wv][0][row] = tv;
-                part[wv][1][row] = sv;
-            }
-            __syncthreads();
-#pragma unroll
-            for (int kk = 0; kk < KB; ++kk) {
-                C a = 0, s2 = 0;
-#pragma unroll
-                for (int w = 0; w < W; ++w) {
-                    a += part[w][0][kk];
-                    s2 += part[w][1][kk];
-                }
-                tk[kk] = a;
-                sk[kk] = s2;
-            }
-            __syncthreads();
-        }
-#pragma unroll
-        for (int kk = 0; kk < KB; ++kk)
-#pragma unroll
-            for (int c = 0; c < CH; ++c) {
-                ca[c] += uu[kk][c] * tk[kk];
-                cb[c] += vv[kk][c] * sk[kk];
-            }
+    StreamBatch<S, C, W, CH, KB> b0, b1;
+    stream_load(b0, U, V, 0, r, m, n, base);
+    for (int k0 = 0; k0 < r; k0 += 2 * KB) {
+        stream_load(b1, U, V, k0 + KB, r, m, n, base);
+        stream_step(b0, sym, xa, xb, ca, cb, part);
+        if (k0 + KB >= r) break;
+        stream_load(b0, U, V, k0 + 2 * KB, r, m, n, base);
+        stream_step(b1, sym, xa, xb, ca, cb, part);
     }
 #pragma unroll
     for (int c = 0; c < CH; ++c) {
@@ -317,8 +343,8 @@ __global__ __launch_bounds__(256) void k_lr_group(const BlockDesc* __restrict__ 
     BlockDesc b{};
     if (valid) b = blocks[item];
     const int r = valid ? b.rank : 0, m = b.m, n = b.n;
-    const S* __restrict__ U = reinterpret_cast<const S*>(b.U);
-    const S* __restrict__ V = reinterpret_cast<const S*>(b.V);
+    const gptr_t<S> U = as_global<S>(b.U);
+    const gptr_t<S> V = as_global<S>(b.V);
     C u[G], v[G], p[G];
 #pragma unroll
     for (int k = 0; k < G; ++k) {
@@ -369,7 +395,7 @@ __device__ __forceinline__ void wg_reduce_store(C (&acc)[NR], C (*red)[NR], int 
 }
 
 template <typename S, typename C, int NR>
-__device__ __forceinline__ void row_dot(const S* __restrict__ row, int len,
+__device__ __forceinline__ void row_dot(gptr_t<S> row, int len,
                                         const C* __restrict__ xs, int64_t N, int nc,
                                         C (&acc)[NR]) {
     C a[4][NR];
@@ -406,8 +432,8 @@ __global__ __launch_bounds__(TP) void k_project(const BlockDesc* __restrict__ bl
     __shared__ C red[TP / 64][NR];
     const WorkItem it = items[blockIdx.x];
     const BlockDesc b = blocks[it.id];
-    const S* __restrict__ Ub = reinterpret_cast<const S*>(b.U);
-    const S* __restrict__ Vb = reinterpret_cast<const S*>(b.V);
+    const gptr_t<S> Ub = as_global<S>(b.U);
+    const gptr_t<S> Vb = as_global<S>(b.V);
     const int nc = min(NR, nrhs - c0);
     const C* __restrict__ xB = x + (int64_t)c0 * N + b.b0;
     const C* __restrict__ xA = x + (int64_t)c0 * N + b.a0;
@@ -435,7 +461,7 @@ __global__ __launch_bounds__(TE) void k_expand_split(const BlockDesc* __restrict
     const BlockDesc b = blocks[it.id];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const bool tr = it.level != 0;
-    const S* __restrict__ W = reinterpret_cast<const S*>(tr ? b.V : b.U);
+    const gptr_t<S> W = as_global<S>(tr ? b.V : b.U);
     const int len = tr ? b.n : b.m;
     const C* __restrict__ coef = (tr ? sb : tb) + b.toff;
     const int o = it.lo + lane;
@@ -471,6 +497,8 @@ __global__ __launch_bounds__(TE) void k_expand_split(const BlockDesc* __restrict
 // The leaf's source ranges and per-level segments are precomputed, so its
 // loads do not depend on each other.
 constexpr int TG = 256;
+constexpr int kNearTile = 256;         // sources per LDS tile
+constexpr int kNearTileRanges = 1024;  // near boxes a tiled leaf may have
 
 template <typename XT, typename C, int NR>
 __global__ __launch_bounds__(TG) void k_gather_near(
@@ -493,12 +521,75 @@ __global__ __launch_bounds__(TG) void k_gather_near(
     C acc[NR];
 #pragma unroll
     for (int c = 0; c < NR; ++c) acc[c] = 0;
-    if (active) {
-        double xi[kMaxD];
+    double xi[kMaxD];
+    if (active)
         for (int a = 0; a < d; ++a) xi[a] = pts[a * N + i];
+    if (d <= 4 && it.nn <= kNearTileRanges) {
+        // sources staged through LDS in tiles: coalesced cooperative loads,
+        // then every lane reads them as broadcasts
+        __shared__ int s_pre[kNearTileRanges + 1], s_rs[kNearTileRanges];
+        __shared__ int s_j[kNearTile];
+        __shared__ double s_pt[4][kNearTile];
+        __shared__ C s_x[NR][kNearTile];
+        for (int e = threadIdx.x; e < it.nn; e += TG) {
+            const int2 rg = nrng[it.nb0 + e];
+            s_rs[e] = rg.x;
+            s_pre[e] = rg.y - rg.x;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            int a = 0;
+            for (int e = 0; e < it.nn; ++e) {
+                const int len = s_pre[e];
+                s_pre[e] = a;
+                a += len;
+            }
+            s_pre[it.nn] = a;
+        }
+        __syncthreads();
+        const int total = s_pre[it.nn];
+        for (int t0 = 0; t0 < total; t0 += kNearTile) {
+            const int tn = min(kNearTile, total - t0);
+            for (int q = threadIdx.x; q < tn; q += TG) {
+                const int sidx = t0 + q;
+                int lo = 0, hi = it.nn - 1;   // last range starting at or before sidx
+                while (lo < hi) {
+                    const int mid = (lo + hi + 1) >> 1;
+                    if (s_pre[mid] <= sidx)
+                        lo = mid;
+                    else
+                        hi = mid - 1;
+                }
+                const int j = s_rs[lo] + (sidx - s_pre[lo]);
+                s_j[q] = j;
+                for (int a = 0; a < d; ++a) s_pt[a][q] = pts[a * N + j];
+#pragma unroll
+                for (int c = 0; c < NR; ++c) s_x[c][q] = c < nc ? x[(int64_t)(c0 + c) * N + j] : (C)0;
+            }
+            __syncthreads();
+            if (active) {
+#pragma unroll 4
+                for (int q = sg; q < tn; q += SG) {
+                    C kij;
+                    if (s_j[q] == i) {
+                        kij = (C)kp.diag;
+                    } else {
+                        C r2 = 0;
+                        for (int a = 0; a < d; ++a) {
+                            const C dx = (C)(xi[a] - s_pt[a][q]);
+                            r2 += dx * dx;
+                        }
+                        kij = kfun(kp, r2);
+                    }
+#pragma unroll
+                    for (int c = 0; c < NR; ++c) acc[c] += kij * s_x[c][q];
+                }
+            }
+            __syncthreads();
+        }
+    } else if (active) {
         for (int e = 0; e < it.nn; ++e) {
             const int2 rg = nrng[it.nb0 + e];
-#pragma unroll 2
             for (int64_t j = rg.x + sg; j < rg.y; j += SG) {
                 C kij;
                 if (j == i) {
@@ -516,6 +607,8 @@ __global__ __launch_bounds__(TG) void k_gather_near(
                     if (c < nc) acc[c] += kij * x[(int64_t)(c0 + c) * N + j];
             }
         }
+    }
+    if (active) {
         const int64_t off = i - it.leaf0;
         for (int l = 0; l < kappa; ++l) {
             const SegRef sr = lseg[(int64_t)it.leaf * kappa + l];
@@ -580,8 +673,9 @@ void plan_apply(hodlr_t h) {
     }
     h->contrib_total = ct;
     // block classes by size: 0, 1: at most 8 / 16 rows, columns and terms
-    // (a lane group each); 2..5: one workgroup streams the block (|A|, |B| up
-    // to 64, 128, 1024, 4608); larger blocks are split over many workgroups
+    // (a lane group each); 2..5: one workgroup streams the block (|A|, |B|
+    // up to 64, 128, 1024, 4608); larger blocks are split over many
+    // workgroups
     std::vector<std::vector<std::pair<int64_t, int32_t>>> cls(kNumClasses);
     for (int64_t b = 0; b < h->nblocks; ++b) {
         const BlockDesc& bd = h->hblocks[b];
@@ -709,16 +803,18 @@ void run_matvec(hodlr_t h, const XT* X, int64_t ldx, int nrhs, XT* Y, int64_t ld
                     k_lr_group<S, C, 16><<<nblk(cnt * 16, 256), 256, 0, s>>>(it, cnt, sym, x, contrib);
                     break;
                 case 2:
-                    k_lr_stream<S, C, 1, 1, 16><<<g, 64, 0, s>>>(it, sym, x, contrib);
+                    k_lr_stream<S, C, 1, 1, 8><<<g, 64, 0, s>>>(it, sym, x, contrib);
                     break;
                 case 3:
-                    k_lr_stream<S, C, 1, 2, 8><<<g, 64, 0, s>>>(it, sym, x, contrib);
+                    k_lr_stream<S, C, 1, 2, 4><<<g, 64, 0, s>>>(it, sym, x, contrib);
                     break;
                 case 4:
-                    k_lr_stream<S, C, 4, 4, 4><<<g, 256, 0, s>>>(it, sym, x, contrib);
+                    k_lr_stream<S, C, 4, 4, sizeof(C) == 8 ? 2 : 4><<<g, 256, 0, s>>>(it, sym, x,
+                                                                                   contrib);
                     break;
                 default:
-                    k_lr_stream<S, C, 8, 9, 2><<<g, 512, 0, s>>>(it, sym, x, contrib);
+                    k_lr_stream<S, C, 8, 9, sizeof(C) == 8 ? 1 : 2><<<g, 512, 0, s>>>(it, sym, x,
+                                                                                   contrib);
                     break;
                 }
             }

@@ -71,6 +71,17 @@ __device__ __forceinline__ float kfun(const KParams& k, float r2) {
     return (float)k.scale * f;
 }
 
+// A device address held as an integer, as a pointer into the global address
+// space (global loads rather than generic ones, which also count against the
+// LDS wait counter).
+template <typename T>
+using gptr_t = const T __attribute__((address_space(1)))*;
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));   // one 16-byte word
+template <typename T>
+__device__ __forceinline__ gptr_t<T> as_global(uint64_t a) {
+    return (gptr_t<T>)a;
+}
+
 // One stored low-rank block: rows = box A (|A| = m, tree offset a0),
 // columns = box B (|B| = n, tree offset b0).  U is m x r column by column,
 // V is r x n row by row, both in the storage type at byte addresses U, V.

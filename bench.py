@@ -31,21 +31,68 @@ def _events(torch, n):
     return [torch.cuda.Event(enable_timing=True) for _ in range(n)]
 
 
+NCLASS = 6
+CLASS_KERNELS = ["k_lr_group<8>", "k_lr_group<16>", "k_lr_stream<1,1,8>", "k_lr_stream<1,2,4>",
+                 "k_lr_stream<4,4,*>", "k_lr_stream<8,9,*>"]
+
+
 def time_matvecs(P, torch, H, X, Y, prec, warmup, steps):
-    """Warm-up, then `steps` matvecs each bracketed by the 5 stage events."""
+    """Warm-up, then `steps` matvecs, each with 11 HIP events recorded by the
+    library on the stream: the 4 stages and the launch of every block class."""
     for _ in range(warmup):
         P.hodlr_matvec(H.h, X, Y, prec)
     torch.cuda.synchronize()
-    evs = [_events(torch, 5) for _ in range(steps)]
+    evs = [_events(torch, 5 + NCLASS) for _ in range(steps)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for e in evs:
         P.hodlr_matvec_events(H.h, X, Y, e, prec)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    per = np.array([[e[i].elapsed_time(e[i + 1]) for i in range(4)] for e in evs])  # ms
+    stages = np.array([[e[i].elapsed_time(e[i + 1]) for i in range(4)] for e in evs])  # ms
+    # class c runs between the previous class's event (or the end of stage 1)
+    # and its own
+    cls = np.array([[(e[1] if c == 0 else e[4 + c]).elapsed_time(e[5 + c]) for c in range(NCLASS)]
+                    for e in evs])
     lat = np.array([e[0].elapsed_time(e[4]) for e in evs])
-    return wall, per, lat
+    return wall, stages, cls, lat
+
+
+def roofline(info, cls_ms, sf, sc):
+    """Dominant block-class kernel: algorithmic bytes (every stored factor
+    element of its blocks once, plus the x reads and contribution writes)
+    over its measured average duration."""
+    c = int(np.argmax(cls_ms))
+    nbytes = info.class_factor_elems[c] * sf + info.class_vector_elems[c] * sc
+    achieved = nbytes / (cls_ms[c] * 1e-3) / 1e9
+    return {"bound": "hbm", "kernel": CLASS_KERNELS[c], "blocks": int(info.class_blocks[c]),
+            "bytes_per_launch": int(nbytes), "avg_ms": float(cls_ms[c]), "achieved": achieved,
+            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS}
+
+
+def measured_traffic(workload, kernel, storage):
+    """HBM bytes per launch of `kernel` from the committed counter summaries
+    under profiles/ (FETCH_SIZE and WRITE_SIZE passes, scaled by a copy of
+    known size), or None when none matches or the apply source has changed
+    since the counters were taken."""
+    import glob
+    import hashlib
+    with open(os.path.join(ROOT, "paper_2209_05819_amd", "csrc", "apply.hip"), "rb") as f:
+        cur = hashlib.sha256(f.read()).hexdigest()
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*_traffic.md"))):
+        rec = {}
+        with open(path) as f:
+            for line in f:
+                k, sep, v = line.strip().partition(": ")
+                if sep and k in ("workload", "kernel", "storage", "traffic_bytes",
+                                 "apply_hip_sha256"):
+                    rec[k] = v.strip()
+        if (rec.get("workload"), rec.get("kernel"), rec.get("storage")) == (workload, kernel,
+                                                                            storage):
+            if rec.get("apply_hip_sha256") != cur:
+                return None
+            return float(rec["traffic_bytes"])
+    return None
 
 
 def factor_bytes(info, elem):
@@ -56,7 +103,7 @@ def rel_err_rows(y, ref, rows):
     return float(np.linalg.norm(y[rows] - ref) / np.linalg.norm(ref))
 
 
-def cpu_baseline(w, pts, q, sample_rows_budget_s=30.0):
+def cpu_baseline(w, pts, q, level_rule, sample_rows_budget_s=30.0):
     """The oracle timed on the host: its matvec over the target rows of one
     level-1 box (all levels' blocks of those rows), after compressing exactly
     the blocks those rows need."""
@@ -64,7 +111,7 @@ def cpu_baseline(w, pts, q, sample_rows_budget_s=30.0):
     oracle.build(force=False)
     k = oracle.kernel(w.kernel, diag=w.diag)
     t0 = time.perf_counter()
-    o = oracle.OracleHODLR(pts, w.leaf, 0, domain=w.domain)
+    o = oracle.OracleHODLR(pts, w.leaf, level_rule, domain=w.domain)
     start, _, _ = o.boxes(1)
     r0, r1 = int(start[0]), int(start[1])
     o.compress(k, w.tol, rows=(r0, r1))
@@ -134,20 +181,21 @@ def main():
 
     X = torch.tensor(q, dtype=torch.float64, device="cuda")
     Y = torch.empty_like(X)
-    wall, per, lat = time_matvecs(P, torch, H64, X, Y, P.FP64, args.warmup, args.steps)
+    wall, per, cls, lat = time_matvecs(P, torch, H64, X, Y, P.FP64, args.warmup, args.steps)
     y64 = Y.cpu().numpy()
     ms_step = wall / args.steps * 1e3
     stage_ms = per.mean(axis=0)
+    cls_ms = cls.mean(axis=0)
     print(f"[bench] FP64 {ms_step:.3f} ms/step stages {np.round(stage_ms, 3).tolist()}",
           file=sys.stderr, flush=True)
 
     fb64 = factor_bytes(info, 8)
-    dominant = 1
-    names = {1: "k_lr_fused+k_project"}
-    # one pass over every stored factor element, plus the vectors it touches
+    roof64 = roofline(info, cls_ms, 8, 8)
+    roof64["traffic"] = measured_traffic(w.name, roof64["kernel"], "fp64")
+    # whole product: every stored factor element once plus x in and y out
     vec_bytes = 8 * (2 * N)
-    achieved = (fb64 + vec_bytes) / (stage_ms[dominant] * 1e-3) / 1e9
     matvec_gbs = (fb64 + vec_bytes) / (lat.mean() * 1e-3) / 1e9
+    apply_gbs = fb64 / (stage_ms[1] * 1e-3 + stage_ms[2] * 1e-3) / 1e9
 
     mixed = None
     if not args.no_mixed:
@@ -158,11 +206,11 @@ def main():
         build32 = time.perf_counter() - t0
         info32 = H32.info()
         Y32 = torch.empty_like(X)
-        wall32, per32, lat32 = time_matvecs(P, torch, H32, X, Y32, P.FP32, args.warmup, args.steps)
+        wall32, per32, cls32, lat32 = time_matvecs(P, torch, H32, X, Y32, P.FP32, args.warmup,
+                                                   args.steps)
         y32 = Y32.cpu().numpy()
         fb32 = factor_bytes(info32, 4)
         st32 = per32.mean(axis=0)
-        dom32 = 1
         mixed = {
             "value": N / (wall32 / args.steps),
             "ms_per_step": wall32 / args.steps * 1e3,
@@ -173,11 +221,11 @@ def main():
             "factor_bytes": int(fb32),
             "build_s": round(build32, 2),
             "speedup_vs_fp64": (N / (wall32 / args.steps)) / (N / (wall / args.steps)),
-            "roofline": {"bound": "hbm", "kernel": names[dom32],
-                         "achieved": (fb32 + 4 * 2 * N) / (st32[dom32] * 1e-3) / 1e9,
-                         "peak": HBM_PEAK_GBS, "unit": "GB/s"},
+            "class_ms": [round(float(v), 4) for v in cls32.mean(axis=0)],
+            "roofline": roofline(info32, cls32.mean(axis=0), 4, 4),
+            "apply_roofline": {"achieved": fb32 / ((st32[1] + st32[2]) * 1e-3) / 1e9,
+                               "frac": fb32 / ((st32[1] + st32[2]) * 1e-3) / 1e9 / HBM_PEAK_GBS},
         }
-        mixed["roofline"]["frac"] = mixed["roofline"]["achieved"] / HBM_PEAK_GBS
         del H32
 
     # accuracy on sampled rows against the plain definition (direct sum)
@@ -192,16 +240,17 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline:
-        cpu, crow, cb = cpu_baseline(w, pts, q)
+        cpu, crow, cb = cpu_baseline(w, pts, q, args.level_rule)
         cpu_err = float(np.linalg.norm(y64[crow] - cb) / np.linalg.norm(cb))
         cpu["gpu_vs_oracle_rel_err"] = cpu_err
 
     if args.copy_calibration:
-        # plain device copy of 1 GiB, for scaling the HBM traffic counters
-        a = torch.empty(1 << 27, dtype=torch.float64, device="cuda")
+        # plain elementwise pass over 1 GiB (reads 1 GiB, writes 1 GiB), for
+        # scaling the HBM traffic counters of the same run
+        a = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
         b = torch.empty_like(a)
         for _ in range(3):
-            b.copy_(a)
+            torch.neg(a, out=b)
         torch.cuda.synchronize()
 
     out = {
@@ -226,7 +275,7 @@ def main():
         "rel_err": err64,
         "rel_err_ref": "direct sum on 1024 sampled rows (seed 203)",
         "stage_ms": [round(float(v), 4) for v in stage_ms],
-        "stages": ["permute_in", "fused_blocks+split_projection", "split_expansion",
+        "stages": ["permute_in", "block_classes+split_projection", "split_expansion",
                    "gather+near_field+permute_out"],
         "build_s": round(build64, 2),
         "build_ms_tree_lists_aca": [round(info.build_ms[i], 1) for i in range(3)],
@@ -235,9 +284,11 @@ def main():
         "rank_max": int(max([info.rank_max[l] for l in range(1, info.kappa + 1)] or [0])),
         "factor_bytes": int(fb64),
         "near_pairs": int(info.near_pairs),
-        "roofline": {"bound": "hbm", "kernel": names[dominant], "achieved": achieved,
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": None},
+        "class_ms": [round(float(v), 4) for v in cls_ms],
+        "class_kernels": CLASS_KERNELS,
+        "roofline": roof64,
+        "apply_roofline": {"achieved": apply_gbs, "frac": apply_gbs / HBM_PEAK_GBS,
+                           "bytes": int(fb64), "what": "all stored factors once over stages 2+3"},
         "matvec_roofline": {"achieved": matvec_gbs, "frac": matvec_gbs / HBM_PEAK_GBS,
                             "bytes": int(fb64 + vec_bytes)},
         "mixed": mixed,

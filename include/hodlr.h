@@ -119,12 +119,16 @@ hodlr_status hodlr_build(const double* points, int64_t N, int d, const hodlr_ker
 hodlr_status hodlr_matvec(hodlr_t h, const void* X, int64_t ldx, int nrhs, int x_prec,
                           void* Y, int64_t ldy, int compute_prec, void* stream);
 
-/* hodlr_matvec that also records five caller-created hipEvent_t (passed as
- * void*, nevents == 5) on the stream: before the product, and after each of
- * its four stages (permutation into tree order; projections t = V x of every
- * stored block; expansion U t into every box of every level; near field
- * evaluated on the fly plus permutation back).  For timing; same results and
- * errors as hodlr_matvec (EINVAL if events is NULL or nevents != 5). */
+/* hodlr_matvec that also records caller-created hipEvent_t (passed as
+ * void*) on the stream, for timing.  nevents == 5: before the product and
+ * after each of its four stages (permutation into tree order; projections
+ * and one-pass applications of the stored blocks; expansions of the blocks
+ * split over several workgroups; gather of the contributions plus the near
+ * field evaluated on the fly plus permutation back).  nevents == 11: the
+ * same five, then events[5 + c] recorded after the launch of block-size
+ * class c = 0..5 inside the second stage (classes of hodlr_info
+ * class_blocks).  Same results and errors as hodlr_matvec (EINVAL if events
+ * is NULL or nevents is neither 5 nor 11). */
 hodlr_status hodlr_matvec_events(hodlr_t h, const void* X, int64_t ldx, int nrhs, int x_prec,
                                  void* Y, int64_t ldy, int compute_prec, void* stream,
                                  void* const* events, int nevents);
@@ -144,6 +148,14 @@ typedef struct {
     int32_t rank_min[32], rank_max[32];
     double rank_mean[32];     /* over stored blocks */
     int64_t factor_elems[32]; /* sum over stored blocks of r(|I|+|J|) */
+    /* blocks applied by one workgroup, by size class (0, 1: at most 8 / 16
+     * rows, columns and terms; 2..5: |A|, |B| up to 64, 128, 1024, 4608),
+     * their factor elements sum r(|I|+|J|) and vector elements 2(|I|+|J|) */
+    int64_t class_blocks[8];
+    int64_t class_factor_elems[8];
+    int64_t class_vector_elems[8];
+    int64_t split_blocks;         /* larger blocks, split over workgroups */
+    int64_t split_factor_elems;
     int64_t near_entries;     /* near-list entries at the leaves */
     int64_t near_pairs;       /* point pairs of the near field */
     size_t device_bytes;      /* device memory held by the handle */

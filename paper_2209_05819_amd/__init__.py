@@ -47,7 +47,10 @@ class Info(C.Structure):
                 ("nboxes", C.c_int64 * 32), ("il_entries", C.c_int64 * 32),
                 ("stored_blocks", C.c_int64 * 32), ("rank_min", C.c_int32 * 32),
                 ("rank_max", C.c_int32 * 32), ("rank_mean", C.c_double * 32),
-                ("factor_elems", C.c_int64 * 32), ("near_entries", C.c_int64),
+                ("factor_elems", C.c_int64 * 32), ("class_blocks", C.c_int64 * 8),
+                ("class_factor_elems", C.c_int64 * 8), ("class_vector_elems", C.c_int64 * 8),
+                ("split_blocks", C.c_int64), ("split_factor_elems", C.c_int64),
+                ("near_entries", C.c_int64),
                 ("near_pairs", C.c_int64), ("device_bytes", C.c_size_t),
                 ("build_ms", C.c_double * 4)]
 
@@ -164,8 +167,8 @@ def _mv_args(X, Y):
 
 
 def hodlr_matvec_events(h: int, X, Y, events, compute_prec: int = FP64, stream=None) -> None:
-    """hodlr_matvec recording 5 torch.cuda.Event (enable_timing=True) at the
-    stage boundaries on the stream."""
+    """hodlr_matvec recording 5 or 11 torch.cuda.Event (enable_timing=True)
+    at the stage boundaries on the stream (see hodlr_matvec_events)."""
     xp, nrhs, ldx, ldy = _mv_args(X, Y)
     if stream is None:
         import torch
@@ -173,7 +176,7 @@ def hodlr_matvec_events(h: int, X, Y, events, compute_prec: int = FP64, stream=N
     for e in events:
         if e.cuda_event == 0:   # torch creates the event lazily
             e.record()
-    arr = (C.c_void_p * 5)(*[C.c_void_p(e.cuda_event) for e in events])
+    arr = (C.c_void_p * len(events))(*[C.c_void_p(e.cuda_event) for e in events])
     _check(lib().hodlr_matvec_events(C.c_void_p(h), C.c_void_p(X.data_ptr()), ldx, nrhs, xp,
                                      C.c_void_p(Y.data_ptr()), ldy, compute_prec,
                                      C.c_void_p(int(stream)), arr, len(events)))

@@ -159,13 +159,15 @@ hodlr_status matvec_checked(hodlr_t h, const void* X, int64_t ldx, int nrhs, int
         return set_error(HODLR_EINVAL, "x_prec must be FP64 or FP32");
     if (compute_prec != HODLR_FP64 && compute_prec != HODLR_FP32)
         return set_error(HODLR_EINVAL, "compute_prec must be FP64 or FP32");
-    if (events && nevents != 5) return set_error(HODLR_EINVAL, "events must hold 5 entries");
+    if (events && nevents != 5 && nevents != 5 + hodlr::kApplyClasses)
+        return set_error(HODLR_EINVAL, "events must hold 5 or 11 entries");
     for (int l = 1; l <= h->kappa; ++l)
         if (!h->lev[l].has_factors) return set_error(HODLR_EINVAL, "factors missing");
     if (!h->near_items) return set_error(HODLR_EINVAL, "factors missing");
     return guarded([&] {
         hodlr::matvec(h, X, ldx, nrhs, x_prec, Y, ldy, compute_prec,
-                      reinterpret_cast<hipEvent_t const*>(events), (hipStream_t)stream);
+                      reinterpret_cast<hipEvent_t const*>(events), events ? nevents : 0,
+                      (hipStream_t)stream);
     });
 }
 }  // namespace
@@ -212,6 +214,15 @@ hodlr_status hodlr_get_info(hodlr_t h, hodlr_info* info) {
         info->rank_mean[l] = h->lev[l].nblk ? rs / h->lev[l].nblk : 0.0;
         info->factor_elems[l] = fe;
     }
+    for (int c = 0; c < hodlr::kApplyClasses && c < 8; ++c) {
+        info->class_blocks[c] = (int64_t)h->class_off.size() > c + 1
+                                    ? h->class_off[c + 1] - h->class_off[c]
+                                    : 0;
+        info->class_factor_elems[c] = h->cls_felems[c];
+        info->class_vector_elems[c] = h->cls_velems[c];
+    }
+    info->split_blocks = h->split_blocks;
+    info->split_factor_elems = h->split_felems;
     info->near_entries = h->near_nnz;
     info->near_pairs = h->near_pairs;
     info->device_bytes = h->device_bytes;

@@ -26,7 +26,7 @@ constexpr int TP = 256;   // split projection workgroup (4 waves)
 constexpr int TE = 256;   // split expansion workgroup (4 waves share 64 rows)
 constexpr int KB = 16;    // rows reduced together in the fused projection
 constexpr int kFusedMaxRank = 256;  // projections a fused wave keeps in LDS at once
-constexpr int kNumClasses = 6;      // block size classes of the one-workgroup kernels
+constexpr int kNumClasses = kApplyClasses;  // block size classes of the one-workgroup kernels
 
 template <typename C>
 __device__ __forceinline__ C wsum(C v) {
@@ -677,6 +677,8 @@ void plan_apply(hodlr_t h) {
     // up to 64, 128, 1024, 4608); larger blocks are split over many
     // workgroups
     std::vector<std::vector<std::pair<int64_t, int32_t>>> cls(kNumClasses);
+    for (int c = 0; c < 8; ++c) h->cls_felems[c] = h->cls_velems[c] = 0;
+    h->split_blocks = h->split_felems = 0;
     for (int64_t b = 0; b < h->nblocks; ++b) {
         const BlockDesc& bd = h->hblocks[b];
         const int64_t el = (int64_t)std::max(bd.rank, 0) * (bd.m + bd.n);
@@ -689,9 +691,14 @@ void plan_apply(hodlr_t h) {
         else if (side <= 128) c = 3;
         else if (side <= 1024) c = 4;
         else if (side <= 4608) c = 5;
+        const int64_t vel = 2 * (int64_t)(bd.m + bd.n) / (h->opts.symmetric ? 1 : 2);
         if (c >= 0) {
             cls[c].push_back({el, (int32_t)b});
+            h->cls_felems[c] += el;
+            h->cls_velems[c] += vel;
         } else {
+            ++h->split_blocks;
+            h->split_felems += el;
             const int per = 1;
             for (int k = 0; k < bd.rank; k += per)
                 proj.push_back(WorkItem{(int32_t)b, k, std::min(per, bd.rank - k), bd.level});
@@ -772,7 +779,7 @@ namespace {
 
 template <typename XT, typename S, typename C, int NR>
 void run_matvec(hodlr_t h, const XT* X, int64_t ldx, int nrhs, XT* Y, int64_t ldy, char* ws,
-                hipEvent_t const* ev, hipStream_t s) {
+                hipEvent_t const* ev, int nev, hipStream_t s) {
     const int64_t N = h->N;
     const int64_t TT = std::max<int64_t>(h->t_total, 1);
     const int64_t CT = std::max<int64_t>(h->contrib_total, 1);
@@ -792,7 +799,10 @@ void run_matvec(hodlr_t h, const XT* X, int64_t ldx, int nrhs, XT* Y, int64_t ld
             // one launch per size class
             for (int c = 0; c < kNumClasses; ++c) {
                 const int64_t n0 = h->class_off[c], cnt = h->class_off[c + 1] - n0;
-                if (!cnt) continue;
+                if (!cnt) {
+                    if (ev && nev > 5 && c0 == 0) HIP_CHECK(hipEventRecord(ev[5 + c], s));
+                    continue;
+                }
                 const BlockDesc* it = h->class_blocks + n0;
                 const unsigned g = (unsigned)cnt;
                 switch (c) {
@@ -817,6 +827,7 @@ void run_matvec(hodlr_t h, const XT* X, int64_t ldx, int nrhs, XT* Y, int64_t ld
                                                                                    contrib);
                     break;
                 }
+                if (ev && nev > 5 && c0 == 0) HIP_CHECK(hipEventRecord(ev[5 + c], s));
             }
         } else {
             const int64_t cnt = h->class_off[kNumClasses];
@@ -844,19 +855,19 @@ void run_matvec(hodlr_t h, const XT* X, int64_t ldx, int nrhs, XT* Y, int64_t ld
 
 template <typename XT, typename S, typename C>
 void dispatch_nr(hodlr_t h, const XT* X, int64_t ldx, int nrhs, XT* Y, int64_t ldy, char* ws,
-                 hipEvent_t const* ev, hipStream_t s) {
+                 hipEvent_t const* ev, int nev, hipStream_t s) {
     if (nrhs == 1)
-        run_matvec<XT, S, C, 1>(h, X, ldx, nrhs, Y, ldy, ws, ev, s);
+        run_matvec<XT, S, C, 1>(h, X, ldx, nrhs, Y, ldy, ws, ev, nev, s);
     else if (nrhs <= 4)
-        run_matvec<XT, S, C, 4>(h, X, ldx, nrhs, Y, ldy, ws, ev, s);
+        run_matvec<XT, S, C, 4>(h, X, ldx, nrhs, Y, ldy, ws, ev, nev, s);
     else
-        run_matvec<XT, S, C, 8>(h, X, ldx, nrhs, Y, ldy, ws, ev, s);
+        run_matvec<XT, S, C, 8>(h, X, ldx, nrhs, Y, ldy, ws, ev, nev, s);
 }
 
 }  // namespace
 
 void matvec(hodlr_t h, const void* X, int64_t ldx, int nrhs, int x_prec, void* Y, int64_t ldy,
-            int compute_prec, hipEvent_t const* ev, hipStream_t s) {
+            int compute_prec, hipEvent_t const* ev, int nev, hipStream_t s) {
     const int64_t N = h->N;
     const size_t cs = compute_prec == HODLR_FP32 ? 4 : 8;
     const int64_t TT = std::max<int64_t>(h->t_total, 1);
@@ -879,17 +890,17 @@ void matvec(hodlr_t h, const void* X, int64_t ldx, int nrhs, int x_prec, void* Y
     if (x_prec == HODLR_FP64) {
         const double* Xd = (const double*)X;
         double* Yd = (double*)Y;
-        if (!s32 && !c32) dispatch_nr<double, double, double>(h, Xd, ldx, nrhs, Yd, ldy, ws, ev, s);
-        else if (!s32 && c32) dispatch_nr<double, double, float>(h, Xd, ldx, nrhs, Yd, ldy, ws, ev, s);
-        else if (s32 && !c32) dispatch_nr<double, float, double>(h, Xd, ldx, nrhs, Yd, ldy, ws, ev, s);
-        else dispatch_nr<double, float, float>(h, Xd, ldx, nrhs, Yd, ldy, ws, ev, s);
+        if (!s32 && !c32) dispatch_nr<double, double, double>(h, Xd, ldx, nrhs, Yd, ldy, ws, ev, nev, s);
+        else if (!s32 && c32) dispatch_nr<double, double, float>(h, Xd, ldx, nrhs, Yd, ldy, ws, ev, nev, s);
+        else if (s32 && !c32) dispatch_nr<double, float, double>(h, Xd, ldx, nrhs, Yd, ldy, ws, ev, nev, s);
+        else dispatch_nr<double, float, float>(h, Xd, ldx, nrhs, Yd, ldy, ws, ev, nev, s);
     } else {
         const float* Xf = (const float*)X;
         float* Yf = (float*)Y;
-        if (!s32 && !c32) dispatch_nr<float, double, double>(h, Xf, ldx, nrhs, Yf, ldy, ws, ev, s);
-        else if (!s32 && c32) dispatch_nr<float, double, float>(h, Xf, ldx, nrhs, Yf, ldy, ws, ev, s);
-        else if (s32 && !c32) dispatch_nr<float, float, double>(h, Xf, ldx, nrhs, Yf, ldy, ws, ev, s);
-        else dispatch_nr<float, float, float>(h, Xf, ldx, nrhs, Yf, ldy, ws, ev, s);
+        if (!s32 && !c32) dispatch_nr<float, double, double>(h, Xf, ldx, nrhs, Yf, ldy, ws, ev, nev, s);
+        else if (!s32 && c32) dispatch_nr<float, double, float>(h, Xf, ldx, nrhs, Yf, ldy, ws, ev, nev, s);
+        else if (s32 && !c32) dispatch_nr<float, float, double>(h, Xf, ldx, nrhs, Yf, ldy, ws, ev, nev, s);
+        else dispatch_nr<float, float, float>(h, Xf, ldx, nrhs, Yf, ldy, ws, ev, nev, s);
     }
 }
 

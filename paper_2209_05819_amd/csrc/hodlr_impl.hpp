@@ -160,6 +160,8 @@ struct hodlr_handle_s {
     // launch plans
     hodlr::BlockDesc* class_blocks = nullptr;  // copies of the descriptors, by size class
     std::vector<int64_t> class_off;        // class c: [class_off[c], class_off[c+1])
+    int64_t cls_felems[8]{}, cls_velems[8]{};  // factor / vector elements per class
+    int64_t split_blocks = 0, split_felems = 0;
     hodlr::WorkItem* proj_items = nullptr; // row ranges of the blocks too large for one wave
     int64_t n_proj_items = 0;
     hodlr::WorkItem* exp_items = nullptr;  // 64-row chunks of those blocks (level = side)
@@ -193,11 +195,14 @@ void build_block_table(hodlr_t h, hipStream_t s);
 void compress_all(hodlr_t h, hipStream_t s);
 // apply.hip
 void plan_apply(hodlr_t h);
-// ev: nullptr or 5 events recorded before the stages and after each of
-// permute-in, projection, expansion and near field + permute-out
+// ev: nullptr or nev = 5 or 5 + kApplyClasses events: [0] before the
+// product, [1] after permute-in, [2] after all block projections (one-pass
+// blocks and split projections), [3] after the split expansions, [4] after
+// gather + near field + permute-out; [5 + c] after the launch of size class c
+constexpr int kApplyClasses = 6;
 void matvec(hodlr_t h, const void* X, int64_t ldx, int nrhs, int x_prec, void* Y, int64_t ldy,
-            int compute_prec, hipEvent_t const* ev, hipStream_t s);
-// factors.cpp-like helpers in aca.hip
+            int compute_prec, hipEvent_t const* ev, int nev, hipStream_t s);
+// factor import / export in aca.hip
 void import_level(hodlr_t h, int level, const int32_t* ranks, const double* U, const double* V,
                   hipStream_t s);
 void export_level(hodlr_t h, int level, int32_t* ranks, int64_t* u_elems, int64_t* v_elems,

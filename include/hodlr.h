@@ -75,7 +75,10 @@ typedef struct {
     int has_domain;
     double domain_lo[8];
     double domain_side;
-    int storage;          /* hodlr_prec of the stored U/V factors (FP64 or FP32) */
+    /* hodlr_prec of the stored U/V factors: FP64, FP32 or BF16 (rounded to
+     * nearest even; BF16 factors are applied in FP32 arithmetic, on matrix
+     * cores when nrhs > 1) */
+    int storage;
     /* 1: store one factor pair per unordered block pair {A,B} and apply
      * K(B,A) = K(A,B)^T (the kernel is symmetric and both index sets are the
      * same point set); 0: store a pair for every ordered block (A,B) */
@@ -113,9 +116,14 @@ hodlr_status hodlr_build(const double* points, int64_t N, int d, const hodlr_ker
  *            (FP64 or FP32) for both.  Y must not overlap X.
  *   compute_prec  FP64: FP64 arithmetic throughout; FP32: FP32 near field
  *            and FP32 accumulation (factors are read in their storage type).
+ *            BF16 storage requires FP32; with nrhs > 1 the blocks of at most
+ *            512 rows and columns are applied on BF16 matrix cores (x and the
+ *            projections V x rounded to BF16, FP32 accumulation), 16 or 32
+ *            right-hand sides per pass.
  *   Asynchronous on stream; owns a workspace inside the handle, so calls on
  *   one handle must not overlap in time (serialize them on one stream).
- * Errors: EINVAL (nrhs < 1, ld < N, bad prec, factors missing), EDEVICE. */
+ * Errors: EINVAL (nrhs < 1, ld < N, bad prec, BF16 storage with FP64
+ * compute, factors missing), EDEVICE. */
 hodlr_status hodlr_matvec(hodlr_t h, const void* X, int64_t ldx, int nrhs, int x_prec,
                           void* Y, int64_t ldy, int compute_prec, void* stream);
 
@@ -160,6 +168,18 @@ typedef struct {
     int64_t near_pairs;       /* point pairs of the near field */
     size_t device_bytes;      /* device memory held by the handle */
     double build_ms[4];       /* tree, lists, ACA, packing */
+    /* BF16 storage, several right-hand sides (matrix cores, two passes):
+     * projection jobs by workgroup width W = 1, 2, 4, 8 waves (a job
+     * projects one side of a stored block over a panel of at most 64 W
+     * columns), the factor elements and the x elements per right-hand side
+     * they read; the factor elements the expansion pass reads (every
+     * interaction-list entry's factor with |I| rows); projection elements per
+     * right-hand side */
+    int64_t mfma_proj_jobs[4];
+    int64_t mfma_proj_factor_elems[4];
+    int64_t mfma_proj_vector_elems[4];
+    int64_t mfma_expand_factor_elems;
+    int64_t mfma_proj_elems;
 } hodlr_info;
 
 hodlr_status hodlr_get_info(hodlr_t h, hodlr_info* info);

@@ -52,7 +52,10 @@ class Info(C.Structure):
                 ("split_blocks", C.c_int64), ("split_factor_elems", C.c_int64),
                 ("near_entries", C.c_int64),
                 ("near_pairs", C.c_int64), ("device_bytes", C.c_size_t),
-                ("build_ms", C.c_double * 4)]
+                ("build_ms", C.c_double * 4),
+                ("mfma_proj_jobs", C.c_int64 * 4), ("mfma_proj_factor_elems", C.c_int64 * 4),
+                ("mfma_proj_vector_elems", C.c_int64 * 4), ("mfma_expand_factor_elems", C.c_int64),
+                ("mfma_proj_elems", C.c_int64)]
 
 
 _lib = None

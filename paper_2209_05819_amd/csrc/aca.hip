@@ -14,6 +14,9 @@
 #include <algorithm>
 #include <climits>
 
+#include <cstdio>
+#include <cstdlib>
+
 #include "hodlr_impl.hpp"
 
 namespace hodlr {
@@ -284,9 +287,14 @@ template <>
 __device__ __forceinline__ float to_storage<float>(double v) {
     return (float)v;
 }
+template <>
+__device__ __forceinline__ bf16 to_storage<bf16>(double v) {
+    return (bf16)bf16_bits(v);
+}
 
-// copy each job's first r columns of U and rows of V into the arena and
-// record the addresses in the block table
+// copy each job's first r columns of U and rows of V into the arena (terms
+// fstride<S> elements apart, zero padded) and record the addresses in the
+// block table
 template <typename S>
 __global__ void k_pack(const AcaJob* __restrict__ jobs, const double* __restrict__ wsbase,
                        const int32_t* __restrict__ ranks, const int64_t* __restrict__ uoff,
@@ -298,8 +306,15 @@ __global__ void k_pack(const AcaJob* __restrict__ jobs, const double* __restrict
     const double* gV = gU + (int64_t)J.cap * J.m;
     S* dU = arena_u + uoff[blockIdx.x];
     S* dV = arena_v + voff[blockIdx.x];
-    for (int64_t e = threadIdx.x; e < (int64_t)r * J.m; e += blockDim.x) dU[e] = to_storage<S>(gU[e]);
-    for (int64_t e = threadIdx.x; e < (int64_t)r * J.n; e += blockDim.x) dV[e] = to_storage<S>(gV[e]);
+    const int64_t lu = fstride<S>(J.m), lv = fstride<S>(J.n);
+    for (int64_t e = threadIdx.x; e < (int64_t)r * lu; e += blockDim.x) {
+        const int64_t k = e / lu, i = e - k * lu;
+        dU[e] = to_storage<S>(i < J.m ? gU[k * J.m + i] : 0.0);
+    }
+    for (int64_t e = threadIdx.x; e < (int64_t)r * lv; e += blockDim.x) {
+        const int64_t k = e / lv, j = e - k * lv;
+        dV[e] = to_storage<S>(j < J.n ? gV[k * J.n + j] : 0.0);
+    }
     if (threadIdx.x == 0) {
         BlockDesc& b = blocks[J.block];
         b.rank = r;
@@ -310,12 +325,14 @@ __global__ void k_pack(const AcaJob* __restrict__ jobs, const double* __restrict
 
 // every factor starts on a 16-byte boundary: sizes rounded up to `align` elements
 __global__ void k_sizes(const AcaJob* __restrict__ jobs, const int32_t* __restrict__ ranks,
-                        int64_t njobs, int align, int64_t* __restrict__ su,
+                        int64_t njobs, int align, int pad8, int64_t* __restrict__ su,
                         int64_t* __restrict__ sv) {
     int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (t >= njobs) return;
-    su[t] = ((int64_t)ranks[t] * jobs[t].m + align - 1) / align * align;
-    sv[t] = ((int64_t)ranks[t] * jobs[t].n + align - 1) / align * align;
+    const int64_t lu = pad8 ? fstride<bf16>(jobs[t].m) : jobs[t].m;
+    const int64_t lv = pad8 ? fstride<bf16>(jobs[t].n) : jobs[t].n;
+    su[t] = ((int64_t)ranks[t] * lu + align - 1) / align * align;
+    sv[t] = ((int64_t)ranks[t] * lv + align - 1) / align * align;
 }
 
 size_t job_lds_bytes(const AcaJob& j) {
@@ -326,12 +343,34 @@ size_t job_ws_doubles(const AcaJob& j) {
     return (size_t)j.cap * (j.m + j.n) + ((size_t)j.m + 7) / 8;
 }
 
-size_t storage_size(int storage) { return storage == HODLR_FP32 ? 4 : 8; }
+size_t storage_size(int storage) {
+    return storage == HODLR_FP32 ? 4 : (storage == HODLR_BF16 ? 2 : 8);
+}
+
+// elements between rank terms of a factor of length len in this storage
+int64_t term_stride(int64_t len, size_t es) { return es == 2 ? fstride<bf16>(len) : len; }
 
 // factor sizes rounded to 16 bytes, so every U and V starts 16-byte aligned
 int64_t padded(int64_t elems, size_t es) {
     const int64_t a = 16 / (int64_t)es;
     return (elems + a - 1) / a * a;
+}
+
+// host-side element access in a storage buffer of element size es
+void put_elem(char* buf, int64_t idx, size_t es, double v) {
+    if (es == 8) {
+        ((double*)buf)[idx] = v;
+    } else if (es == 4) {
+        ((float*)buf)[idx] = (float)v;
+    } else {
+        ((uint16_t*)buf)[idx] = bf16_bits(v);
+    }
+}
+
+double get_elem(const char* buf, int64_t idx, size_t es) {
+    if (es == 8) return ((const double*)buf)[idx];
+    if (es == 4) return (double)((const float*)buf)[idx];
+    return (double)bf16_to_float(((const uint16_t*)buf)[idx]);
 }
 
 struct ChunkResult {
@@ -389,14 +428,15 @@ void run_chunk(hodlr_t h, std::vector<AcaJob>& jobs, bool lds, size_t lds_bytes,
         int64_t* ou = (int64_t*)dalloc(h, sizeof(int64_t) * nk);
         int64_t* ov = (int64_t*)dalloc(h, sizeof(int64_t) * nk);
         const size_t es = storage_size(h->opts.storage);
-        k_sizes<<<nblk(nk, 256), 256, 0, s>>>(djobs, dr, nk, (int)(16 / es), su, sv);
+        k_sizes<<<nblk(nk, 256), 256, 0, s>>>(djobs, dr, nk, (int)(16 / es), es == 2 ? 1 : 0,
+                                               su, sv);
         HIP_CHECK(hipGetLastError());
         exclusive_scan_i64(su, ou, nk, s);
         exclusive_scan_i64(sv, ov, nk, s);
         int64_t tu = 0, tv = 0;
         for (int64_t t = 0; t < nk; ++t) {
-            tu += padded((int64_t)okr[t] * ok[t].m, es);
-            tv += padded((int64_t)okr[t] * ok[t].n, es);
+            tu += padded((int64_t)okr[t] * term_stride(ok[t].m, es), es);
+            tv += padded((int64_t)okr[t] * term_stride(ok[t].n, es), es);
         }
         // 16 bytes of slack: kernels may read whole 16-byte words at the end
         char* arena = (char*)dalloc(h, es * (size_t)(tu + tv) + 16);
@@ -404,6 +444,9 @@ void run_chunk(hodlr_t h, std::vector<AcaJob>& jobs, bool lds, size_t lds_bytes,
         if (h->opts.storage == HODLR_FP32)
             k_pack<float><<<(unsigned)nk, 256, 0, s>>>(djobs, ws, dr, ou, ov, (float*)arena,
                                                        (float*)arena + tu, h->blocks);
+        else if (h->opts.storage == HODLR_BF16)
+            k_pack<bf16><<<(unsigned)nk, 256, 0, s>>>(djobs, ws, dr, ou, ov, (bf16*)arena,
+                                                      (bf16*)arena + tu, h->blocks);
         else
             k_pack<double><<<(unsigned)nk, 256, 0, s>>>(djobs, ws, dr, ou, ov, (double*)arena,
                                                         (double*)arena + tu, h->blocks);
@@ -421,6 +464,12 @@ void run_chunk(hodlr_t h, std::vector<AcaJob>& jobs, bool lds, size_t lds_bytes,
 }
 
 }  // namespace
+
+// progress lines on stderr when HODLR_VERBOSE is set (long builds)
+bool verbose() {
+    static const bool v = std::getenv("HODLR_VERBOSE") != nullptr;
+    return v;
+}
 
 void compress_all(hodlr_t h, hipStream_t s) {
     int dev_lds = 0;
@@ -462,6 +511,8 @@ void compress_all(hodlr_t h, hipStream_t s) {
             chunk.push_back(lds_jobs[i++]);
         }
         run_chunk(h, chunk, true, lmax, rk, ov, s);
+        if (verbose())
+            std::fprintf(stderr, "[hodlr] ACA (LDS) %zu / %zu blocks\n", i, lds_jobs.size());
     }
     // workspace blocks: a first pass with a modest rank cap, retries with more room
     while (!glob_jobs.empty()) {
@@ -475,6 +526,9 @@ void compress_all(hodlr_t h, hipStream_t s) {
                 chunk.push_back(glob_jobs[i++]);
             }
             run_chunk(h, chunk, false, 0, rk, ov, s);
+            if (verbose())
+                std::fprintf(stderr, "[hodlr] ACA (workspace, rank cap %d) %zu / %zu blocks\n",
+                             chunk.empty() ? 0 : chunk[0].cap, i, glob_jobs.size());
             for (size_t t = 0; t < chunk.size(); ++t)
                 if (ov[t]) {
                     AcaJob j = chunk[t];
@@ -566,8 +620,8 @@ void import_level(hodlr_t h, int level, const int32_t* ranks, const double* U, c
             if (ranks[e] < 0 || ranks[e] > std::min(m, n))
                 fail(HODLR_EINVAL, "imported rank out of range");
             if ((c.eref[e] & 1) == 0) {
-                tu += padded(ranks[e] * m, es);
-                tv += padded(ranks[e] * n, es);
+                tu += padded(ranks[e] * term_stride(m, es), es);
+                tv += padded(ranks[e] * term_stride(n, es), es);
             }
         }
     if ((tu + tv) > 0 && (!U || !V)) fail(HODLR_EINVAL, "factor arrays missing");
@@ -585,20 +639,15 @@ void import_level(hodlr_t h, int level, const int32_t* ranks, const double* U, c
                 bd.rank = (int32_t)r;
                 bd.U = reinterpret_cast<uint64_t>(arena + es * pu);
                 bd.V = reinterpret_cast<uint64_t>(arena + es * (tu + pv));
-                for (int64_t t = 0; t < r * m; ++t) {
-                    if (es == 4)
-                        ((float*)hbuf.data())[pu + t] = (float)U[ou + t];
-                    else
-                        ((double*)hbuf.data())[pu + t] = U[ou + t];
-                }
-                for (int64_t t = 0; t < r * n; ++t) {
-                    if (es == 4)
-                        ((float*)hbuf.data())[tu + pv + t] = (float)V[ov + t];
-                    else
-                        ((double*)hbuf.data())[tu + pv + t] = V[ov + t];
-                }
-                pu += padded(r * m, es);
-                pv += padded(r * n, es);
+                const int64_t lu = term_stride(m, es), lv = term_stride(n, es);
+                for (int64_t k = 0; k < r; ++k)
+                    for (int64_t i = 0; i < m; ++i)
+                        put_elem(hbuf.data(), pu + k * lu + i, es, U[ou + k * m + i]);
+                for (int64_t k = 0; k < r; ++k)
+                    for (int64_t j = 0; j < n; ++j)
+                        put_elem(hbuf.data(), tu + pv + k * lv + j, es, V[ov + k * n + j]);
+                pu += padded(r * lu, es);
+                pv += padded(r * lv, es);
             }
             ou += r * m;
             ov += r * n;
@@ -634,19 +683,22 @@ void export_level(hodlr_t h, int level, int32_t* ranks, int64_t* u_elems, int64_
             // a transposed entry's U is the stored V and its V the stored U
             const uint64_t srcU = tr ? bd.V : bd.U;
             const uint64_t srcV = tr ? bd.U : bd.V;
+            // the factor with |A| rows has term stride term_stride(|A|) in either
+            // orientation (a transposed entry's U is the stored V of (B,A))
+            const int64_t su = term_stride(m, es), sv = term_stride(n, es);
             if (U && r * m) {
-                tmp.resize(es * r * m);
-                HIP_CHECK(hipMemcpy(tmp.data(), reinterpret_cast<void*>(srcU), es * r * m,
+                tmp.resize(es * r * su);
+                HIP_CHECK(hipMemcpy(tmp.data(), reinterpret_cast<void*>(srcU), es * r * su,
                                     hipMemcpyDeviceToHost));
-                for (int64_t t = 0; t < r * m; ++t)
-                    U[ou + t] = es == 4 ? (double)((float*)tmp.data())[t] : ((double*)tmp.data())[t];
+                for (int64_t k = 0; k < r; ++k)
+                    for (int64_t i = 0; i < m; ++i) U[ou + k * m + i] = get_elem(tmp.data(), k * su + i, es);
             }
             if (V && r * n) {
-                tmp.resize(es * r * n);
-                HIP_CHECK(hipMemcpy(tmp.data(), reinterpret_cast<void*>(srcV), es * r * n,
+                tmp.resize(es * r * sv);
+                HIP_CHECK(hipMemcpy(tmp.data(), reinterpret_cast<void*>(srcV), es * r * sv,
                                     hipMemcpyDeviceToHost));
-                for (int64_t t = 0; t < r * n; ++t)
-                    V[ov + t] = es == 4 ? (double)((float*)tmp.data())[t] : ((double*)tmp.data())[t];
+                for (int64_t k = 0; k < r; ++k)
+                    for (int64_t j = 0; j < n; ++j) V[ov + k * n + j] = get_elem(tmp.data(), k * sv + j, es);
             }
             ou += r * m;
             ov += r * n;

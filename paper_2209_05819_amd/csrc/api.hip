@@ -99,9 +99,8 @@ hodlr_status hodlr_build(const double* points, int64_t N, int d, const hodlr_ker
     hodlr_default_opts(&o);
     if (opts) o = *opts;
     if (o.level_rule != 0 && o.level_rule != 1) return set_error(HODLR_EINVAL, "bad level_rule");
-    if (o.storage != HODLR_FP64 && o.storage != HODLR_FP32)
-        return set_error(o.storage == HODLR_BF16 ? HODLR_EUNSUPPORTED : HODLR_EINVAL,
-                         "storage must be FP64 or FP32");
+    if (o.storage != HODLR_FP64 && o.storage != HODLR_FP32 && o.storage != HODLR_BF16)
+        return set_error(HODLR_EINVAL, "storage must be FP64, FP32 or BF16");
     if (o.has_domain && !(o.domain_side > 0.0 && std::isfinite(o.domain_side)))
         return set_error(HODLR_EINVAL, "domain_side must be > 0");
     if (o.max_rank < 0) return set_error(HODLR_EINVAL, "max_rank must be >= 0");
@@ -159,6 +158,8 @@ hodlr_status matvec_checked(hodlr_t h, const void* X, int64_t ldx, int nrhs, int
         return set_error(HODLR_EINVAL, "x_prec must be FP64 or FP32");
     if (compute_prec != HODLR_FP64 && compute_prec != HODLR_FP32)
         return set_error(HODLR_EINVAL, "compute_prec must be FP64 or FP32");
+    if (h->opts.storage == HODLR_BF16 && compute_prec != HODLR_FP32)
+        return set_error(HODLR_EINVAL, "BF16 factors are applied in FP32 arithmetic");
     if (events && nevents != 5 && nevents != 5 + hodlr::kApplyClasses)
         return set_error(HODLR_EINVAL, "events must hold 5 or 11 entries");
     for (int l = 1; l <= h->kappa; ++l)
@@ -223,6 +224,15 @@ hodlr_status hodlr_get_info(hodlr_t h, hodlr_info* info) {
     }
     info->split_blocks = h->split_blocks;
     info->split_factor_elems = h->split_felems;
+    if (h->opts.storage == HODLR_BF16) {
+        for (int c = 0; c < 4; ++c) {
+            info->mfma_proj_jobs[c] = h->mjob_count[c];
+            info->mfma_proj_factor_elems[c] = h->mjob_felems[c];
+            info->mfma_proj_vector_elems[c] = h->mjob_velems[c];
+        }
+        info->mfma_expand_factor_elems = h->mexp_felems;
+        info->mfma_proj_elems = h->mt_total;
+    }
     info->near_entries = h->near_nnz;
     info->near_pairs = h->near_pairs;
     info->device_bytes = h->device_bytes;

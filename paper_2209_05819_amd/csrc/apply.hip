@@ -15,6 +15,7 @@
 // Each output is produced by one lane in a fixed order: results are bitwise
 // reproducible and no floating-point atomics are used.
 #include <algorithm>
+#include <type_traits>
 
 #include "hodlr_impl.hpp"
 
@@ -102,6 +103,7 @@ __global__ __launch_bounds__(64) void k_lr_fused(const BlockDesc* __restrict__ b
     const gptr_t<S> V = as_global<S>(b.V);
     const int nc = min(NR, nrhs - c0);
     const int r = b.rank, m = b.m, n = b.n;
+    const int64_t lu = fstride<S>(m), lv = fstride<S>(n);
     const C* __restrict__ xA = x + (int64_t)c0 * N + b.a0;
     const C* __restrict__ xB = x + (int64_t)c0 * N + b.b0;
     for (int kc = 0; kc == 0 || kc < r; kc += RMAX) {
@@ -120,7 +122,7 @@ __global__ __launch_bounds__(64) void k_lr_fused(const BlockDesc* __restrict__ b
 #pragma unroll
                 for (int kk = 0; kk < K; ++kk)
                     if (kk < kr) {
-                        const C v = (C)V[(int64_t)(kc + k0 + kk) * n + j];
+                        const C v = ldf<C>(V, (int64_t)(kc + k0 + kk) * lv + j);
 #pragma unroll
                         for (int c = 0; c < NR; ++c) pv[c][kk] += v * xv[c];
                     }
@@ -133,7 +135,7 @@ __global__ __launch_bounds__(64) void k_lr_fused(const BlockDesc* __restrict__ b
 #pragma unroll
                     for (int kk = 0; kk < K; ++kk)
                         if (kk < kr) {
-                            const C u = (C)U[(int64_t)(kc + k0 + kk) * m + i];
+                            const C u = ldf<C>(U, (int64_t)(kc + k0 + kk) * lu + i);
 #pragma unroll
                             for (int c = 0; c < NR; ++c) pu[c][kk] += u * xu[c];
                         }
@@ -160,7 +162,7 @@ __global__ __launch_bounds__(64) void k_lr_fused(const BlockDesc* __restrict__ b
                 acc[c] = (kc > 0 && c < nc) ? contrib[(int64_t)c * CT + b.cfwd + i] : (C)0;
 #pragma unroll 4
             for (int k = 0; k < rc; ++k) {
-                const C u = (C)U[(int64_t)(kc + k) * m + i];
+                const C u = ldf<C>(U, (int64_t)(kc + k) * lu + i);
 #pragma unroll
                 for (int c = 0; c < NR; ++c) acc[c] += u * tw[k][c];
             }
@@ -174,7 +176,7 @@ __global__ __launch_bounds__(64) void k_lr_fused(const BlockDesc* __restrict__ b
                     acc[c] = (kc > 0 && c < nc) ? contrib[(int64_t)c * CT + b.cbwd + j] : (C)0;
 #pragma unroll 4
                 for (int k = 0; k < rc; ++k) {
-                    const C v = (C)V[(int64_t)(kc + k) * n + j];
+                    const C v = ldf<C>(V, (int64_t)(kc + k) * lv + j);
 #pragma unroll
                     for (int c = 0; c < NR; ++c) acc[c] += v * sw[k][c];
                 }
@@ -203,15 +205,16 @@ __device__ __forceinline__ void stream_load(StreamBatch<S, C, W, CH, KB>& bt, gp
                                             gptr_t<S> V, int k0, int r, int m, int n,
                                             int base) {
     const int kr = r - k0;   // may be <= 0: nothing is loaded
-    gptr_t<S> Vk = V + k0 * n;
-    gptr_t<S> Uk = U + k0 * m;
+    const int lu = (int)fstride<S>(m), lv = (int)fstride<S>(n);
+    gptr_t<S> Vk = V + k0 * lv;
+    gptr_t<S> Uk = U + k0 * lu;
 #pragma unroll
     for (int kk = 0; kk < KB; ++kk)
 #pragma unroll
         for (int c = 0; c < CH; ++c) {
             const int i = base + c * 64;
-            bt.v[kk][c] = (kk < kr && i < n) ? (C)Vk[kk * n + i] : (C)0;
-            bt.u[kk][c] = (kk < kr && i < m) ? (C)Uk[kk * m + i] : (C)0;
+            bt.v[kk][c] = (kk < kr && i < n) ? ldf<C>(Vk, kk * lv + i) : (C)0;
+            bt.u[kk][c] = (kk < kr && i < m) ? ldf<C>(Uk, kk * lu + i) : (C)0;
         }
 }
 
@@ -346,10 +349,11 @@ __global__ __launch_bounds__(256) void k_lr_group(const BlockDesc* __restrict__ 
     const gptr_t<S> U = as_global<S>(b.U);
     const gptr_t<S> V = as_global<S>(b.V);
     C u[G], v[G], p[G];
+    const int lu = (int)fstride<S>(m), lv = (int)fstride<S>(n);
 #pragma unroll
     for (int k = 0; k < G; ++k) {
-        u[k] = (k < r && g < m) ? (C)U[(int64_t)k * m + g] : (C)0;
-        v[k] = (k < r && g < n) ? (C)V[(int64_t)k * n + g] : (C)0;
+        u[k] = (k < r && g < m) ? ldf<C>(U, k * lu + g) : (C)0;
+        v[k] = (k < r && g < n) ? ldf<C>(V, k * lv + g) : (C)0;
     }
     const C xa = (valid && g < m) ? x[b.a0 + g] : (C)0;
     const C xb = (valid && g < n) ? x[b.b0 + g] : (C)0;
@@ -370,6 +374,264 @@ __global__ __launch_bounds__(256) void k_lr_group(const BlockDesc* __restrict__ 
     }
     if (valid && g < m) contrib[b.cfwd + g] = ca;
     if (valid && sym && g < n) contrib[b.cbwd + g] = cb;
+}
+
+// ---------------------------------------------------------------------------
+// Matrix-core product of BF16 factors with NRP = 16 CT right-hand sides.
+//
+// Each factor element takes part in two contractions (over the rows of the
+// block in the projection, over the rank in the expansion), so the product
+// runs in two passes that each read every factor once:
+//   pass 1 (k_mproj): per stored block t = V x_B and, when the block also
+//     stands for its transpose, s = U^T x_A, on 16x16x32 BF16 matrix cores;
+//     a workgroup of W waves takes a panel of at most 64 W columns, 64 per
+//     wave, 16 terms at a time, and sums its waves' partials through LDS.
+//     Blocks wider than 512 are projected in several panels whose FP32
+//     partials k_mreduce adds in panel order.  Projections are stored in
+//     BF16 in the operand layout of pass 2.
+//   pass 2 (k_mexp): one wave per 128-row tile of a target box A at a
+//     level accumulates, over A's interaction-list entries in order,
+//     C += F_e t_e (F_e the entry's factor with |A| rows: U of (A,B), or V of
+//     the stored (B,A) whose s it takes) on 16x16x16 BF16 matrix cores, in
+//     FP32 registers, and adds C to the level sum y once.  No per-block
+//     output buffer: a box's result leaves the chip once per level.
+// Pass 2 needs 4 consecutive terms of a row per lane while the factor is
+// stored term by term: each 16-term chunk of the tile is staged in LDS with
+// 16-byte loads and read back transposed.
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef unsigned short u16x8_t __attribute__((ext_vector_type(8)));
+typedef unsigned short u16x4_t __attribute__((ext_vector_type(4)));
+typedef short s16x4_t __attribute__((ext_vector_type(4)));
+typedef float f32x4_t __attribute__((ext_vector_type(4)));
+
+constexpr int MR = 64;        // factor columns per wave in a projection job
+constexpr int MPANEL = 512;   // widest projection panel (8 waves)
+constexpr int MTR = 128;      // rows per expansion tile
+constexpr int MPAD = 8;       // LDS row padding of a staged chunk (elements)
+
+// orders this wave's LDS accesses (a staged chunk is written and read by
+// different lanes of the same wave)
+__device__ __forceinline__ void wave_lds_fence() { asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory"); }
+
+// x in tree order, row-major N x nrp, BF16 (columns c0 .. c0 + nc of X; the
+// remaining columns zero)
+template <typename XT>
+__global__ void k_rows_bf16(const XT* __restrict__ X, int64_t ldx, int c0, int nc, int64_t N,
+                            const int32_t* __restrict__ perm, int nrp, uint16_t* __restrict__ xr) {
+    const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (t >= N * nrp) return;
+    const int64_t p = t / nrp;
+    const int c = (int)(t - p * nrp);
+    xr[t] = c < nc ? bf16_from_float((float)X[(int64_t)(c0 + c) * ldx + perm[p]]) : (uint16_t)0;
+}
+
+template <typename C>
+__global__ void k_fill_zero(C* __restrict__ p, int64_t n) {
+    const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (t < n) p[t] = (C)0;
+}
+
+// index of projection (term k, right-hand side c) in the BF16 projection
+// layout: groups of 4 terms, then the right-hand side, then the term in the
+// group (a pass-2 lane loads 4 consecutive terms of one column as 8 bytes)
+__device__ __forceinline__ int64_t tidx(int64_t base, int k, int c, int nrp) {
+    return base + ((int64_t)(k >> 2) * nrp + c) * 4 + (k & 3);
+}
+
+template <int W, int CT>
+__global__ __launch_bounds__(64 * W) void k_mproj(const MJob* __restrict__ jobs,
+                                                  const uint16_t* __restrict__ xr,
+                                                  uint16_t* __restrict__ tproj,
+                                                  float* __restrict__ part) {
+    constexpr int NRP = 16 * CT;
+    __shared__ f32x4_t red[W > 1 ? W : 1][CT][64];
+    const MJob J = jobs[blockIdx.x];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int a = lane & 15, q = lane >> 4;
+    const int64_t ld = fstride<bf16>(J.len);
+    const int col0 = J.p0 + wv * MR;
+    const int cend = J.p0 + J.plen;
+    // x operand (K = factor column, N = right-hand side): lane holds columns
+    // col0 + 32 kt + 8 q + e (e < 8) of right-hand side 16 ct + a
+    bf16x8_t xs[2][CT];
+#pragma unroll
+    for (int kt = 0; kt < 2; ++kt)
+#pragma unroll
+        for (int ct = 0; ct < CT; ++ct) {
+            u16x8_t u;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const int j = col0 + 32 * kt + 8 * q + e;
+                u[e] = j < cend ? xr[(int64_t)(J.x0 + j) * NRP + 16 * ct + a] : (uint16_t)0;
+            }
+            xs[kt][ct] = __builtin_bit_cast(bf16x8_t, u);
+        }
+    // factor words of a 16-term chunk: lane holds term k0 + a, columns
+    // col0 + 32 kt + 8 q .. + 7; the next chunk's are loaded in advance
+    auto load_chunk = [&](int k0, u32x4 (&w)[2]) {
+        const int k = k0 + a;
+#pragma unroll
+        for (int kt = 0; kt < 2; ++kt) {
+            const int c8 = col0 + 32 * kt + 8 * q;
+            w[kt] = u32x4{0u, 0u, 0u, 0u};
+            if (k < J.r && c8 < cend) w[kt] = *as_global<u32x4>(J.F + 2 * ((int64_t)k * ld + c8));
+        }
+    };
+    u32x4 wc[2];
+    load_chunk(0, wc);
+    for (int k0 = 0; k0 < J.r; k0 += 16) {
+        u32x4 wn[2];
+        load_chunk(k0 + 16, wn);
+        f32x4_t t[CT];
+#pragma unroll
+        for (int ct = 0; ct < CT; ++ct) t[ct] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int kt = 0; kt < 2; ++kt) {
+            const bf16x8_t fv = __builtin_bit_cast(bf16x8_t, wc[kt]);
+#pragma unroll
+            for (int ct = 0; ct < CT; ++ct)
+                t[ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fv, xs[kt][ct], t[ct], 0, 0, 0);
+        }
+        wc[0] = wn[0];
+        wc[1] = wn[1];
+        if (W > 1) {
+#pragma unroll
+            for (int ct = 0; ct < CT; ++ct) red[wv][ct][lane] = t[ct];
+            __syncthreads();
+            if (wv == 0)
+#pragma unroll
+                for (int ct = 0; ct < CT; ++ct) {
+                    f32x4_t v = red[0][ct][lane];
+#pragma unroll
+                    for (int w2 = 1; w2 < W; ++w2) v += red[w2][ct][lane];
+                    t[ct] = v;
+                }
+            __syncthreads();
+        }
+        if (wv == 0) {
+            // lane (a, q) holds t[term k0 + 4 q + e][rhs 16 ct + a]
+#pragma unroll
+            for (int ct = 0; ct < CT; ++ct) {
+                if (J.fin) {
+                    u16x4_t o;
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) o[e] = bf16_from_float(t[ct][e]);
+                    *reinterpret_cast<u16x4_t*>(tproj + tidx(J.out * NRP, k0 + 4 * q, 16 * ct + a, NRP)) = o;
+                } else {
+#pragma unroll
+                    for (int e = 0; e < 4; ++e)
+                        part[(J.out + k0 + 4 * q + e) * NRP + 16 * ct + a] = t[ct][e];
+                }
+            }
+        }
+    }
+}
+
+// projections of the blocks done in np panels: sum of the panel partials
+// (layout [panel][term][rhs], r16 terms each) in panel order
+__global__ void k_mreduce(const MRed* __restrict__ reds, const float* __restrict__ part, int nrp,
+                          uint16_t* __restrict__ tproj) {
+    const MRed R = reds[blockIdx.x];
+    const int64_t per = (int64_t)R.r16 * nrp;
+    const float* __restrict__ pp = part + R.part * nrp;
+    for (int64_t t = threadIdx.x; t < per; t += blockDim.x) {
+        float v = 0.f;
+        for (int p = 0; p < R.np; ++p) v += pp[p * per + t];
+        const int k = (int)(t / nrp), c = (int)(t - (int64_t)k * nrp);
+        tproj[tidx(R.out * nrp, k, c, nrp)] = bf16_from_float(v);
+    }
+}
+
+template <int CT>
+__global__ __launch_bounds__(64, 4) void k_mexp(const MTile* __restrict__ tiles,
+                                             const MEnt* __restrict__ ents,
+                                             const uint16_t* __restrict__ tproj, int64_t N,
+                                             int nc, float* __restrict__ yl) {
+    constexpr int NRP = 16 * CT;
+    __shared__ __attribute__((aligned(16))) uint16_t stg[16][MTR + MPAD];
+    const MTile T = tiles[blockIdx.x];
+    const int lane = threadIdx.x;
+    const int a = lane & 15, q = lane >> 4;
+    const int64_t ld = fstride<bf16>(T.len);
+    f32x4_t acc[MTR / 16][CT];
+#pragma unroll
+    for (int it = 0; it < MTR / 16; ++it)
+#pragma unroll
+        for (int ct = 0; ct < CT; ++ct) acc[it][ct] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+    // (entry, 16-term chunk) pairs in order; the loads of the next pair are
+    // issued before the current one is multiplied
+    auto load_chunk = [&](const MEnt& E, int k0, u32x4 (&w)[4], s16x4_t (&ta)[CT]) {
+#pragma unroll
+        for (int sI = 0; sI < 4; ++sI) {
+            const int f = lane + 64 * sI, tt = f >> 4, g = f & 15;
+            w[sI] = u32x4{0u, 0u, 0u, 0u};
+            if (k0 + tt < E.r && 8 * g < T.rows)
+                w[sI] = *as_global<u32x4>(E.F + 2 * ((int64_t)(k0 + tt) * ld + T.rowoff + 8 * g));
+        }
+#pragma unroll
+        for (int ct = 0; ct < CT; ++ct)
+            ta[ct] = __builtin_bit_cast(
+                s16x4_t, *reinterpret_cast<const u16x4_t*>(tproj + tidx(E.t * NRP, k0 + 4 * q, 16 * ct + a, NRP)));
+    };
+    int e = 0;
+    MEnt E{};
+    while (e < T.ne && (E = ents[T.e0 + e]).r <= 0) ++e;
+    int k0 = 0;
+    u32x4 w[4];
+    s16x4_t ta[CT];
+    if (e < T.ne) load_chunk(E, k0, w, ta);
+    while (e < T.ne) {
+        int en = e, kn = k0 + 16;
+        MEnt En = E;
+        if (kn >= E.r) {
+            kn = 0;
+            ++en;
+            while (en < T.ne && (En = ents[T.e0 + en]).r <= 0) ++en;
+        }
+        u32x4 wn[4];
+        s16x4_t tn[CT];
+        if (en < T.ne) load_chunk(En, kn, wn, tn);
+        // stage this chunk: 16 terms x 16 groups of 8 rows
+        wave_lds_fence();   // the previous chunk's reads precede these writes
+#pragma unroll
+        for (int sI = 0; sI < 4; ++sI) {
+            const int f = lane + 64 * sI, tt = f >> 4, g = f & 15;
+            *reinterpret_cast<u32x4*>(&stg[tt][8 * g]) = w[sI];
+        }
+        wave_lds_fence();
+#pragma unroll
+        for (int it = 0; it < MTR / 16; ++it) {
+            if (16 * it < T.rows) {
+                s16x4_t up;
+#pragma unroll
+                for (int e2 = 0; e2 < 4; ++e2) up[e2] = (short)stg[4 * q + e2][16 * it + a];
+#pragma unroll
+                for (int ct = 0; ct < CT; ++ct)
+                    acc[it][ct] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ta[ct], up, acc[it][ct], 0, 0, 0);
+            }
+        }
+        if (en >= T.ne) break;
+#pragma unroll
+        for (int sI = 0; sI < 4; ++sI) w[sI] = wn[sI];
+#pragma unroll
+        for (int ct = 0; ct < CT; ++ct) ta[ct] = tn[ct];
+        e = en;
+        k0 = kn;
+        E = En;
+    }
+    // lane (a, q) holds C[row 16 it + a][rhs 16 ct + 4 q + e]
+#pragma unroll
+    for (int it = 0; it < MTR / 16; ++it) {
+        const int i = 16 * it + a;
+        if (i < T.rows)
+#pragma unroll
+            for (int ct = 0; ct < CT; ++ct)
+#pragma unroll
+                for (int e2 = 0; e2 < 4; ++e2) {
+                    const int c = 16 * ct + 4 * q + e2;
+                    if (c < nc) yl[(int64_t)c * N + T.row0 + i] += acc[it][ct][e2];
+                }
+    }
 }
 
 // One term (row of V, column of U) of a large block per workgroup: the 256
@@ -407,14 +669,14 @@ __device__ __forceinline__ void row_dot(gptr_t<S> row, int len,
     for (; j + 3 * TP < len; j += 4 * TP) {
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-            const C v = (C)row[j + u * TP];
+            const C v = ldf<C>(row, j + u * TP);
 #pragma unroll
             for (int c = 0; c < NR; ++c)
                 if (c < nc) a[u][c] += v * xs[(int64_t)c * N + j + u * TP];
         }
     }
     for (; j < len; j += TP) {
-        const C v = (C)row[j];
+        const C v = ldf<C>(row, j);
 #pragma unroll
         for (int c = 0; c < NR; ++c)
             if (c < nc) a[0][c] += v * xs[(int64_t)c * N + j];
@@ -439,10 +701,10 @@ __global__ __launch_bounds__(TP) void k_project(const BlockDesc* __restrict__ bl
     const C* __restrict__ xA = x + (int64_t)c0 * N + b.a0;
     for (int k = it.lo; k < it.lo + it.cnt; ++k) {
         C acc[NR];
-        row_dot<S, C, NR>(Vb + (int64_t)k * b.n, b.n, xB, N, nc, acc);
+        row_dot<S, C, NR>(Vb + (int64_t)k * fstride<S>(b.n), b.n, xB, N, nc, acc);
         wg_reduce_store<C, NR>(acc, red, nc, tb + b.toff + k, TT);
         if (sym) {
-            row_dot<S, C, NR>(Ub + (int64_t)k * b.m, b.m, xA, N, nc, acc);
+            row_dot<S, C, NR>(Ub + (int64_t)k * fstride<S>(b.m), b.m, xA, N, nc, acc);
             wg_reduce_store<C, NR>(acc, red, nc, sb + b.toff + k, TT);
         }
     }
@@ -463,6 +725,7 @@ __global__ __launch_bounds__(TE) void k_expand_split(const BlockDesc* __restrict
     const bool tr = it.level != 0;
     const gptr_t<S> W = as_global<S>(tr ? b.V : b.U);
     const int len = tr ? b.n : b.m;
+    const int64_t ld = fstride<S>(len);
     const C* __restrict__ coef = (tr ? sb : tb) + b.toff;
     const int o = it.lo + lane;
     const bool active = lane < it.cnt;
@@ -472,7 +735,7 @@ __global__ __launch_bounds__(TE) void k_expand_split(const BlockDesc* __restrict
     for (int c = 0; c < NR; ++c) acc[c] = 0;
     if (active) {
         for (int k = wv; k < b.rank; k += TE / 64) {
-            const C w = (C)W[(int64_t)k * len + o];
+            const C w = ldf<C>(W, (int64_t)k * ld + o);
 #pragma unroll
             for (int c = 0; c < NR; ++c) acc[c] += w * coef[(int64_t)c * TT + k];
         }
@@ -505,7 +768,8 @@ __global__ __launch_bounds__(TG) void k_gather_near(
     const NearItem* __restrict__ items, const SegRef* __restrict__ lseg,
     const int2* __restrict__ nrng, int kappa, const double* __restrict__ pts, int64_t N, int d,
     KParams kp, const C* __restrict__ x, const C* __restrict__ contrib, int64_t CT,
-    const int32_t* __restrict__ perm, int nrhs, int c0, XT* __restrict__ Y, int64_t ldy) {
+    const int32_t* __restrict__ perm, int nrhs, int c0, XT* __restrict__ Y, int64_t ldy,
+    const C* __restrict__ ylev) {
     __shared__ C red[TG / 64][NR][64];
     const NearItem it = items[blockIdx.x];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -608,7 +872,13 @@ __global__ __launch_bounds__(TG) void k_gather_near(
             }
         }
     }
-    if (active) {
+    if (active && ylev) {
+        // the low-rank part is already summed per row (columns c0 .. c0+nc)
+        if (sg == 0)
+#pragma unroll
+            for (int c = 0; c < NR; ++c)
+                if (c < nc) acc[c] += ylev[(int64_t)c * N + i];
+    } else if (active) {
         const int64_t off = i - it.leaf0;
         for (int l = 0; l < kappa; ++l) {
             const SegRef sr = lseg[(int64_t)it.leaf * kappa + l];
@@ -632,6 +902,166 @@ __global__ __launch_bounds__(TG) void k_gather_near(
             C v = red[0][c][lane];
             for (int w = 1; w < TG / 64; ++w) v += red[w][c][lane];
             Y[(int64_t)(c0 + c) * ldy + u] = (XT)v;
+        }
+    }
+}
+
+// Near field on matrix cores (BF16 factors, several right-hand sides):
+// y_A += K(A, near(A)) x, K evaluated on the fly in FP32 and rounded to BF16,
+// times x in BF16, FP32 accumulation.  One workgroup of 4 waves per 64-row
+// chunk of a leaf; the sources are staged through LDS 128 at a time
+// (coordinates, and x rows in the operand layout) and each wave multiplies
+// all 64 targets by 32 of them: 4 x CT 16x16x32 products per wave and tile.
+// The waves' partial sums meet in LDS in wave order; the level sums of the
+// low-rank part are added and the rows written to Y in user order.
+constexpr int kNmTile = 128;
+
+template <typename XT, int CT>
+__global__ __launch_bounds__(256) void k_near_mfma(
+    const NearItem* __restrict__ items, const int2* __restrict__ nrng,
+    const double* __restrict__ pts, int64_t N, int d, KParams kp,
+    const uint16_t* __restrict__ xr, const float* __restrict__ ylev,
+    const int32_t* __restrict__ perm, int nc, int c0, XT* __restrict__ Y, int64_t ldy) {
+    constexpr int NRP = 16 * CT;
+    __shared__ int s_pre[kNearTileRanges + 1], s_rs[kNearTileRanges];
+    __shared__ __attribute__((aligned(16))) int s_j[kNmTile];
+    __shared__ __attribute__((aligned(16))) float s_pt[4][kNmTile];
+    __shared__ __attribute__((aligned(16))) uint16_t s_x[kNmTile / 8][NRP][8];
+    __shared__ f32x4_t red[4][4][CT][64];
+    const NearItem it = items[blockIdx.x];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int a = lane & 15, q = lane >> 4;
+    // target coordinates (d <= 4, zero padded): target tile tm, row
+    // it.lo + 16 tm + a
+    float xt[4][4];
+    int ti[4];
+#pragma unroll
+    for (int tm = 0; tm < 4; ++tm) {
+        const int o = 16 * tm + a;
+        ti[tm] = o < it.cnt ? it.lo + o : -1;
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+            xt[tm][c] = (ti[tm] >= 0 && c < d) ? (float)pts[c * N + ti[tm]] : 0.f;
+    }
+    for (int e = threadIdx.x; e < it.nn; e += 256) {
+        const int2 rg = nrng[it.nb0 + e];
+        s_rs[e] = rg.x;
+        s_pre[e] = rg.y - rg.x;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int acc = 0;
+        for (int e = 0; e < it.nn; ++e) {
+            const int len = s_pre[e];
+            s_pre[e] = acc;
+            acc += len;
+        }
+        s_pre[it.nn] = acc;
+    }
+    __syncthreads();
+    const int total = s_pre[it.nn];
+    f32x4_t acc[4][CT];
+#pragma unroll
+    for (int tm = 0; tm < 4; ++tm)
+#pragma unroll
+        for (int ct = 0; ct < CT; ++ct) acc[tm][ct] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+    for (int t0 = 0; t0 < total; t0 += kNmTile) {
+        const int tn = min(kNmTile, total - t0);
+        // stage the tile: source index, coordinates, x rows (zero past tn)
+        for (int sI = threadIdx.x; sI < kNmTile; sI += 256) {
+            int j = -1;
+            if (sI < tn) {
+                const int sidx = t0 + sI;
+                int lo = 0, hi = it.nn - 1;
+                while (lo < hi) {
+                    const int mid = (lo + hi + 1) >> 1;
+                    if (s_pre[mid] <= sidx)
+                        lo = mid;
+                    else
+                        hi = mid - 1;
+                }
+                j = s_rs[lo] + (sidx - s_pre[lo]);
+            }
+            s_j[sI] = j;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) s_pt[c][sI] = (j >= 0 && c < d) ? (float)pts[c * N + j] : 0.f;
+        }
+        __syncthreads();
+        for (int f = threadIdx.x; f < kNmTile * NRP; f += 256) {
+            const int sI = f / NRP, c = f - sI * NRP;
+            const int j = s_j[sI];
+            s_x[sI >> 3][c][sI & 7] = j >= 0 ? xr[(int64_t)j * NRP + c] : (uint16_t)0;
+        }
+        __syncthreads();
+        // this wave: sources 32 wv + 8 q + e of the tile
+        bf16x8_t xb[CT];
+#pragma unroll
+        for (int ct = 0; ct < CT; ++ct)
+            xb[ct] = __builtin_bit_cast(bf16x8_t,
+                                        *reinterpret_cast<const u16x8_t*>(&s_x[4 * wv + q][16 * ct + a][0]));
+        // this lane's 8 sources: indices and coordinates, read once per tile
+        const int sb0 = 32 * wv + 8 * q;
+        int sj[8];
+        float sp[4][8];
+        {
+            const int4 j0 = *reinterpret_cast<const int4*>(&s_j[sb0]);
+            const int4 j1 = *reinterpret_cast<const int4*>(&s_j[sb0 + 4]);
+            sj[0] = j0.x; sj[1] = j0.y; sj[2] = j0.z; sj[3] = j0.w;
+            sj[4] = j1.x; sj[5] = j1.y; sj[6] = j1.z; sj[7] = j1.w;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const float4 p0 = *reinterpret_cast<const float4*>(&s_pt[c][sb0]);
+                const float4 p1 = *reinterpret_cast<const float4*>(&s_pt[c][sb0 + 4]);
+                sp[c][0] = p0.x; sp[c][1] = p0.y; sp[c][2] = p0.z; sp[c][3] = p0.w;
+                sp[c][4] = p1.x; sp[c][5] = p1.y; sp[c][6] = p1.z; sp[c][7] = p1.w;
+            }
+        }
+#pragma unroll
+        for (int tm = 0; tm < 4; ++tm) {
+            u16x8_t kv;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                float r2 = 0.f;
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    const float dx = xt[tm][c] - sp[c][e];
+                    r2 += dx * dx;
+                }
+                float kij = kfun(kp, r2);
+                if (sj[e] == ti[tm]) kij = (float)kp.diag;
+                if (sj[e] < 0 || ti[tm] < 0) kij = 0.f;
+                kv[e] = bf16_from_float(kij);
+            }
+            const bf16x8_t ka = __builtin_bit_cast(bf16x8_t, kv);
+#pragma unroll
+            for (int ct = 0; ct < CT; ++ct)
+                acc[tm][ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ka, xb[ct], acc[tm][ct], 0, 0, 0);
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int tm = 0; tm < 4; ++tm)
+#pragma unroll
+        for (int ct = 0; ct < CT; ++ct) red[wv][tm][ct][lane] = acc[tm][ct];
+    __syncthreads();
+    // wave tm writes target tile tm: lane (a, q) holds rows 16 tm + 4 q + e,
+    // right-hand side 16 ct + a
+    {
+        const int tm = wv;
+#pragma unroll
+        for (int ct = 0; ct < CT; ++ct) {
+            f32x4_t v = red[0][tm][ct][lane];
+#pragma unroll
+            for (int w2 = 1; w2 < 4; ++w2) v += red[w2][tm][ct][lane];
+            const int c = 16 * ct + a;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int o = 16 * tm + 4 * q + e;
+                if (o < it.cnt && c < nc) {
+                    const int64_t i = it.lo + o;
+                    Y[(int64_t)(c0 + c) * ldy + perm[i]] = (XT)(v[e] + ylev[(int64_t)c * N + i]);
+                }
+            }
         }
     }
 }
@@ -731,6 +1161,9 @@ void plan_apply(hodlr_t h) {
         HIP_CHECK(hipMemcpy(ncol.data(), h->near_col, sizeof(int32_t) * h->near_nnz,
                             hipMemcpyDeviceToHost));
     std::vector<NearItem> nr;
+    h->near_max_ranges = 0;
+    for (int64_t A = 0; A < nleaf; ++A)
+        h->near_max_ranges = std::max<int64_t>(h->near_max_ranges, nptr[A + 1] - nptr[A]);
     for (int64_t A = 0; A < nleaf; ++A)
         for (int32_t i = st[A]; i < st[A + 1]; i += 64)
             nr.push_back(NearItem{(int32_t)A, i, std::min(64, st[A + 1] - i), st[A], nptr[A],
@@ -770,12 +1203,112 @@ void plan_apply(hodlr_t h) {
     upload(rng.data(), sizeof(int2) * rng.size(), (void**)&h->near_rng);
     upload(seg.data(), sizeof(SegRef) * seg.size(), (void**)&h->leaf_seg);
     h->nleaf = nleaf;
+    // matrix-core plan for BF16 factors (several right-hand sides)
+    if (h->opts.storage == HODLR_BF16) {
+        const bool sym = h->opts.symmetric != 0;
+        auto r16 = [](int r) { return (int64_t)((r + 15) & ~15); };
+        // projection term offsets: t of every stored block, then s
+        std::vector<int64_t> toff(h->nblocks), soff(h->nblocks);
+        int64_t tt = 0;
+        for (int64_t b = 0; b < h->nblocks; ++b) {
+            toff[b] = tt;
+            tt += r16(h->hblocks[b].rank);
+        }
+        if (sym)
+            for (int64_t b = 0; b < h->nblocks; ++b) {
+                soff[b] = tt;
+                tt += r16(h->hblocks[b].rank);
+            }
+        h->mt_total = tt;
+        std::vector<std::vector<std::pair<int64_t, MJob>>> jobs(4);
+        std::vector<MRed> reds;
+        int64_t pt = 0;
+        for (int c = 0; c < 4; ++c) h->mjob_felems[c] = h->mjob_velems[c] = h->mjob_count[c] = 0;
+        auto wclass = [](int len) { return len <= 64 ? 0 : len <= 128 ? 1 : len <= 256 ? 2 : 3; };
+        auto add_side = [&](uint64_t F, int len, int x0, int r, int64_t out) {
+            const int np = (len + MPANEL - 1) / MPANEL;
+            if (np <= 1) {
+                const int w = wclass(len);
+                jobs[w].push_back({(int64_t)r * len, MJob{F, out, r, len, x0, 0, len, 1}});
+            } else {
+                reds.push_back(MRed{out, pt, (int32_t)r16(r), np});
+                for (int p = 0; p < np; ++p) {
+                    const int p0 = p * MPANEL, pl = std::min(MPANEL, len - p0);
+                    const int w = wclass(pl);
+                    jobs[w].push_back({(int64_t)r * pl,
+                                       MJob{F, pt + p * r16(r), r, len, x0, p0, pl, 0}});
+                }
+                pt += np * r16(r);
+            }
+        };
+        for (int64_t b = 0; b < h->nblocks; ++b) {
+            const BlockDesc& bd = h->hblocks[b];
+            if (bd.rank <= 0) continue;
+            add_side(bd.V, bd.n, bd.b0, bd.rank, toff[b]);
+            if (sym) add_side(bd.U, bd.m, bd.a0, bd.rank, soff[b]);
+        }
+        h->mpart_total = pt;
+        std::vector<MJob> mj;
+        h->mjob_off.assign(5, 0);
+        for (int c = 0; c < 4; ++c) {
+            std::stable_sort(jobs[c].begin(), jobs[c].end(),
+                             [](const auto& a, const auto& b) { return a.first > b.first; });
+            h->mjob_off[c] = (int64_t)mj.size();
+            for (auto& p : jobs[c]) {
+                mj.push_back(p.second);
+                h->mjob_felems[c] += p.first;
+                h->mjob_velems[c] += p.second.plen;
+            }
+            h->mjob_count[c] = (int64_t)jobs[c].size();
+        }
+        h->mjob_off[4] = (int64_t)mj.size();
+        // expansion: per level, every box's interaction-list entries in order
+        // and its 128-row tiles
+        std::vector<MEnt> ents;
+        std::vector<MTile> tiles;
+        h->mtile_off.assign(1, 0);
+        h->mexp_felems = 0;
+        for (int l = 1; l <= kappa; ++l) {
+            LevelData& Lv = h->lev[l];
+            std::vector<int64_t> ptr(Lv.nb + 1), eref(std::max<int64_t>(Lv.nnz, 1));
+            HIP_CHECK(hipMemcpy(ptr.data(), Lv.il_ptr, sizeof(int64_t) * (Lv.nb + 1),
+                                hipMemcpyDeviceToHost));
+            if (Lv.nnz)
+                HIP_CHECK(hipMemcpy(eref.data(), Lv.eref, sizeof(int64_t) * Lv.nnz,
+                                    hipMemcpyDeviceToHost));
+            for (int64_t A = 0; A < Lv.nb; ++A) {
+                const int32_t len = Lv.hstart[A + 1] - Lv.hstart[A];
+                const int64_t e0 = (int64_t)ents.size();
+                for (int64_t e = ptr[A]; e < ptr[A + 1]; ++e) {
+                    const int64_t blk = eref[e] >> 1;
+                    const BlockDesc& bd = h->hblocks[blk];
+                    if (eref[e] & 1)
+                        ents.push_back(MEnt{bd.V, soff[blk], bd.rank, 0});
+                    else
+                        ents.push_back(MEnt{bd.U, toff[blk], bd.rank, 0});
+                    h->mexp_felems += (int64_t)std::max(bd.rank, 0) * len;
+                }
+                const int32_t ne = (int32_t)((int64_t)ents.size() - e0);
+                for (int32_t r0 = 0; r0 < len; r0 += MTR)
+                    tiles.push_back(MTile{Lv.hstart[A] + r0, std::min(MTR, len - r0), len, r0, e0,
+                                          ne, 0});
+            }
+            h->mtile_off.push_back((int64_t)tiles.size());
+        }
+        upload(mj.data(), sizeof(MJob) * mj.size(), (void**)&h->mjobs);
+        upload(reds.data(), sizeof(MRed) * reds.size(), (void**)&h->mreds);
+        h->n_mreds = (int64_t)reds.size();
+        upload(ents.data(), sizeof(MEnt) * ents.size(), (void**)&h->ments);
+        upload(tiles.data(), sizeof(MTile) * tiles.size(), (void**)&h->mtiles);
+    }
     if (h->nblocks)
         HIP_CHECK(hipMemcpy(h->blocks, h->hblocks.data(), sizeof(BlockDesc) * h->nblocks,
                             hipMemcpyHostToDevice));
 }
 
 namespace {
+
+inline size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
 template <typename XT, typename S, typename C, int NR>
 void run_matvec(hodlr_t h, const XT* X, int64_t ldx, int nrhs, XT* Y, int64_t ldy, char* ws,
@@ -794,7 +1327,66 @@ void run_matvec(hodlr_t h, const XT* X, int64_t ldx, int nrhs, XT* Y, int64_t ld
     if (ev) HIP_CHECK(hipEventRecord(ev[1], s));
     // the contribution buffer holds NR columns: stages repeat per column batch
     constexpr int RMAX = kFusedMaxRank;
+    constexpr bool kMfma = std::is_same<S, bf16>::value && NR >= 16;
     for (int c0 = 0; c0 < nrhs; c0 += NR) {
+        if constexpr (kMfma) {
+            const int nc = std::min(NR, nrhs - c0);
+            constexpr int CTn = NR / 16;
+            // workspace after x: x rows (BF16), level sums, projections, partials
+            char* p = ws + align256(sizeof(C) * (size_t)N * nrhs);
+            uint16_t* xr = reinterpret_cast<uint16_t*>(p);
+            p += align256(2 * (size_t)N * NR);
+            float* yl = reinterpret_cast<float*>(p);
+            p += align256(4 * (size_t)N * NR);
+            uint16_t* tproj = reinterpret_cast<uint16_t*>(p);
+            p += align256(2 * (size_t)std::max<int64_t>(h->mt_total, 1) * NR);
+            float* part = reinterpret_cast<float*>(p);
+            k_rows_bf16<XT><<<nblk(N * NR, 256), 256, 0, s>>>(X, ldx, c0, nc, N, h->perm, NR, xr);
+            k_fill_zero<float><<<nblk(N * NR, 256), 256, 0, s>>>(yl, N * NR);
+            HIP_CHECK(hipGetLastError());
+            // pass 1: projections, by workgroup width
+            for (int w = 0; w < 4; ++w) {
+                const int64_t n0 = h->mjob_off[w], cnt = h->mjob_off[w + 1] - n0;
+                if (cnt) {
+                    const MJob* jb = h->mjobs + n0;
+                    const unsigned g = (unsigned)cnt;
+                    switch (w) {
+                    case 0: k_mproj<1, CTn><<<g, 64, 0, s>>>(jb, xr, tproj, part); break;
+                    case 1: k_mproj<2, CTn><<<g, 128, 0, s>>>(jb, xr, tproj, part); break;
+                    case 2: k_mproj<4, CTn><<<g, 256, 0, s>>>(jb, xr, tproj, part); break;
+                    default: k_mproj<8, CTn><<<g, 512, 0, s>>>(jb, xr, tproj, part); break;
+                    }
+                    HIP_CHECK(hipGetLastError());
+                }
+                if (ev && nev > 5 && c0 == 0) HIP_CHECK(hipEventRecord(ev[5 + w], s));
+            }
+            if (h->n_mreds)
+                k_mreduce<<<(unsigned)h->n_mreds, 256, 0, s>>>(h->mreds, part, NR, tproj);
+            HIP_CHECK(hipGetLastError());
+            if (ev && nev > 5 && c0 == 0)
+                for (int c = 4; c < kNumClasses; ++c) HIP_CHECK(hipEventRecord(ev[5 + c], s));
+            if (ev && c0 == 0) HIP_CHECK(hipEventRecord(ev[2], s));
+            // pass 2: expansions, one level at a time (tiles of a level own
+            // disjoint rows of the level sum)
+            for (int l = 1; l <= h->kappa; ++l) {
+                const int64_t t0 = h->mtile_off[l - 1], cnt = h->mtile_off[l] - t0;
+                if (cnt)
+                    k_mexp<CTn><<<(unsigned)cnt, 64, 0, s>>>(h->mtiles + t0, h->ments, tproj, N, nc,
+                                                             yl);
+                HIP_CHECK(hipGetLastError());
+            }
+            if (ev && c0 == 0) HIP_CHECK(hipEventRecord(ev[3], s));
+            if (h->near_max_ranges <= kNearTileRanges && h->d <= 4)
+                k_near_mfma<XT, CTn><<<(unsigned)h->n_near_items, 256, 0, s>>>(
+                    h->near_items, h->near_rng, h->pts, N, h->d, h->kp, xr, yl, h->perm, nc, c0, Y,
+                    ldy);
+            else
+                k_gather_near<XT, C, NR><<<(unsigned)h->n_near_items, TG, 0, s>>>(
+                    h->near_items, h->leaf_seg, h->near_rng, h->kappa, h->pts, N, h->d, h->kp, x,
+                    contrib, CT, h->perm, nrhs, c0, Y, ldy, yl);
+            HIP_CHECK(hipGetLastError());
+            continue;
+        } else {
         if (NR == 1) {
             // one launch per size class
             for (int c = 0; c < kNumClasses; ++c) {
@@ -845,9 +1437,10 @@ void run_matvec(hodlr_t h, const XT* X, int64_t ldx, int nrhs, XT* Y, int64_t ld
                 h->blocks, h->exp_items, nrhs, c0, TT, tb, sb, CT, contrib);
         HIP_CHECK(hipGetLastError());
         if (ev && c0 == 0) HIP_CHECK(hipEventRecord(ev[3], s));
+        }
         k_gather_near<XT, C, NR><<<(unsigned)h->n_near_items, TG, 0, s>>>(
             h->near_items, h->leaf_seg, h->near_rng, h->kappa, h->pts, N, h->d, h->kp, x,
-            contrib, CT, h->perm, nrhs, c0, Y, ldy);
+            contrib, CT, h->perm, nrhs, c0, Y, ldy, nullptr);
         HIP_CHECK(hipGetLastError());
     }
     if (ev) HIP_CHECK(hipEventRecord(ev[4], s));
@@ -856,6 +1449,16 @@ void run_matvec(hodlr_t h, const XT* X, int64_t ldx, int nrhs, XT* Y, int64_t ld
 template <typename XT, typename S, typename C>
 void dispatch_nr(hodlr_t h, const XT* X, int64_t ldx, int nrhs, XT* Y, int64_t ldy, char* ws,
                  hipEvent_t const* ev, int nev, hipStream_t s) {
+    if constexpr (std::is_same<S, bf16>::value) {
+        // BF16 factors: matrix cores for several right-hand sides
+        if (nrhs == 1)
+            run_matvec<XT, S, C, 1>(h, X, ldx, nrhs, Y, ldy, ws, ev, nev, s);
+        else if (nrhs <= 16)
+            run_matvec<XT, S, C, 16>(h, X, ldx, nrhs, Y, ldy, ws, ev, nev, s);
+        else
+            run_matvec<XT, S, C, 32>(h, X, ldx, nrhs, Y, ldy, ws, ev, nev, s);
+        return;
+    }
     if (nrhs == 1)
         run_matvec<XT, S, C, 1>(h, X, ldx, nrhs, Y, ldy, ws, ev, nev, s);
     else if (nrhs <= 4)
@@ -872,8 +1475,15 @@ void matvec(hodlr_t h, const void* X, int64_t ldx, int nrhs, int x_prec, void* Y
     const size_t cs = compute_prec == HODLR_FP32 ? 4 : 8;
     const int64_t TT = std::max<int64_t>(h->t_total, 1);
     const int64_t CT = std::max<int64_t>(h->contrib_total, 1);
-    const int nr = nrhs == 1 ? 1 : (nrhs <= 4 ? 4 : 8);
-    const size_t need = cs * ((size_t)N * nrhs + (size_t)CT * nr + 2 * (size_t)TT * nr) + 4096;
+    const bool b16 = h->opts.storage == HODLR_BF16;
+    const int nr = nrhs == 1 ? 1 : b16 ? (nrhs <= 16 ? 16 : 32) : (nrhs <= 4 ? 4 : 8);
+    size_t need;
+    if (b16 && nr >= 16)   // x, x rows, level sums, projections, panel partials
+        need = align256(cs * (size_t)N * nrhs) + align256(2 * (size_t)N * nr) + align256(4 * (size_t)N * nr) +
+               align256(2 * (size_t)std::max<int64_t>(h->mt_total, 1) * nr) +
+               4 * (size_t)std::max<int64_t>(h->mpart_total, 1) * nr + 4096;
+    else
+        need = cs * ((size_t)N * nrhs + (size_t)CT * nr + 2 * (size_t)TT * nr) + 4096;
     if (h->ws_bytes < need) {
         if (h->ws) {
             HIP_CHECK(hipStreamSynchronize(s));
@@ -887,6 +1497,16 @@ void matvec(hodlr_t h, const void* X, int64_t ldx, int nrhs, int x_prec, void* Y
     char* ws = (char*)h->ws;
     const bool s32 = h->opts.storage == HODLR_FP32;
     const bool c32 = compute_prec == HODLR_FP32;
+    if (b16) {
+        // BF16 factors are applied in FP32 (checked by the caller)
+        if (x_prec == HODLR_FP64)
+            dispatch_nr<double, bf16, float>(h, (const double*)X, ldx, nrhs, (double*)Y, ldy, ws,
+                                             ev, nev, s);
+        else
+            dispatch_nr<float, bf16, float>(h, (const float*)X, ldx, nrhs, (float*)Y, ldy, ws, ev,
+                                            nev, s);
+        return;
+    }
     if (x_prec == HODLR_FP64) {
         const double* Xd = (const double*)X;
         double* Yd = (double*)Y;

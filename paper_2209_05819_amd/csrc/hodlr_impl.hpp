@@ -82,9 +82,56 @@ __device__ __forceinline__ gptr_t<T> as_global(uint64_t a) {
     return (gptr_t<T>)a;
 }
 
+// BF16 factor storage: the upper 16 bits of an IEEE binary32, rounded to
+// nearest even.  A distinct type so that loads convert by bit pattern.
+enum class bf16 : uint16_t {};
+
+__host__ __device__ inline uint16_t bf16_from_float(float f) {
+    uint32_t u;
+    __builtin_memcpy(&u, &f, 4);
+    if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)((u >> 16) | ((u & 0xffffu) ? 0x40u : 0u));
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+// FP64 -> BF16 through FP32 (both round to nearest even; the double rounding
+// differs from a direct rounding only on exact BF16 ties after the first)
+__host__ __device__ inline uint16_t bf16_bits(double v) { return bf16_from_float((float)v); }
+
+__host__ __device__ inline float bf16_to_float(uint16_t b) {
+    const uint32_t u = (uint32_t)b << 16;
+    float f;
+    __builtin_memcpy(&f, &u, 4);
+    return f;
+}
+
+// Elements between consecutive rank terms of a stored factor of length
+// `len` (U: |A| per column, V: |B| per row).  BF16 terms are padded with
+// zeros to a multiple of 8 elements, so every term starts 16-byte aligned
+// and matrix-core operands load as whole 16-byte words.
+template <typename S>
+__host__ __device__ constexpr int64_t fstride(int64_t len) {
+    return len;
+}
+template <>
+__host__ __device__ constexpr int64_t fstride<bf16>(int64_t len) {
+    return (len + 7) & ~(int64_t)7;
+}
+
+// factor element i of a stored factor, converted to the compute type
+template <typename C, typename S>
+__device__ __forceinline__ C ldf(gptr_t<S> p, int64_t i) {
+    return (C)p[i];
+}
+template <typename C>
+__device__ __forceinline__ C ldf(gptr_t<bf16> p, int64_t i) {
+    return (C)bf16_to_float((uint16_t)p[i]);
+}
+
 // One stored low-rank block: rows = box A (|A| = m, tree offset a0),
 // columns = box B (|B| = n, tree offset b0).  U is m x r column by column,
-// V is r x n row by row, both in the storage type at byte addresses U, V.
+// V is r x n row by row, both in the storage type at byte addresses U, V,
+// consecutive terms fstride<S>(m) resp. fstride<S>(n) elements apart.
 struct BlockDesc {
     int32_t a0, m, b0, n;
     int32_t rank, level;
@@ -121,6 +168,33 @@ struct LevelData {
     int64_t blk0 = 0, nblk = 0;  // range in the global block table
     std::vector<int32_t> hstart; // host copy of start
     bool has_factors = false;
+};
+
+// Matrix-core product records (BF16 factors).  A projection job computes
+// t = F x over the panel [p0, p0 + plen) of the factor's columns for all
+// its terms: F = V (t = V x_B) or F = U (s = U^T x_A).
+struct MJob {
+    uint64_t F;
+    int64_t out;        // fin: BF16 projection offset; else FP32 partial offset
+    int32_t r, len;     // rank; factor length (term stride fstride<bf16>(len))
+    int32_t x0;         // tree row of the factor's column 0
+    int32_t p0, plen;
+    int32_t fin;        // 1 when the panel is the whole factor
+};
+struct MRed {           // sum of the np panel partials of one projection
+    int64_t out, part;
+    int32_t r16, np;
+};
+struct MEnt {           // an interaction-list entry (A,B) in the expansion:
+    uint64_t F;         // the factor with |A| rows (U, or V of the stored (B,A))
+    int64_t t;          // its projections (t of (A,B), or s of the stored (B,A))
+    int32_t r, pad;
+};
+struct MTile {          // up to 128 rows of a target box A at one level
+    int32_t row0, rows; // tree row of the tile, rows in it
+    int32_t len, rowoff;// |A|, offset of the tile in A
+    int64_t e0;         // entries [e0, e0 + ne) in interaction-list order
+    int32_t ne, pad;
 };
 
 struct WorkItem {   // launch planning record: a block (or box) and a sub-range
@@ -168,8 +242,24 @@ struct hodlr_handle_s {
     int64_t n_exp_items = 0;
     hodlr::NearItem* near_items = nullptr; // 64-row chunks of the leaves
     int64_t n_near_items = 0;
+    int64_t near_max_ranges = 0;           // most near-list boxes of a leaf
     int2* near_rng = nullptr;              // tree-order ranges of the near-list boxes
     hodlr::SegRef* leaf_seg = nullptr;     // [leaf][level-1] contribution segments
+    // matrix-core plan (BF16 factors, several right-hand sides), two passes:
+    // projection jobs by workgroup width W = 1, 2, 4, 8 waves, the reductions
+    // of the blocks projected in several panels, and per level the 128-row
+    // tiles of the target boxes with their interaction-list entries
+    hodlr::MJob* mjobs = nullptr;
+    std::vector<int64_t> mjob_off;          // W class c: [mjob_off[c], mjob_off[c+1])
+    hodlr::MRed* mreds = nullptr;
+    int64_t n_mreds = 0;
+    hodlr::MEnt* ments = nullptr;
+    hodlr::MTile* mtiles = nullptr;
+    std::vector<int64_t> mtile_off;         // level l: [mtile_off[l-1], mtile_off[l])
+    int64_t mt_total = 0;                   // BF16 projection elements per right-hand side
+    int64_t mpart_total = 0;                // FP32 panel partials per right-hand side
+    int64_t mjob_felems[4]{}, mjob_velems[4]{}, mjob_count[4]{};
+    int64_t mexp_felems = 0;
     int64_t contrib_total = 0;             // contribution elements per right-hand side
     int64_t nleaf = 0;
     // matvec workspace

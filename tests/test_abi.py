@@ -37,7 +37,8 @@ def test_struct_layouts_match_header():
     # sizes implied by the C declarations on x86-64
     assert C.sizeof(P.Kernel) == 32
     assert C.sizeof(P.Opts) == 4 * 2 + 8 * 8 + 8 + 4 * 4 + 8
-    assert P.Info.build_ms.offset + 32 == C.sizeof(P.Info)
+    assert P.Info.build_ms.offset + 32 == P.Info.mfma_proj_jobs.offset
+    assert P.Info.mfma_proj_elems.offset + 8 == C.sizeof(P.Info)
 
 
 def test_default_opts_and_errors_without_gpu():

@@ -9,7 +9,9 @@ level, near field evaluated on the fly, permutation back.
 
 Two precisions are timed on the same inputs: FP64 (factors and arithmetic)
 and mixed (FP32 factors, FP32 arithmetic).  `value` is the FP64 throughput;
-the mixed figures are in `mixed`.  Prints one JSON line.
+the mixed figures are in `mixed`.  `multi_rhs` times the matrix-core path on
+its own workload (2^19 points in 4D, 1/r^2, 32 right-hand sides, BF16
+factors).  Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -95,6 +97,65 @@ def measured_traffic(workload, kernel, storage):
     return None
 
 
+def multi_rhs(P, torch, W, steps, warmup, n_override=0):
+    """Several right-hand sides on matrix cores: 2^19 points uniform in
+    [-1,1]^4, 1/r^2, leaf 128, ACA 1e-8, 32 N(0,1) right-hand sides in FP32,
+    BF16 factors, FP32 accumulation.  Error against the direct sum on
+    sampled rows."""
+    import oracle
+    w = W.WORKLOADS["uniform4d_invr2_n524288"]
+    if n_override:
+        w = W.scaled(w, n_override)
+    pts, q = w.points(), w.rhs()
+    N, nrhs = w.N, q.shape[1]
+    kern = P.make_kernel(w.kernel, h=w.h, diag=w.diag)
+    t0 = time.perf_counter()
+    H = P.HODLR(pts, kern, w.leaf, w.tol, domain=w.domain, storage=P.BF16)
+    torch.cuda.synchronize()
+    build = time.perf_counter() - t0
+    info = H.info()
+    print(f"[bench] multi-RHS BF16 build {build:.1f} s kappa={info.kappa}", file=sys.stderr,
+          flush=True)
+    X = torch.tensor(np.ascontiguousarray(q.T), dtype=torch.float32, device="cuda").t()
+    Y = torch.empty((nrhs, N), dtype=torch.float32, device="cuda").t()
+    wall, per, cls, lat = time_matvecs(P, torch, H, X, Y, P.FP32, warmup, steps)
+    st = per.mean(axis=0)
+    y = Y.t().contiguous().cpu().numpy().T
+    oracle.build(force=False)
+    rows = np.sort(W.rng(203).choice(N, size=min(N, 512), replace=False))
+    bd = oracle.direct(pts, oracle.kernel(w.kernel, diag=w.diag), q, rows=rows)
+    err = float(np.linalg.norm(y[rows] - bd) / np.linalg.norm(bd))
+    fe = sum(info.factor_elems[l] for l in range(1, info.kappa + 1))
+    proj_b = 2 * sum(info.mfma_proj_factor_elems)
+    exp_b = 2 * info.mfma_expand_factor_elems
+    # dominant pass: projections (stage 2) or expansions (stage 3); bytes
+    # are the factor elements that pass reads, once
+    if st[2] >= st[1]:
+        kern_name, nb, ms = "k_mexp", exp_b, st[2]
+    else:
+        kern_name, nb, ms = "k_mproj", proj_b, st[1]
+    ach = nb / (ms * 1e-3) / 1e9
+    mfma_tf = 2.0 * 16 * ((nrhs + 15) // 16) * (fe if kern_name == "k_mproj" else
+                                                  info.mfma_expand_factor_elems) / (ms * 1e-3) / 1e12
+    del H
+    return {
+        "workload": w.name, "N": N, "d": w.d, "nrhs": nrhs, "kernel": "1/r^2, diag 0",
+        "leaf": w.leaf, "aca_tol": w.tol, "dtype": "bf16 factors, f32 accumulation",
+        "value": N * nrhs / (wall / steps), "unit": "N*nrhs/s",
+        "ms_per_step": wall / steps * 1e3,
+        "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+        "rel_err": err, "rel_err_ref": "direct sum on 512 sampled rows (seed 203)",
+        "stage_ms": [round(float(v), 4) for v in st],
+        "stages": ["permute_in", "projections (pass 1)", "expansions (pass 2)",
+                   "near_field+permute_out"],
+        "build_s": round(build, 2), "kappa": info.kappa, "factor_bytes": int(2 * fe),
+        "roofline": {"bound": "hbm", "kernel": kern_name, "bytes_per_launch": int(nb),
+                     "avg_ms": float(ms), "achieved": ach, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": ach / HBM_PEAK_GBS, "traffic": None,
+                     "mfma_tflops": mfma_tf, "mfma_peak_tflops": 2500.0},
+    }
+
+
 def factor_bytes(info, elem):
     return sum(info.factor_elems[l] for l in range(1, info.kappa + 1)) * elem
 
@@ -149,6 +210,9 @@ def main():
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--level-rule", type=int, default=1,
                     help="1: depth from the closed form (balanced tree); 0: fullest box rule")
+    ap.add_argument("--no-multi-rhs", action="store_true",
+                    help="skip the 32-RHS BF16 matrix-core workload")
+    ap.add_argument("--multi-rhs-n", type=int, default=0, help="override its N")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain device copy of known size (counter calibration)")
     args = ap.parse_args()
@@ -238,6 +302,10 @@ def main():
     if mixed is not None:
         mixed["rel_err"] = rel_err_rows(y32, bd, rows)
 
+    mrhs = None
+    if not args.no_multi_rhs:
+        mrhs = multi_rhs(P, torch, W, max(3, args.steps // 4), 1, args.multi_rhs_n)
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu, crow, cb = cpu_baseline(w, pts, q, args.level_rule)
@@ -292,6 +360,7 @@ def main():
         "matvec_roofline": {"achieved": matvec_gbs, "frac": matvec_gbs / HBM_PEAK_GBS,
                             "bytes": int(fb64 + vec_bytes)},
         "mixed": mixed,
+        "multi_rhs": mrhs,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))

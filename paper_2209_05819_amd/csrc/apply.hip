@@ -389,8 +389,10 @@ __global__ __launch_bounds__(256) void k_lr_group(const BlockDesc* __restrict__ 
 //     Blocks wider than 512 are projected in several panels whose FP32
 //     partials k_mreduce adds in panel order.  Projections are stored in
 //     BF16 in the operand layout of pass 2.
-//   pass 2 (k_mexp): one wave per 128-row tile of a target box A at a
-//     level accumulates, over A's interaction-list entries in order,
+//   pass 2 (k_mexp): one wave per 16 RT rows of a target box A at a
+//     level (boxes up to 192 rows: one wave; larger ones: workgroups of 4
+//     waves x 128 rows sharing the projections) accumulates, over A's
+//     interaction-list entries in order,
 //     C += F_e t_e (F_e the entry's factor with |A| rows: U of (A,B), or V of
 //     the stored (B,A) whose s it takes) on 16x16x16 BF16 matrix cores, in
 //     FP32 registers, and adds C to the level sum y once.  No per-block
@@ -406,7 +408,8 @@ typedef float f32x4_t __attribute__((ext_vector_type(4)));
 
 constexpr int MR = 64;        // factor columns per wave in a projection job
 constexpr int MPANEL = 512;   // widest projection panel (8 waves)
-constexpr int MTR = 128;      // rows per expansion tile
+constexpr int MSMALL = 192;   // boxes up to this many rows: one wave (12 row tiles)
+constexpr int MBIGW = 4;      // larger boxes: workgroups of 4 waves x 128 rows
 constexpr int MPAD = 8;       // LDS row padding of a staged chunk (elements)
 
 // orders this wave's LDS accesses (a staged chunk is written and read by
@@ -542,44 +545,56 @@ __global__ void k_mreduce(const MRed* __restrict__ reds, const float* __restrict
     }
 }
 
-template <int CT>
-__global__ __launch_bounds__(64, 4) void k_mexp(const MTile* __restrict__ tiles,
-                                             const MEnt* __restrict__ ents,
-                                             const uint16_t* __restrict__ tproj, int64_t N,
-                                             int nc, float* __restrict__ yl) {
+// One workgroup of TW waves per tile of a target box; wave w takes the rows
+// [rowoff + 16 RT w, rowoff + 16 RT (w + 1)) of the tile.  With TW > 1 the
+// projection chunk every wave multiplies by is loaded once by wave 0 and
+// shared through LDS (one barrier per chunk, two buffers).
+template <int CT, int RT, int TW>
+__global__ __launch_bounds__(64 * TW, RT > 8 ? 2 : 4) void k_mexp(
+    const MTile* __restrict__ tiles, const MEnt* __restrict__ ents,
+    const uint16_t* __restrict__ tproj, int64_t N, int nc, float* __restrict__ yl) {
     constexpr int NRP = 16 * CT;
-    __shared__ __attribute__((aligned(16))) uint16_t stg[16][MTR + MPAD];
+    constexpr int WR = 16 * RT;              // rows per wave
+    constexpr int NWORD = WR / 8 * 16 / 64;  // 16-byte factor words per lane and chunk
+    __shared__ __attribute__((aligned(16))) uint16_t stg[TW][16][WR + MPAD];
+    __shared__ __attribute__((aligned(16))) uint16_t s_t[TW > 1 ? 2 : 1][16 * NRP];
     const MTile T = tiles[blockIdx.x];
-    const int lane = threadIdx.x;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int a = lane & 15, q = lane >> 4;
     const int64_t ld = fstride<bf16>(T.len);
-    f32x4_t acc[MTR / 16][CT];
+    const int wrow = wv * WR;                       // first row of this wave in the tile
+    const int wrows = min(WR, T.rows - wrow);       // may be <= 0 (idle wave)
+    f32x4_t acc[RT][CT];
 #pragma unroll
-    for (int it = 0; it < MTR / 16; ++it)
+    for (int it = 0; it < RT; ++it)
 #pragma unroll
         for (int ct = 0; ct < CT; ++ct) acc[it][ct] = f32x4_t{0.f, 0.f, 0.f, 0.f};
     // (entry, 16-term chunk) pairs in order; the loads of the next pair are
     // issued before the current one is multiplied
-    auto load_chunk = [&](const MEnt& E, int k0, u32x4 (&w)[4], s16x4_t (&ta)[CT]) {
+    auto load_words = [&](const MEnt& E, int k0, u32x4 (&w)[NWORD]) {
 #pragma unroll
-        for (int sI = 0; sI < 4; ++sI) {
-            const int f = lane + 64 * sI, tt = f >> 4, g = f & 15;
+        for (int sI = 0; sI < NWORD; ++sI) {
+            const int f = lane + 64 * sI, tt = f / (WR / 8), g = f % (WR / 8);
             w[sI] = u32x4{0u, 0u, 0u, 0u};
-            if (k0 + tt < E.r && 8 * g < T.rows)
-                w[sI] = *as_global<u32x4>(E.F + 2 * ((int64_t)(k0 + tt) * ld + T.rowoff + 8 * g));
+            if (k0 + tt < E.r && 8 * g < wrows)
+                w[sI] = *as_global<u32x4>(E.F + 2 * ((int64_t)(k0 + tt) * ld + T.rowoff + wrow + 8 * g));
         }
-#pragma unroll
-        for (int ct = 0; ct < CT; ++ct)
-            ta[ct] = __builtin_bit_cast(
-                s16x4_t, *reinterpret_cast<const u16x4_t*>(tproj + tidx(E.t * NRP, k0 + 4 * q, 16 * ct + a, NRP)));
+    };
+    // the chunk's projections, 16 terms x NRP contiguous (16-byte word per lane)
+    auto load_t = [&](const MEnt& E, int k0, u32x4& tw) {
+        tw = u32x4{0u, 0u, 0u, 0u};
+        if (8 * lane < 16 * NRP)
+            tw = *reinterpret_cast<const u32x4*>(tproj + (E.t + k0) * NRP + 8 * lane);
     };
     int e = 0;
     MEnt E{};
     while (e < T.ne && (E = ents[T.e0 + e]).r <= 0) ++e;
-    int k0 = 0;
-    u32x4 w[4];
-    s16x4_t ta[CT];
-    if (e < T.ne) load_chunk(E, k0, w, ta);
+    int k0 = 0, par = 0;
+    u32x4 w[NWORD], tw;
+    if (e < T.ne) {
+        load_words(E, k0, w);
+        if (TW == 1 || wv == 0) load_t(E, k0, tw);
+    }
     while (e < T.ne) {
         int en = e, kn = k0 + 16;
         MEnt En = E;
@@ -588,23 +603,40 @@ __global__ __launch_bounds__(64, 4) void k_mexp(const MTile* __restrict__ tiles,
             ++en;
             while (en < T.ne && (En = ents[T.e0 + en]).r <= 0) ++en;
         }
-        u32x4 wn[4];
-        s16x4_t tn[CT];
-        if (en < T.ne) load_chunk(En, kn, wn, tn);
-        // stage this chunk: 16 terms x 16 groups of 8 rows
-        wave_lds_fence();   // the previous chunk's reads precede these writes
+        u32x4 wn[NWORD], tn;
+        if (en < T.ne) {
+            load_words(En, kn, wn);
+            if (TW == 1 || wv == 0) load_t(En, kn, tn);
+        }
+        // the projections as the A operand: lane (a, q) takes terms
+        // k0 + 4 q .. + 3 of right-hand side 16 ct + a
+        s16x4_t ta[CT];
+        if (TW == 1) {
+            wave_lds_fence();
+            if (8 * lane < 16 * NRP) *reinterpret_cast<u32x4*>(&s_t[0][8 * lane]) = tw;
+            wave_lds_fence();
+        } else {
+            if (wv == 0 && 8 * lane < 16 * NRP) *reinterpret_cast<u32x4*>(&s_t[par][8 * lane]) = tw;
+            __syncthreads();
+        }
 #pragma unroll
-        for (int sI = 0; sI < 4; ++sI) {
-            const int f = lane + 64 * sI, tt = f >> 4, g = f & 15;
-            *reinterpret_cast<u32x4*>(&stg[tt][8 * g]) = w[sI];
+        for (int ct = 0; ct < CT; ++ct)
+            ta[ct] = __builtin_bit_cast(
+                s16x4_t, *reinterpret_cast<const u16x4_t*>(&s_t[TW > 1 ? par : 0][(q * NRP + 16 * ct + a) * 4]));
+        // stage this chunk of the wave's rows: 16 terms x WR/8 words
+        wave_lds_fence();
+#pragma unroll
+        for (int sI = 0; sI < NWORD; ++sI) {
+            const int f = lane + 64 * sI, tt = f / (WR / 8), g = f % (WR / 8);
+            *reinterpret_cast<u32x4*>(&stg[wv][tt][8 * g]) = w[sI];
         }
         wave_lds_fence();
 #pragma unroll
-        for (int it = 0; it < MTR / 16; ++it) {
-            if (16 * it < T.rows) {
+        for (int it = 0; it < RT; ++it) {
+            if (16 * it < wrows) {
                 s16x4_t up;
 #pragma unroll
-                for (int e2 = 0; e2 < 4; ++e2) up[e2] = (short)stg[4 * q + e2][16 * it + a];
+                for (int e2 = 0; e2 < 4; ++e2) up[e2] = (short)stg[wv][4 * q + e2][16 * it + a];
 #pragma unroll
                 for (int ct = 0; ct < CT; ++ct)
                     acc[it][ct] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ta[ct], up, acc[it][ct], 0, 0, 0);
@@ -612,24 +644,24 @@ __global__ __launch_bounds__(64, 4) void k_mexp(const MTile* __restrict__ tiles,
         }
         if (en >= T.ne) break;
 #pragma unroll
-        for (int sI = 0; sI < 4; ++sI) w[sI] = wn[sI];
-#pragma unroll
-        for (int ct = 0; ct < CT; ++ct) ta[ct] = tn[ct];
+        for (int sI = 0; sI < NWORD; ++sI) w[sI] = wn[sI];
+        tw = tn;
         e = en;
         k0 = kn;
         E = En;
+        par ^= 1;
     }
     // lane (a, q) holds C[row 16 it + a][rhs 16 ct + 4 q + e]
 #pragma unroll
-    for (int it = 0; it < MTR / 16; ++it) {
+    for (int it = 0; it < RT; ++it) {
         const int i = 16 * it + a;
-        if (i < T.rows)
+        if (i < wrows)
 #pragma unroll
             for (int ct = 0; ct < CT; ++ct)
 #pragma unroll
                 for (int e2 = 0; e2 < 4; ++e2) {
                     const int c = 16 * ct + 4 * q + e2;
-                    if (c < nc) yl[(int64_t)c * N + T.row0 + i] += acc[it][ct][e2];
+                    if (c < nc) yl[(int64_t)c * N + T.row0 + wrow + i] += acc[it][ct][e2];
                 }
     }
 }
@@ -1265,7 +1297,7 @@ void plan_apply(hodlr_t h) {
         // expansion: per level, every box's interaction-list entries in order
         // and its 128-row tiles
         std::vector<MEnt> ents;
-        std::vector<MTile> tiles;
+        std::vector<MTile> tiles, small, big;
         h->mtile_off.assign(1, 0);
         h->mexp_felems = 0;
         for (int l = 1; l <= kappa; ++l) {
@@ -1289,11 +1321,22 @@ void plan_apply(hodlr_t h) {
                     h->mexp_felems += (int64_t)std::max(bd.rank, 0) * len;
                 }
                 const int32_t ne = (int32_t)((int64_t)ents.size() - e0);
-                for (int32_t r0 = 0; r0 < len; r0 += MTR)
-                    tiles.push_back(MTile{Lv.hstart[A] + r0, std::min(MTR, len - r0), len, r0, e0,
-                                          ne, 0});
+                if (len <= MSMALL) {
+                    small.push_back(MTile{Lv.hstart[A], len, len, 0, e0, ne, 0});
+                } else {
+                    const int32_t span = MBIGW * 128;
+                    for (int32_t r0 = 0; r0 < len; r0 += span)
+                        big.push_back(MTile{Lv.hstart[A] + r0, std::min(span, len - r0), len, r0, e0,
+                                            ne, 0});
+                }
             }
+            // level l: small-box tiles, then big-box tiles
+            tiles.insert(tiles.end(), small.begin(), small.end());
             h->mtile_off.push_back((int64_t)tiles.size());
+            tiles.insert(tiles.end(), big.begin(), big.end());
+            h->mtile_off.push_back((int64_t)tiles.size());
+            small.clear();
+            big.clear();
         }
         upload(mj.data(), sizeof(MJob) * mj.size(), (void**)&h->mjobs);
         upload(reds.data(), sizeof(MRed) * reds.size(), (void**)&h->mreds);
@@ -1369,10 +1412,14 @@ void run_matvec(hodlr_t h, const XT* X, int64_t ldx, int nrhs, XT* Y, int64_t ld
             // pass 2: expansions, one level at a time (tiles of a level own
             // disjoint rows of the level sum)
             for (int l = 1; l <= h->kappa; ++l) {
-                const int64_t t0 = h->mtile_off[l - 1], cnt = h->mtile_off[l] - t0;
-                if (cnt)
-                    k_mexp<CTn><<<(unsigned)cnt, 64, 0, s>>>(h->mtiles + t0, h->ments, tproj, N, nc,
-                                                             yl);
+                const int64_t t0 = h->mtile_off[2 * l - 2], n0 = h->mtile_off[2 * l - 1] - t0;
+                const int64_t t1 = h->mtile_off[2 * l - 1], n1 = h->mtile_off[2 * l] - t1;
+                if (n0)
+                    k_mexp<CTn, MSMALL / 16, 1><<<(unsigned)n0, 64, 0, s>>>(
+                        h->mtiles + t0, h->ments, tproj, N, nc, yl);
+                if (n1)
+                    k_mexp<CTn, 8, MBIGW><<<(unsigned)n1, 64 * MBIGW, 0, s>>>(
+                        h->mtiles + t1, h->ments, tproj, N, nc, yl);
                 HIP_CHECK(hipGetLastError());
             }
             if (ev && c0 == 0) HIP_CHECK(hipEventRecord(ev[3], s));

@@ -190,7 +190,7 @@ struct MEnt {           // an interaction-list entry (A,B) in the expansion:
     int64_t t;          // its projections (t of (A,B), or s of the stored (B,A))
     int32_t r, pad;
 };
-struct MTile {          // up to 128 rows of a target box A at one level
+struct MTile {          // rows of a target box A at one level applied by one workgroup
     int32_t row0, rows; // tree row of the tile, rows in it
     int32_t len, rowoff;// |A|, offset of the tile in A
     int64_t e0;         // entries [e0, e0 + ne) in interaction-list order

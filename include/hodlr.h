@@ -141,6 +141,47 @@ hodlr_status hodlr_matvec_events(hodlr_t h, const void* X, int64_t ldx, int nrhs
                                  void* Y, int64_t ldy, int compute_prec, void* stream,
                                  void* const* events, int nevents);
 
+/* Options of hodlr_solve. */
+typedef struct {
+    double tol;           /* outer stop: max over columns of |F - A U| / |F| (FP64 operator) */
+    double inner_tol;     /* inner GMRES stop: residual estimate <= inner_tol |r| */
+    int restart;          /* Krylov dimension of one inner cycle, 1..512 */
+    int max_outer;        /* refinement steps, >= 0 */
+    int lo_compute;       /* hodlr_prec of the inner products' arithmetic (FP32 forced for BF16) */
+    int use_initial_guess;/* 1: start from U; 0: from zero */
+} hodlr_solve_opts;
+
+typedef struct {
+    int outer_iters;      /* refinement steps taken */
+    int inner_iters;      /* Arnoldi steps taken in total (one product with lo each) */
+    int converged;        /* 1 if the outer tolerance was met */
+    double rel_residual;  /* final max over columns of |F - A U| / |F| */
+    double history[64];   /* the same before each of the first 64 refinement steps */
+} hodlr_solve_info;
+
+/* Defaults: tol 1e-10, inner_tol 1e-4, restart 50, max_outer 30,
+ * lo_compute FP32, use_initial_guess 0. */
+void hodlr_default_solve_opts(hodlr_solve_opts* opts);
+
+/* Solve (alpha I + beta K~) U = F (the paper's GMRES use of the product,
+ * sec. 6.2) by iterative refinement: residuals r = F - A U with the FP64
+ * representation `hi`, corrections from one restarted GMRES cycle on `lo`
+ * (a lower-precision representation of the same points, e.g. BF16 or FP32
+ * factors; lo == hi gives plain restarted GMRES).  Krylov basis,
+ * orthogonalisation (classical Gram-Schmidt applied twice) and norms in FP64.
+ *   hi, lo   handles built on the same points and kernel; hi must hold FP64 factors.
+ *   F, U     device pointers, N x nrhs column-major FP64 in user order,
+ *            leading dimensions ldf, ldu >= N; U receives the solution.
+ *   opts     host pointer or NULL for the defaults; info host pointer (may be NULL).
+ *   Allocates a workspace of about (restart + 4) N nrhs doubles for the
+ *   call; synchronous on stream.  Calls must not overlap other calls on hi or lo.
+ * Errors: EINVAL (arguments, mismatched handles, hi not FP64, factors
+ * missing), ENOMEM, EDEVICE.  Not converging is not an error: check
+ * info->converged. */
+hodlr_status hodlr_solve(hodlr_t hi, hodlr_t lo, double alpha, double beta, const double* F,
+                         int64_t ldf, int nrhs, double* U, int64_t ldu,
+                         const hodlr_solve_opts* opts, hodlr_solve_info* info, void* stream);
+
 typedef struct {
     int64_t N;
     int d;

@@ -58,6 +58,16 @@ class Info(C.Structure):
                 ("mfma_proj_elems", C.c_int64)]
 
 
+class SolveOpts(C.Structure):
+    _fields_ = [("tol", C.c_double), ("inner_tol", C.c_double), ("restart", C.c_int),
+                ("max_outer", C.c_int), ("lo_compute", C.c_int), ("use_initial_guess", C.c_int)]
+
+
+class SolveInfo(C.Structure):
+    _fields_ = [("outer_iters", C.c_int), ("inner_iters", C.c_int), ("converged", C.c_int),
+                ("rel_residual", C.c_double), ("history", C.c_double * 64)]
+
+
 _lib = None
 _P = C.c_void_p
 _i64 = C.c_int64
@@ -78,6 +88,10 @@ def lib():
         L.hodlr_matvec_events.argtypes = [_P, _P, _i64, C.c_int, C.c_int, _P, _i64, C.c_int, _P,
                                           C.POINTER(_P), C.c_int]
         L.hodlr_get_info.argtypes = [_P, C.POINTER(Info)]
+        L.hodlr_default_solve_opts.argtypes = [C.POINTER(SolveOpts)]
+        L.hodlr_default_solve_opts.restype = None
+        L.hodlr_solve.argtypes = [_P, _P, C.c_double, C.c_double, _P, _i64, C.c_int, _P, _i64,
+                                  C.POINTER(SolveOpts), C.POINTER(SolveInfo), _P]
         L.hodlr_export_tree.argtypes = [_P, _P, _P]
         L.hodlr_export_boxes.argtypes = [_P, C.c_int, _P, _P, _P]
         L.hodlr_export_il.argtypes = [_P, C.c_int, C.POINTER(_i64), _P, _P]
@@ -90,7 +104,7 @@ def lib():
         for f in ("hodlr_build", "hodlr_matvec", "hodlr_matvec_events", "hodlr_get_info",
                   "hodlr_export_tree",
                   "hodlr_export_boxes", "hodlr_export_il", "hodlr_export_near",
-                  "hodlr_export_factors", "hodlr_import_factors"):
+                  "hodlr_export_factors", "hodlr_import_factors", "hodlr_solve"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -185,6 +199,35 @@ def hodlr_matvec_events(h: int, X, Y, events, compute_prec: int = FP64, stream=N
                                      C.c_void_p(int(stream)), arr, len(events)))
 
 
+def default_solve_opts() -> SolveOpts:
+    o = SolveOpts()
+    lib().hodlr_default_solve_opts(C.byref(o))
+    return o
+
+
+def hodlr_solve(hi: int, lo: int, alpha: float, beta: float, F, U, opts: SolveOpts | None = None,
+                stream=None) -> SolveInfo:
+    """(alpha I + beta K~) U = F for float64 device tensors F, U (N or N x nrhs,
+    column-major): FP64 refinement with `hi`, inner GMRES with `lo`."""
+    import torch
+    if F.dtype != torch.float64 or U.dtype != torch.float64 or not (F.is_cuda and U.is_cuda):
+        raise TypeError("F and U must be float64 device tensors")
+    if F.dim() == 1:
+        N, nrhs, ldf, ldu = F.shape[0], 1, F.shape[0], U.shape[0]
+    else:
+        N, nrhs = F.shape
+        if F.stride(0) != 1 or U.stride(0) != 1:
+            raise ValueError("F and U must be column-major (stride 1 along N)")
+        ldf, ldu = (F.stride(1) if nrhs > 1 else N), (U.stride(1) if nrhs > 1 else N)
+    info = SolveInfo()
+    _check(lib().hodlr_solve(C.c_void_p(hi), C.c_void_p(lo), C.c_double(alpha), C.c_double(beta),
+                             C.c_void_p(F.data_ptr()), C.c_int64(ldf), nrhs,
+                             C.c_void_p(U.data_ptr()), C.c_int64(ldu),
+                             C.byref(opts) if opts is not None else None, C.byref(info),
+                             _stream_ptr(stream)))
+    return info
+
+
 def hodlr_get_info(h: int) -> Info:
     info = Info()
     _check(lib().hodlr_get_info(C.c_void_p(h), C.byref(info)))
@@ -275,7 +318,10 @@ class HODLR:
     def __del__(self):
         h = getattr(self, "h", None)
         if h:
-            hodlr_destroy(h)
+            try:
+                hodlr_destroy(h)
+            except Exception:   # interpreter shutdown: the module may be gone
+                pass
             self.h = None
 
     def info(self) -> Info:

@@ -185,6 +185,49 @@ hodlr_status hodlr_matvec_events(hodlr_t h, const void* X, int64_t ldx, int nrhs
     return matvec_checked(h, X, ldx, nrhs, x_prec, Y, ldy, compute_prec, stream, events, nevents);
 }
 
+void hodlr_default_solve_opts(hodlr_solve_opts* o) {
+    if (!o) return;
+    o->tol = 1e-10;
+    o->inner_tol = 1e-4;
+    o->restart = 50;
+    o->max_outer = 30;
+    o->lo_compute = HODLR_FP32;
+    o->use_initial_guess = 0;
+}
+
+hodlr_status hodlr_solve(hodlr_t hi, hodlr_t lo, double alpha, double beta, const double* F,
+                         int64_t ldf, int nrhs, double* U, int64_t ldu,
+                         const hodlr_solve_opts* opts, hodlr_solve_info* info, void* stream) {
+    if (!hi || !lo || !F || !U) return set_error(HODLR_EINVAL, "null pointer argument");
+    if (hi->N != lo->N || hi->d != lo->d)
+        return set_error(HODLR_EINVAL, "hi and lo must be built on the same points");
+    if (hi->opts.storage != HODLR_FP64)
+        return set_error(HODLR_EINVAL, "hi must hold FP64 factors (FP64 residuals)");
+    if (nrhs < 1) return set_error(HODLR_EINVAL, "nrhs must be >= 1");
+    if (ldf < hi->N || ldu < hi->N) return set_error(HODLR_EINVAL, "leading dimension < N");
+    if (!std::isfinite(alpha) || !std::isfinite(beta))
+        return set_error(HODLR_EINVAL, "alpha and beta must be finite");
+    hodlr_solve_opts o;
+    hodlr_default_solve_opts(&o);
+    if (opts) o = *opts;
+    if (!(o.tol > 0.0) || !(o.inner_tol > 0.0 && o.inner_tol < 1.0))
+        return set_error(HODLR_EINVAL, "need tol > 0 and 0 < inner_tol < 1");
+    if (o.restart < 1 || o.restart > 512) return set_error(HODLR_EINVAL, "restart must be 1..512");
+    if (o.max_outer < 0) return set_error(HODLR_EINVAL, "max_outer must be >= 0");
+    if (o.lo_compute != HODLR_FP64 && o.lo_compute != HODLR_FP32)
+        return set_error(HODLR_EINVAL, "lo_compute must be FP64 or FP32");
+    for (hodlr_t h : {hi, lo}) {
+        for (int l = 1; l <= h->kappa; ++l)
+            if (!h->lev[l].has_factors) return set_error(HODLR_EINVAL, "factors missing");
+        if (!h->near_items) return set_error(HODLR_EINVAL, "factors missing");
+    }
+    hodlr_solve_info tmp{};
+    return guarded([&] {
+        hodlr::solve(hi, lo, alpha, beta, F, ldf, nrhs, U, ldu, o, info ? info : &tmp,
+                     (hipStream_t)stream);
+    });
+}
+
 hodlr_status hodlr_get_info(hodlr_t h, hodlr_info* info) {
     if (!h || !info) return set_error(HODLR_EINVAL, "null pointer argument");
     std::memset(info, 0, sizeof(*info));

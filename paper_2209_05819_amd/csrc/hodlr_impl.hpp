@@ -292,6 +292,10 @@ void plan_apply(hodlr_t h);
 constexpr int kApplyClasses = 6;
 void matvec(hodlr_t h, const void* X, int64_t ldx, int nrhs, int x_prec, void* Y, int64_t ldy,
             int compute_prec, hipEvent_t const* ev, int nev, hipStream_t s);
+// solve.hip: (alpha I + beta K~) U = F, FP64 refinement over GMRES on lo
+void solve(hodlr_t hi, hodlr_t lo, double alpha, double beta, const double* F, int64_t ldf,
+           int nrhs, double* U, int64_t ldu, const hodlr_solve_opts& o, hodlr_solve_info* info,
+           hipStream_t s);
 // factor import / export in aca.hip
 void import_level(hodlr_t h, int level, const int32_t* ranks, const double* U, const double* V,
                   hipStream_t s);

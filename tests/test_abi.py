@@ -39,6 +39,8 @@ def test_struct_layouts_match_header():
     assert C.sizeof(P.Opts) == 4 * 2 + 8 * 8 + 8 + 4 * 4 + 8
     assert P.Info.build_ms.offset + 32 == P.Info.mfma_proj_jobs.offset
     assert P.Info.mfma_proj_elems.offset + 8 == C.sizeof(P.Info)
+    assert C.sizeof(P.SolveOpts) == 8 * 2 + 4 * 4
+    assert C.sizeof(P.SolveInfo) == 4 * 3 + 4 + 8 + 8 * 64
 
 
 def test_default_opts_and_errors_without_gpu():
@@ -58,6 +60,10 @@ def test_default_opts_and_errors_without_gpu():
     st = L.hodlr_build(pts.ctypes.data_as(C.c_void_p), 4, 9, C.byref(k), 8, 1e-6, None, None,
                        C.byref(out))
     assert st == 1 and b"d must be" in L.hodlr_last_error()
+    so = P.default_solve_opts()
+    assert so.tol == 1e-10 and so.restart == 50 and so.lo_compute == P.FP32
+    st = L.hodlr_solve(None, None, 1.0, 1.0, None, 0, 1, None, 0, None, None, None)
+    assert st == 1 and b"null" in L.hodlr_last_error()
     st = L.hodlr_matvec(None, None, 0, 1, 0, None, 0, 0, None)
     assert st == 1
 

@@ -11,7 +11,8 @@ Two precisions are timed on the same inputs: FP64 (factors and arithmetic)
 and mixed (FP32 factors, FP32 arithmetic).  `value` is the FP64 throughput;
 the mixed figures are in `mixed`.  `multi_rhs` times the matrix-core path on
 its own workload (2^19 points in 4D, 1/r^2, 32 right-hand sides, BF16
-factors).  Prints one JSON line.
+factors); `solve` times GMRES with FP64 iterative refinement on the 2^20-point
+Gaussian-mixture workload.  Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -156,6 +157,46 @@ def multi_rhs(P, torch, W, steps, warmup, n_override=0):
     }
 
 
+def solve_bench(P, torch, W, n_override=0):
+    """GMRES with FP64 iterative refinement: (I + K/N) U = F on the 2^20-point
+    Gaussian-mixture cloud (exp(-r^2/0.25), diagonal 1 + 1e-3, leaf 64, ACA
+    1e-6), 16 N(0,1) right-hand sides; FP64 residuals on FP64 factors, inner
+    GMRES on BF16 factors, to a relative residual of 1e-10."""
+    w = W.WORKLOADS["mixture3d_gauss_n1048576"]
+    if n_override:
+        w = W.scaled(w, n_override)
+    pts, q = w.points(), w.rhs()
+    N, nrhs = w.N, q.shape[1]
+    k = P.make_kernel(w.kernel, h=w.h, diag=w.diag)
+    t0 = time.perf_counter()
+    H64 = P.HODLR(pts, k, w.leaf, w.tol, domain=w.domain)
+    H16 = P.HODLR(pts, k, w.leaf, w.tol, domain=w.domain, storage=P.BF16)
+    torch.cuda.synchronize()
+    build = time.perf_counter() - t0
+    F = torch.tensor(np.ascontiguousarray(q.T), dtype=torch.float64, device="cuda").t()
+    U = torch.zeros((nrhs, N), dtype=torch.float64, device="cuda").t()
+    o = P.default_solve_opts()
+    o.tol, o.inner_tol, o.restart, o.max_outer = 1e-10, 1e-3, 30, 20
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    info = P.hodlr_solve(H64.h, H16.h, 1.0, 1.0 / N, F, U, o)
+    torch.cuda.synchronize()
+    secs = time.perf_counter() - t0
+    print(f"[bench] solve {secs:.2f} s outer {info.outer_iters} inner {info.inner_iters} "
+          f"rel {info.rel_residual:.2e}", file=sys.stderr, flush=True)
+    del H64, H16
+    return {
+        "workload": w.name, "system": "(I + K/N) U = F", "N": N, "nrhs": nrhs,
+        "kernel": "exp(-r^2/0.25), diag 1+1e-3", "leaf": w.leaf, "aca_tol": w.tol,
+        "tol": o.tol, "inner": "GMRES(30) on BF16 factors, f32 arithmetic, to 1e-3",
+        "outer": "FP64 residuals on FP64 factors", "converged": bool(info.converged),
+        "rel_residual": info.rel_residual, "outer_iters": info.outer_iters,
+        "inner_iters": info.inner_iters, "seconds": secs,
+        "value": N * nrhs / secs, "unit": "N*nrhs/s solved", "build_s": round(build, 2),
+        "history": [info.history[i] for i in range(min(info.outer_iters + 1, 64))],
+    }
+
+
 def factor_bytes(info, elem):
     return sum(info.factor_elems[l] for l in range(1, info.kappa + 1)) * elem
 
@@ -213,6 +254,8 @@ def main():
     ap.add_argument("--no-multi-rhs", action="store_true",
                     help="skip the 32-RHS BF16 matrix-core workload")
     ap.add_argument("--multi-rhs-n", type=int, default=0, help="override its N")
+    ap.add_argument("--no-solve", action="store_true", help="skip the GMRES-IR solve")
+    ap.add_argument("--solve-n", type=int, default=0, help="override the solve's N")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain device copy of known size (counter calibration)")
     args = ap.parse_args()
@@ -306,6 +349,10 @@ def main():
     if not args.no_multi_rhs:
         mrhs = multi_rhs(P, torch, W, max(3, args.steps // 4), 1, args.multi_rhs_n)
 
+    solve = None
+    if not args.no_solve:
+        solve = solve_bench(P, torch, W, args.solve_n)
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu, crow, cb = cpu_baseline(w, pts, q, args.level_rule)
@@ -361,6 +408,7 @@ def main():
                             "bytes": int(fb64 + vec_bytes)},
         "mixed": mixed,
         "multi_rhs": mrhs,
+        "solve": solve,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))

@@ -169,18 +169,93 @@ void hodlr_default_solve_opts(hodlr_solve_opts* opts);
  * (a lower-precision representation of the same points, e.g. BF16 or FP32
  * factors; lo == hi gives plain restarted GMRES).  Krylov basis,
  * orthogonalisation (classical Gram-Schmidt applied twice) and norms in FP64.
- *   hi, lo   handles built on the same points and kernel; hi must hold FP64 factors.
+ *   hi, lo   handles built on the same points and kernel; hi holds FP64 or FP32
+ *            factors and is applied in FP64 arithmetic.
  *   F, U     device pointers, N x nrhs column-major FP64 in user order,
  *            leading dimensions ldf, ldu >= N; U receives the solution.
  *   opts     host pointer or NULL for the defaults; info host pointer (may be NULL).
  *   Allocates a workspace of about (restart + 4) N nrhs doubles for the
  *   call; synchronous on stream.  Calls must not overlap other calls on hi or lo.
- * Errors: EINVAL (arguments, mismatched handles, hi not FP64, factors
+ * Errors: EINVAL (arguments, mismatched handles, hi with BF16 factors, factors
  * missing), ENOMEM, EDEVICE.  Not converging is not an error: check
  * info->converged. */
 hodlr_status hodlr_solve(hodlr_t hi, hodlr_t lo, double alpha, double beta, const double* F,
                          int64_t ldf, int nrhs, double* U, int64_t ldu,
                          const hodlr_solve_opts* opts, hodlr_solve_info* info, void* stream);
+
+/* ---- Serving: resident point sets, continuous batching of requests ---- */
+
+typedef struct hodlr_server_s* hodlr_server_t;
+
+typedef struct {
+    size_t mem_budget_bytes;  /* device memory for resident sets, batch buffers and
+                               * running solves; 0 = 90% of the free memory at creation */
+    int max_concurrent;       /* stream slots: launches in flight at once, 1..64 */
+    int max_batch_cols;       /* columns of one batched product = largest nrhs, 1..1024 */
+    int64_t max_points;       /* largest set (sizes the batch buffers), >= 1 */
+} hodlr_server_opts;
+
+typedef enum { HODLR_REQ_MATVEC = 0, HODLR_REQ_SOLVE = 1 } hodlr_request_kind;
+
+typedef struct {
+    int kind;                 /* hodlr_request_kind */
+    int set;                  /* from hodlr_server_add_set */
+    int nrhs;                 /* 1 .. max_batch_cols */
+    const double* X;          /* device, N x nrhs column-major (ld N), FP64, user order */
+    double* Y;                /* device, same shape: the product, or the solution */
+    double alpha, beta;       /* solve: (alpha I + beta K~) Y = X */
+    double tol;               /* solve: relative residual to reach */
+} hodlr_request;
+
+typedef struct {
+    int64_t submitted, completed, failed;
+    int64_t launches;          /* products and solves started */
+    int64_t batched_requests;  /* products that shared a launch with others */
+    int64_t max_concurrent;    /* most launches in flight at once */
+    size_t used_bytes, budget_bytes;
+    int sets;
+} hodlr_server_stats;
+
+/* Defaults: budget 0 (90% of free), 8 slots, 64 columns, 2^18 points. */
+void hodlr_server_default_opts(hodlr_server_opts* opts);
+
+/* Start a server (one scheduler thread, max_concurrent HIP streams of default
+ * priority, batch buffers of 2 max_points max_batch_cols doubles per slot).
+ * Errors: EINVAL, ENOMEM, EDEVICE. */
+hodlr_status hodlr_server_create(const hodlr_server_opts* opts, hodlr_server_t* out);
+
+/* Build and keep resident the representation of a point set (arguments as
+ * hodlr_build, points on the host; opts->mem_budget_bytes is replaced by the
+ * server's remaining room).  Blocks until built.  *set_id receives its index.
+ * Errors: those of hodlr_build; ENOMEM when it does not fit the budget. */
+hodlr_status hodlr_server_add_set(hodlr_server_t srv, const double* points, int64_t N, int d,
+                                  const hodlr_kernel* kernel, int leaf_size, double tol,
+                                  const hodlr_opts* opts, int* set_id);
+
+/* Queue a request; returns at once with its id.  The scheduler starts it when
+ * its set is idle, a slot is free and its workspace fits the budget; queued
+ * products of one set are applied together as one product of their columns.
+ * Solves run GMRES with iterative refinement on the set itself (FP64
+ * residuals; inner GMRES(30) in FP32 arithmetic, to tol).  X and Y must stay
+ * valid until the request completes.  Errors: EINVAL (unknown set, nrhs out
+ * of range, solve on BF16 factors, set larger than max_points). */
+hodlr_status hodlr_server_submit(hodlr_server_t srv, const hodlr_request* req, int64_t* id);
+
+/* Block until request id completes; returns its status (a solve that misses
+ * its tolerance: EUNSUPPORTED) and its time in the queue and running, in
+ * microseconds (either pointer may be NULL).  A completed request is
+ * reported once; its id is then unknown (EINVAL). */
+hodlr_status hodlr_server_wait(hodlr_server_t srv, int64_t id, double* queue_us, double* run_us);
+
+/* Non-blocking hodlr_server_wait: *done = 0 while the request is queued or
+ * running (status OK, nothing else written). */
+hodlr_status hodlr_server_poll(hodlr_server_t srv, int64_t id, int* done, double* queue_us,
+                               double* run_us);
+
+hodlr_status hodlr_server_get_stats(hodlr_server_t srv, hodlr_server_stats* stats);
+
+/* Finish every queued request, stop the scheduler, free the sets. */
+void hodlr_server_destroy(hodlr_server_t srv);
 
 typedef struct {
     int64_t N;

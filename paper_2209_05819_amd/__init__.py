@@ -68,6 +68,26 @@ class SolveInfo(C.Structure):
                 ("rel_residual", C.c_double), ("history", C.c_double * 64)]
 
 
+class ServerOpts(C.Structure):
+    _fields_ = [("mem_budget_bytes", C.c_size_t), ("max_concurrent", C.c_int),
+                ("max_batch_cols", C.c_int), ("max_points", C.c_int64)]
+
+
+class Request(C.Structure):
+    _fields_ = [("kind", C.c_int), ("set", C.c_int), ("nrhs", C.c_int), ("X", C.c_void_p),
+                ("Y", C.c_void_p), ("alpha", C.c_double), ("beta", C.c_double),
+                ("tol", C.c_double)]
+
+
+class ServerStats(C.Structure):
+    _fields_ = [("submitted", C.c_int64), ("completed", C.c_int64), ("failed", C.c_int64),
+                ("launches", C.c_int64), ("batched_requests", C.c_int64),
+                ("max_concurrent", C.c_int64), ("used_bytes", C.c_size_t),
+                ("budget_bytes", C.c_size_t), ("sets", C.c_int)]
+
+
+REQ_MATVEC, REQ_SOLVE = 0, 1
+
 _lib = None
 _P = C.c_void_p
 _i64 = C.c_int64
@@ -88,6 +108,18 @@ def lib():
         L.hodlr_matvec_events.argtypes = [_P, _P, _i64, C.c_int, C.c_int, _P, _i64, C.c_int, _P,
                                           C.POINTER(_P), C.c_int]
         L.hodlr_get_info.argtypes = [_P, C.POINTER(Info)]
+        L.hodlr_server_default_opts.argtypes = [C.POINTER(ServerOpts)]
+        L.hodlr_server_default_opts.restype = None
+        L.hodlr_server_create.argtypes = [C.POINTER(ServerOpts), C.POINTER(_P)]
+        L.hodlr_server_add_set.argtypes = [_P, _P, _i64, C.c_int, C.POINTER(Kernel), C.c_int,
+                                           C.c_double, C.POINTER(Opts), C.POINTER(C.c_int)]
+        L.hodlr_server_submit.argtypes = [_P, C.POINTER(Request), C.POINTER(_i64)]
+        L.hodlr_server_wait.argtypes = [_P, _i64, C.POINTER(C.c_double), C.POINTER(C.c_double)]
+        L.hodlr_server_poll.argtypes = [_P, _i64, C.POINTER(C.c_int), C.POINTER(C.c_double),
+                                        C.POINTER(C.c_double)]
+        L.hodlr_server_get_stats.argtypes = [_P, C.POINTER(ServerStats)]
+        L.hodlr_server_destroy.argtypes = [_P]
+        L.hodlr_server_destroy.restype = None
         L.hodlr_default_solve_opts.argtypes = [C.POINTER(SolveOpts)]
         L.hodlr_default_solve_opts.restype = None
         L.hodlr_solve.argtypes = [_P, _P, C.c_double, C.c_double, _P, _i64, C.c_int, _P, _i64,
@@ -104,7 +136,9 @@ def lib():
         for f in ("hodlr_build", "hodlr_matvec", "hodlr_matvec_events", "hodlr_get_info",
                   "hodlr_export_tree",
                   "hodlr_export_boxes", "hodlr_export_il", "hodlr_export_near",
-                  "hodlr_export_factors", "hodlr_import_factors", "hodlr_solve"):
+                  "hodlr_export_factors", "hodlr_import_factors", "hodlr_solve",
+                  "hodlr_server_create", "hodlr_server_add_set", "hodlr_server_submit",
+                  "hodlr_server_wait", "hodlr_server_poll", "hodlr_server_get_stats"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -334,3 +368,86 @@ class HODLR:
                 (X.shape[1], X.shape[0]), dtype=X.dtype, device=X.device).t()
         hodlr_matvec(self.h, X, out, compute_prec, stream)
         return out
+
+
+class Server:
+    """Resident point sets and a continuously batched request loop (the C
+    library's hodlr_server_*).  Requests take float64 device tensors (N or
+    N x nrhs, column-major with leading dimension N) that must stay alive
+    until the request completes."""
+
+    def __init__(self, mem_budget_bytes=0, max_concurrent=8, max_batch_cols=64,
+                 max_points=1 << 18):
+        o = ServerOpts()
+        lib().hodlr_server_default_opts(C.byref(o))
+        o.mem_budget_bytes = int(mem_budget_bytes)
+        o.max_concurrent = int(max_concurrent)
+        o.max_batch_cols = int(max_batch_cols)
+        o.max_points = int(max_points)
+        out = _P()
+        _check(lib().hodlr_server_create(C.byref(o), C.byref(out)))
+        self.s = out.value
+        self._keep = {}
+
+    def add_set(self, points, kernel: Kernel, leaf_size: int, tol: float, *, level_rule=1,
+                storage=FP64, domain=None) -> int:
+        o = default_opts()
+        o.level_rule = level_rule
+        o.storage = storage
+        if domain is not None:
+            o.has_domain = 1
+            lo = np.asarray(domain[0], dtype=np.float64)
+            for a in range(len(lo)):
+                o.domain_lo[a] = lo[a]
+            o.domain_side = float(domain[1])
+        P = np.ascontiguousarray(points, dtype=np.float64)
+        sid = C.c_int()
+        _check(lib().hodlr_server_add_set(C.c_void_p(self.s), _np_ptr(P), P.shape[0], P.shape[1],
+                                          C.byref(kernel), int(leaf_size), float(tol),
+                                          C.byref(o), C.byref(sid)))
+        return sid.value
+
+    @staticmethod
+    def _shape(X):
+        if X.dim() == 1:
+            return X.shape[0], 1
+        if X.stride(0) != 1 or (X.shape[1] > 1 and X.stride(1) != X.shape[0]):
+            raise ValueError("requests take column-major tensors with leading dimension N")
+        return X.shape
+
+    def submit(self, kind: int, set_id: int, X, Y, alpha=1.0, beta=1.0, tol=1e-8) -> int:
+        import torch
+        if X.dtype != torch.float64 or Y.dtype != torch.float64:
+            raise TypeError("requests take float64 tensors")
+        _, nrhs = self._shape(X)
+        r = Request(kind, set_id, nrhs, X.data_ptr(), Y.data_ptr(), alpha, beta, tol)
+        rid = _i64()
+        _check(lib().hodlr_server_submit(C.c_void_p(self.s), C.byref(r), C.byref(rid)))
+        self._keep[rid.value] = (X, Y)
+        return rid.value
+
+    def wait(self, rid: int):
+        """Blocks; returns (queue_us, run_us); raises on a failed request."""
+        qu, ru = C.c_double(), C.c_double()
+        try:
+            _check(lib().hodlr_server_wait(C.c_void_p(self.s), rid, C.byref(qu), C.byref(ru)))
+        finally:
+            self._keep.pop(rid, None)
+        return qu.value, ru.value
+
+    def stats(self) -> ServerStats:
+        st = ServerStats()
+        _check(lib().hodlr_server_get_stats(C.c_void_p(self.s), C.byref(st)))
+        return st
+
+    def close(self):
+        if getattr(self, "s", None):
+            lib().hodlr_server_destroy(C.c_void_p(self.s))
+            self.s = None
+            self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

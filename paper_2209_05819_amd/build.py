@@ -10,7 +10,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libhodlr.so")
-SOURCES = ["api.hip", "tree.hip", "lists.hip", "aca.hip", "apply.hip", "prim.hip", "solve.hip"]
+SOURCES = ["api.hip", "tree.hip", "lists.hip", "aca.hip", "apply.hip", "prim.hip", "solve.hip",
+           "serve.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

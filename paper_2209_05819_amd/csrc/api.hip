@@ -201,8 +201,8 @@ hodlr_status hodlr_solve(hodlr_t hi, hodlr_t lo, double alpha, double beta, cons
     if (!hi || !lo || !F || !U) return set_error(HODLR_EINVAL, "null pointer argument");
     if (hi->N != lo->N || hi->d != lo->d)
         return set_error(HODLR_EINVAL, "hi and lo must be built on the same points");
-    if (hi->opts.storage != HODLR_FP64)
-        return set_error(HODLR_EINVAL, "hi must hold FP64 factors (FP64 residuals)");
+    if (hi->opts.storage == HODLR_BF16)
+        return set_error(HODLR_EINVAL, "hi must hold FP64 or FP32 factors (FP64 residuals)");
     if (nrhs < 1) return set_error(HODLR_EINVAL, "nrhs must be >= 1");
     if (ldf < hi->N || ldu < hi->N) return set_error(HODLR_EINVAL, "leading dimension < N");
     if (!std::isfinite(alpha) || !std::isfinite(beta))
@@ -226,6 +226,109 @@ hodlr_status hodlr_solve(hodlr_t hi, hodlr_t lo, double alpha, double beta, cons
         hodlr::solve(hi, lo, alpha, beta, F, ldf, nrhs, U, ldu, o, info ? info : &tmp,
                      (hipStream_t)stream);
     });
+}
+
+void hodlr_server_default_opts(hodlr_server_opts* o) {
+    if (!o) return;
+    o->mem_budget_bytes = 0;
+    o->max_concurrent = 8;
+    o->max_batch_cols = 64;
+    o->max_points = (int64_t)1 << 18;
+}
+
+hodlr_status hodlr_server_create(const hodlr_server_opts* opts, hodlr_server_t* out) {
+    if (!out) return set_error(HODLR_EINVAL, "null pointer argument");
+    hodlr_server_opts o;
+    hodlr_server_default_opts(&o);
+    if (opts) o = *opts;
+    if (o.max_concurrent < 1 || o.max_concurrent > 64)
+        return set_error(HODLR_EINVAL, "max_concurrent must be 1..64");
+    if (o.max_batch_cols < 1 || o.max_batch_cols > 1024)
+        return set_error(HODLR_EINVAL, "max_batch_cols must be 1..1024");
+    if (o.max_points < 1) return set_error(HODLR_EINVAL, "max_points must be >= 1");
+    return guarded([&] {
+        if (o.mem_budget_bytes == 0) {
+            size_t fr = 0, tot = 0;
+            HIP_CHECK(hipMemGetInfo(&fr, &tot));
+            o.mem_budget_bytes = fr / 10 * 9;
+        }
+        const hodlr_status st = hodlr::server_create(o, out);
+        if (st != HODLR_OK) hodlr::fail(st, "server creation failed");
+    });
+}
+
+hodlr_status hodlr_server_add_set(hodlr_server_t srv, const double* points, int64_t N, int d,
+                                  const hodlr_kernel* kernel, int leaf_size, double tol,
+                                  const hodlr_opts* opts, int* set_id) {
+    if (!srv || !set_id) return set_error(HODLR_EINVAL, "null pointer argument");
+    hodlr_opts o;
+    hodlr_default_opts(&o);
+    if (opts) o = *opts;
+    o.mem_budget_bytes = hodlr::server_room(srv);
+    if (o.mem_budget_bytes == 0) return set_error(HODLR_ENOMEM, "server memory budget exhausted");
+    hodlr_t h = nullptr;
+    const hodlr_status st = hodlr_build(points, N, d, kernel, leaf_size, tol, &o, nullptr, &h);
+    if (st != HODLR_OK) return st;
+    return guarded([&] {
+        try {
+            // size the product workspace once for every batch width it will see
+            const int cols = hodlr::server_batch_cols(srv);
+            for (int prec : {HODLR_FP64, HODLR_FP32}) {
+                if (h->opts.storage == HODLR_BF16 && prec == HODLR_FP64) continue;
+                hodlr::reserve_workspace(h, 1, prec, nullptr);
+                hodlr::reserve_workspace(h, cols, prec, nullptr);
+            }
+        } catch (...) {
+            hodlr_destroy(h);
+            throw;
+        }
+        *set_id = hodlr::server_add(srv, h);
+    });
+}
+
+hodlr_status hodlr_server_submit(hodlr_server_t srv, const hodlr_request* req, int64_t* id) {
+    if (!srv || !req || !id || !req->X || !req->Y)
+        return set_error(HODLR_EINVAL, "null pointer argument");
+    if (req->kind != HODLR_REQ_MATVEC && req->kind != HODLR_REQ_SOLVE)
+        return set_error(HODLR_EINVAL, "unknown request kind");
+    if (req->nrhs < 1) return set_error(HODLR_EINVAL, "nrhs must be >= 1");
+    if (req->kind == HODLR_REQ_SOLVE &&
+        (!(req->tol > 0) || !std::isfinite(req->alpha) || !std::isfinite(req->beta)))
+        return set_error(HODLR_EINVAL, "solve needs tol > 0 and finite alpha, beta");
+    std::string err;
+    const hodlr_status st = hodlr::server_submit(srv, *req, id, err);
+    if (st != HODLR_OK) return set_error(st, err);
+    g_last_error.clear();
+    return HODLR_OK;
+}
+
+hodlr_status hodlr_server_wait(hodlr_server_t srv, int64_t id, double* queue_us, double* run_us) {
+    if (!srv) return set_error(HODLR_EINVAL, "null server");
+    std::string err;
+    const hodlr_status st = hodlr::server_wait(srv, id, 1, nullptr, queue_us, run_us, err);
+    if (st != HODLR_OK) return set_error(st, err);
+    g_last_error.clear();
+    return HODLR_OK;
+}
+
+hodlr_status hodlr_server_poll(hodlr_server_t srv, int64_t id, int* done, double* queue_us,
+                               double* run_us) {
+    if (!srv || !done) return set_error(HODLR_EINVAL, "null pointer argument");
+    std::string err;
+    const hodlr_status st = hodlr::server_wait(srv, id, 0, done, queue_us, run_us, err);
+    if (st != HODLR_OK) return set_error(st, err);
+    g_last_error.clear();
+    return HODLR_OK;
+}
+
+hodlr_status hodlr_server_get_stats(hodlr_server_t srv, hodlr_server_stats* stats) {
+    if (!srv || !stats) return set_error(HODLR_EINVAL, "null pointer argument");
+    hodlr::server_stats(srv, stats);
+    return HODLR_OK;
+}
+
+void hodlr_server_destroy(hodlr_server_t srv) {
+    if (srv) hodlr::server_destroy(srv);
 }
 
 hodlr_status hodlr_get_info(hodlr_t h, hodlr_info* info) {

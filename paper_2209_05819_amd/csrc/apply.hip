@@ -1516,8 +1516,7 @@ void dispatch_nr(hodlr_t h, const XT* X, int64_t ldx, int nrhs, XT* Y, int64_t l
 
 }  // namespace
 
-void matvec(hodlr_t h, const void* X, int64_t ldx, int nrhs, int x_prec, void* Y, int64_t ldy,
-            int compute_prec, hipEvent_t const* ev, int nev, hipStream_t s) {
+void reserve_workspace(hodlr_t h, int nrhs, int compute_prec, hipStream_t s) {
     const int64_t N = h->N;
     const size_t cs = compute_prec == HODLR_FP32 ? 4 : 8;
     const int64_t TT = std::max<int64_t>(h->t_total, 1);
@@ -1541,6 +1540,12 @@ void matvec(hodlr_t h, const void* X, int64_t ldx, int nrhs, int x_prec, void* Y
         h->ws = dalloc(h, need);
         h->ws_bytes = need;
     }
+}
+
+void matvec(hodlr_t h, const void* X, int64_t ldx, int nrhs, int x_prec, void* Y, int64_t ldy,
+            int compute_prec, hipEvent_t const* ev, int nev, hipStream_t s) {
+    reserve_workspace(h, nrhs, compute_prec, s);
+    const bool b16 = h->opts.storage == HODLR_BF16;
     char* ws = (char*)h->ws;
     const bool s32 = h->opts.storage == HODLR_FP32;
     const bool c32 = compute_prec == HODLR_FP32;

@@ -292,6 +292,18 @@ void plan_apply(hodlr_t h);
 constexpr int kApplyClasses = 6;
 void matvec(hodlr_t h, const void* X, int64_t ldx, int nrhs, int x_prec, void* Y, int64_t ldy,
             int compute_prec, hipEvent_t const* ev, int nev, hipStream_t s);
+// grows the handle's product workspace to what nrhs columns need
+void reserve_workspace(hodlr_t h, int nrhs, int compute_prec, hipStream_t s);
+// serve.hip
+hodlr_status server_create(const hodlr_server_opts& o, hodlr_server_t* out);
+void server_destroy(hodlr_server_t S);
+int server_add(hodlr_server_t S, hodlr_t h);
+size_t server_room(hodlr_server_t S);
+int server_batch_cols(hodlr_server_t S);
+hodlr_status server_submit(hodlr_server_t S, const hodlr_request& r, int64_t* id, std::string& err);
+hodlr_status server_wait(hodlr_server_t S, int64_t id, int block, int* done, double* queue_us,
+                         double* run_us, std::string& err);
+void server_stats(hodlr_server_t S, hodlr_server_stats* st);
 // solve.hip: (alpha I + beta K~) U = F, FP64 refinement over GMRES on lo
 void solve(hodlr_t hi, hodlr_t lo, double alpha, double beta, const double* F, int64_t ldf,
            int nrhs, double* U, int64_t ldu, const hodlr_solve_opts& o, hodlr_solve_info* info,

@@ -1,0 +1,145 @@
+"""Serving loop: resident sets, continuous batching (needs an MI355X).
+
+Every request is run once alone (submitted, then waited for before the next)
+and once in a mix (all submitted back to back, so products of one set are
+batched into shared launches and sets run concurrently); each result must be
+the same within the precision of its set: FP64 sets 1e-12 relative (batched
+products take a different kernel path, so rounding differs), FP32 sets
+1e-5, solves 1e-6 (both runs meet the 1e-8 residual on a system with
+condition number near 1).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2209_05819_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def P():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2209_05819_amd as P
+    P.lib()
+    return P
+
+
+def _sets(P, srv):
+    specs = [
+        (W.uniform_points(12000, 3, 61), P.make_kernel("inv_r"), 64, 1e-8, P.FP64),
+        (W.uniform_points(8000, 2, 62), P.make_kernel("log"), 64, 1e-8, P.FP32),
+        (W.gaussian_mixture(10000, 3, 63), P.make_kernel("gauss", h=0.5, diag=1.001), 64, 1e-8,
+         P.FP64),
+        (W.uniform_points(5000, 2, 64), P.make_kernel("gauss", h=0.5, diag=1.0), 48, 1e-8, P.FP32),
+    ]
+    ids, Ns, precs = [], [], []
+    for pts, k, leaf, tol, st in specs:
+        ids.append(srv.add_set(pts, k, leaf, tol, storage=st))
+        Ns.append(pts.shape[0])
+        precs.append(st)
+    return ids, Ns, precs
+
+
+def _requests(P, Ns, nreq, seed):
+    g = W.rng(seed)
+    reqs = []
+    for i in range(nreq):
+        s = int(g.integers(0, len(Ns)))
+        if g.random() < 0.7:
+            reqs.append((P.REQ_MATVEC, s, int(g.integers(1, 9))))
+        else:
+            reqs.append((P.REQ_SOLVE, s, int(g.integers(1, 3))))
+    return reqs
+
+
+def _tensor(torch, N, nrhs, seed):
+    x = W.rhs_normal(N, nrhs, seed)
+    return torch.tensor(np.ascontiguousarray(x.T), device="cuda").t() if nrhs > 1 else \
+        torch.tensor(x[:, 0], device="cuda")
+
+
+def test_results_same_alone_and_in_the_mix(P):
+    import torch
+    srv = P.Server(max_concurrent=4, max_batch_cols=32, max_points=20000)
+    ids, Ns, precs = _sets(P, srv)
+    reqs = _requests(P, Ns, 40, 7)
+    X = [_tensor(torch, Ns[s], n, 100 + i) for i, (_, s, n) in enumerate(reqs)]
+    kw = lambda kind, s: dict(alpha=1.0, beta=1.0 / Ns[s], tol=1e-8) if kind == P.REQ_SOLVE else {}
+    alone = []
+    for i, (kind, s, n) in enumerate(reqs):
+        Y = torch.zeros_like(X[i])
+        srv.wait(srv.submit(kind, ids[s], X[i], Y, **kw(kind, s)))
+        alone.append(Y.cpu().numpy())
+    st0 = srv.stats()
+    Ymix = [torch.zeros_like(x) for x in X]
+    rids = [srv.submit(kind, ids[s], X[i], Ymix[i], **kw(kind, s))
+            for i, (kind, s, n) in enumerate(reqs)]
+    lat = [srv.wait(r) for r in rids]
+    torch.cuda.synchronize()
+    st1 = srv.stats()
+    for i, (kind, s, n) in enumerate(reqs):
+        a, m = alone[i], Ymix[i].cpu().numpy()
+        err = np.linalg.norm(m - a) / np.linalg.norm(a)
+        bound = 1e-6 if kind == P.REQ_SOLVE else (1e-12 if precs[s] == P.FP64 else 1e-5)
+        assert err <= bound, (i, kind, s, n, err)
+    launches = st1.launches - st0.launches
+    _say(f"[serve] mix: {len(reqs)} requests in {launches} launches, "
+         f"batched {st1.batched_requests - st0.batched_requests}, "
+         f"most concurrent {st1.max_concurrent}, "
+         f"p50 {np.percentile([q + r for q, r in lat], 50) / 1e3:.2f} ms")
+    assert launches < len(reqs)
+    assert st1.batched_requests > st0.batched_requests
+    assert st1.max_concurrent >= 2
+    assert st1.failed == 0 and st1.completed == 2 * len(reqs)
+    srv.close()
+
+
+def test_products_match_a_standalone_handle(P):
+    import torch
+    pts = W.uniform_points(9000, 3, 71)
+    k = P.make_kernel("inv_r")
+    srv = P.Server(max_concurrent=2, max_batch_cols=16, max_points=10000)
+    sid = srv.add_set(pts, k, 64, 1e-8)
+    H = P.HODLR(pts, k, 64, 1e-8)
+    X = _tensor(torch, 9000, 5, 3)
+    Y = torch.zeros_like(X)
+    srv.wait(srv.submit(P.REQ_MATVEC, sid, X, Y))
+    Yh = H.matvec(X)
+    torch.cuda.synchronize()
+    assert torch.allclose(Y, Yh, rtol=0, atol=1e-12 * float(Yh.abs().max()))
+    srv.close()
+
+
+def test_server_errors(P):
+    import torch
+    srv = P.Server(max_concurrent=1, max_batch_cols=4, max_points=4000)
+    sid = srv.add_set(W.uniform_points(3000, 2, 5), P.make_kernel("log"), 32, 1e-6,
+                      storage=P.BF16)
+    X = _tensor(torch, 3000, 8, 1)
+    Y = torch.zeros_like(X)
+    with pytest.raises(P.HodlrError, match="EINVAL"):
+        srv.submit(P.REQ_MATVEC, sid, X, Y)            # 8 columns > max_batch_cols
+    x1 = _tensor(torch, 3000, 1, 2)
+    with pytest.raises(P.HodlrError, match="EINVAL"):
+        srv.submit(P.REQ_SOLVE, sid, x1, torch.zeros_like(x1))   # BF16 set
+    with pytest.raises(P.HodlrError, match="EINVAL"):
+        srv.submit(P.REQ_MATVEC, sid + 1, x1, torch.zeros_like(x1))
+    big = srv.add_set(W.uniform_points(5000, 2, 6), P.make_kernel("log"), 32, 1e-6)
+    xb = _tensor(torch, 5000, 1, 3)
+    with pytest.raises(P.HodlrError, match="EINVAL"):
+        srv.submit(P.REQ_MATVEC, big, xb, torch.zeros_like(xb))   # N > max_points
+    srv.close()
+    small = P.Server(mem_budget_bytes=64 << 20, max_concurrent=1, max_batch_cols=2,
+                     max_points=1 << 16)
+    with pytest.raises(P.HodlrError, match="ENOMEM"):
+        small.add_set(W.uniform_points(60000, 3, 9), P.make_kernel("inv_r"), 64, 1e-10)
+    small.close()

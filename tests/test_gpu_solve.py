@@ -129,11 +129,12 @@ def test_solve_argument_errors(P, orc):
     pts = W.uniform_points(3000, 3, 3)
     H64 = P.HODLR(pts, P.make_kernel("inv_r"), 64, 1e-8)
     H32 = P.HODLR(pts, P.make_kernel("inv_r"), 64, 1e-8, storage=P.FP32)
+    H16 = P.HODLR(pts, P.make_kernel("inv_r"), 64, 1e-8, storage=P.BF16)
     Hx = P.HODLR(W.uniform_points(2000, 3, 4), P.make_kernel("inv_r"), 64, 1e-8)
     F = torch.ones(3000, dtype=torch.float64, device="cuda")
     U = torch.zeros_like(F)
     with pytest.raises(RuntimeError, match="EINVAL"):
-        P.hodlr_solve(H32.h, H64.h, 1.0, 1.0, F, U)          # hi must be FP64
+        P.hodlr_solve(H16.h, H64.h, 1.0, 1.0, F, U)          # hi applied in FP64: not BF16
     with pytest.raises(RuntimeError, match="EINVAL"):
         P.hodlr_solve(H64.h, Hx.h, 1.0, 1.0, F, U)           # different point sets
     bad = P.default_solve_opts()

@@ -12,7 +12,8 @@ and mixed (FP32 factors, FP32 arithmetic).  `value` is the FP64 throughput;
 the mixed figures are in `mixed`.  `multi_rhs` times the matrix-core path on
 its own workload (2^19 points in 4D, 1/r^2, 32 right-hand sides, BF16
 factors); `solve` times GMRES with FP64 iterative refinement on the 2^20-point
-Gaussian-mixture workload.  Prints one JSON line.
+Gaussian-mixture workload; `serve` reports p50/p99 latency of a Poisson
+request stream on resident point sets.  Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -197,6 +198,72 @@ def solve_bench(P, torch, W, n_override=0):
     }
 
 
+def serve_bench(P, torch, W, full=False):
+    """Serving: resident point sets (N log-uniform, d in {2,3}, kernels log r,
+    1/r, Gaussian h=0.5 drawn uniformly, FP32 factors, leaf 64, ACA 1e-8);
+    requests half products (nrhs 1..64) and half solves of (I + K/N) u = f
+    to 1e-8, arriving as a Poisson stream at 70% of the capacity measured
+    with all requests submitted at once.  Latency = queueing + running."""
+    nsets, nreq, nmax = (64, 256, 18) if full else (16, 128, 16)
+    g = W.rng(5)
+    srv = P.Server(max_concurrent=8, max_batch_cols=64, max_points=1 << nmax)
+    kinds = ["log", "inv_r", "gauss"]
+    sets = []
+    t0 = time.perf_counter()
+    for i in range(nsets):
+        N = int(round(2.0 ** g.uniform(14, nmax)))
+        d = int(g.integers(2, 4))
+        kn = kinds[int(g.integers(0, 3))]
+        pts = W.uniform_points(N, d, 500 + i)
+        k = P.make_kernel(kn, h=0.5, diag=1.0 if kn == "gauss" else 0.0)
+        sets.append((srv.add_set(pts, k, 64, 1e-8, storage=P.FP32), N))
+    build = time.perf_counter() - t0
+    reqs = []
+    for i in range(nreq):
+        s = int(g.integers(0, nsets))
+        if g.random() < 0.5:
+            reqs.append((P.REQ_MATVEC, s, int(g.integers(1, 65))))
+        else:
+            reqs.append((P.REQ_SOLVE, s, 1))
+    X = []
+    for i, (kind, s, n) in enumerate(reqs):
+        N = sets[s][1]
+        X.append(torch.tensor(W.rng(900 + i).standard_normal((n, N)), device="cuda").t()
+                 if n > 1 else torch.tensor(W.rng(900 + i).standard_normal(N), device="cuda"))
+    Y = [torch.zeros_like(x) for x in X]
+
+    def run(rate):
+        t_start = time.perf_counter()
+        arr = np.cumsum(W.rng(11).exponential(1.0 / rate, size=nreq)) if rate else np.zeros(nreq)
+        ids = []
+        for i, (kind, s, n) in enumerate(reqs):
+            while time.perf_counter() - t_start < arr[i]:
+                pass
+            kw = dict(alpha=1.0, beta=1.0 / sets[s][1], tol=1e-8) if kind == P.REQ_SOLVE else {}
+            ids.append(srv.submit(kind, sets[s][0], X[i], Y[i], **kw))
+        lat = np.array([sum(srv.wait(r)) for r in ids]) / 1e3   # ms
+        return time.perf_counter() - t_start, lat
+
+    run(None)   # warm-up
+    wall0, _ = run(None)
+    cap = nreq / wall0
+    st0 = srv.stats()
+    wall, lat = run(0.7 * cap)
+    st1 = srv.stats()
+    cols = sum(n * sets[s][1] for kind, s, n in reqs if kind == P.REQ_MATVEC)
+    srv.close()
+    return {
+        "sets": nsets, "requests": nreq, "N_range": [14, nmax], "storage": "fp32 factors",
+        "capacity_req_per_s": cap, "arrival_rate_req_per_s": 0.7 * cap,
+        "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+        "throughput_req_per_s": nreq / wall, "matvec_N_nrhs_per_s": cols / wall,
+        "launches": int(st1.launches - st0.launches),
+        "batched_requests": int(st1.batched_requests - st0.batched_requests),
+        "max_concurrent": int(st1.max_concurrent), "failed": int(st1.failed),
+        "build_s": round(build, 1),
+    }
+
+
 def factor_bytes(info, elem):
     return sum(info.factor_elems[l] for l in range(1, info.kappa + 1)) * elem
 
@@ -255,6 +322,9 @@ def main():
                     help="skip the 32-RHS BF16 matrix-core workload")
     ap.add_argument("--multi-rhs-n", type=int, default=0, help="override its N")
     ap.add_argument("--no-solve", action="store_true", help="skip the GMRES-IR solve")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving measurement")
+    ap.add_argument("--serve-full", action="store_true",
+                    help="serving with 64 sets up to 2^18 points and 256 requests")
     ap.add_argument("--solve-n", type=int, default=0, help="override the solve's N")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain device copy of known size (counter calibration)")
@@ -353,6 +423,10 @@ def main():
     if not args.no_solve:
         solve = solve_bench(P, torch, W, args.solve_n)
 
+    serve = None
+    if not args.no_serve:
+        serve = serve_bench(P, torch, W, args.serve_full)
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu, crow, cb = cpu_baseline(w, pts, q, args.level_rule)
@@ -409,6 +483,7 @@ def main():
         "mixed": mixed,
         "multi_rhs": mrhs,
         "solve": solve,
+        "serve": serve,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))

@@ -264,6 +264,15 @@ def serve_bench(P, torch, W, full=False):
     }
 
 
+def class_gbs(info, cls_ms, sf, sc):
+    """achieved GB/s of every block class (algorithmic bytes over its time)"""
+    out = []
+    for c in range(NCLASS):
+        nb = info.class_factor_elems[c] * sf + info.class_vector_elems[c] * sc
+        out.append(round(nb / (cls_ms[c] * 1e-3) / 1e9, 1) if cls_ms[c] > 0 and nb else 0.0)
+    return out
+
+
 def factor_bytes(info, elem):
     return sum(info.factor_elems[l] for l in range(1, info.kappa + 1)) * elem
 
@@ -399,6 +408,7 @@ def main():
             "build_s": round(build32, 2),
             "speedup_vs_fp64": (N / (wall32 / args.steps)) / (N / (wall / args.steps)),
             "class_ms": [round(float(v), 4) for v in cls32.mean(axis=0)],
+            "class_gbs": class_gbs(info32, cls32.mean(axis=0), 4, 4),
             "roofline": roofline(info32, cls32.mean(axis=0), 4, 4),
             "apply_roofline": {"achieved": fb32 / ((st32[1] + st32[2]) * 1e-3) / 1e9,
                                "frac": fb32 / ((st32[1] + st32[2]) * 1e-3) / 1e9 / HBM_PEAK_GBS},
@@ -475,6 +485,7 @@ def main():
         "near_pairs": int(info.near_pairs),
         "class_ms": [round(float(v), 4) for v in cls_ms],
         "class_kernels": CLASS_KERNELS,
+        "class_gbs": class_gbs(info, cls_ms, 8, 8),
         "roofline": roof64,
         "apply_roofline": {"achieved": apply_gbs, "frac": apply_gbs / HBM_PEAK_GBS,
                            "bytes": int(fb64), "what": "all stored factors once over stages 2+3"},

@@ -795,7 +795,7 @@ constexpr int TG = 256;
 constexpr int kNearTile = 256;         // sources per LDS tile
 constexpr int kNearTileRanges = 1024;  // near boxes a tiled leaf may have
 
-template <typename XT, typename C, int NR>
+template <typename XT, typename C, int NR, int KIND = -1>
 __global__ __launch_bounds__(TG) void k_gather_near(
     const NearItem* __restrict__ items, const SegRef* __restrict__ lseg,
     const int2* __restrict__ nrng, int kappa, const double* __restrict__ pts, int64_t N, int d,
@@ -825,8 +825,18 @@ __global__ __launch_bounds__(TG) void k_gather_near(
         // then every lane reads them as broadcasts
         __shared__ int s_pre[kNearTileRanges + 1], s_rs[kNearTileRanges];
         __shared__ int s_j[kNearTile];
-        __shared__ double s_pt[4][kNearTile];
+        __shared__ C s_pt[4][kNearTile];
         __shared__ C s_x[NR][kNearTile];
+        // coordinates in the compute type: FP64 as they are; FP32 relative to
+        // the leaf's first point, so that differences of nearby points keep
+        // their relative accuracy (zero beyond d)
+        double ref[4];
+        C xc[4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+            ref[a] = (sizeof(C) == 4 && a < d) ? pts[a * N + it.leaf0] : 0.0;
+            xc[a] = (active && a < d) ? (C)(xi[a] - ref[a]) : (C)0;
+        }
         for (int e = threadIdx.x; e < it.nn; e += TG) {
             const int2 rg = nrng[it.nb0 + e];
             s_rs[e] = rg.x;
@@ -858,7 +868,8 @@ __global__ __launch_bounds__(TG) void k_gather_near(
                 }
                 const int j = s_rs[lo] + (sidx - s_pre[lo]);
                 s_j[q] = j;
-                for (int a = 0; a < d; ++a) s_pt[a][q] = pts[a * N + j];
+#pragma unroll
+                for (int a = 0; a < 4; ++a) s_pt[a][q] = a < d ? (C)(pts[a * N + j] - ref[a]) : (C)0;
 #pragma unroll
                 for (int c = 0; c < NR; ++c) s_x[c][q] = c < nc ? x[(int64_t)(c0 + c) * N + j] : (C)0;
             }
@@ -871,11 +882,12 @@ __global__ __launch_bounds__(TG) void k_gather_near(
                         kij = (C)kp.diag;
                     } else {
                         C r2 = 0;
-                        for (int a = 0; a < d; ++a) {
-                            const C dx = (C)(xi[a] - s_pt[a][q]);
+#pragma unroll
+                        for (int a = 0; a < 4; ++a) {
+                            const C dx = xc[a] - s_pt[a][q];
                             r2 += dx * dx;
                         }
-                        kij = kfun(kp, r2);
+                        kij = kfun_k<KIND>(kp, r2);
                     }
 #pragma unroll
                     for (int c = 0; c < NR; ++c) acc[c] += kij * s_x[c][q];
@@ -896,7 +908,7 @@ __global__ __launch_bounds__(TG) void k_gather_near(
                         const C dx = (C)(xi[a] - pts[a * N + j]);
                         r2 += dx * dx;
                     }
-                    kij = kfun(kp, r2);
+                    kij = kfun_k<KIND>(kp, r2);
                 }
 #pragma unroll
                 for (int c = 0; c < NR; ++c)
@@ -1485,9 +1497,31 @@ void run_matvec(hodlr_t h, const XT* X, int64_t ldx, int nrhs, XT* Y, int64_t ld
         HIP_CHECK(hipGetLastError());
         if (ev && c0 == 0) HIP_CHECK(hipEventRecord(ev[3], s));
         }
-        k_gather_near<XT, C, NR><<<(unsigned)h->n_near_items, TG, 0, s>>>(
-            h->near_items, h->leaf_seg, h->near_rng, h->kappa, h->pts, N, h->d, h->kp, x,
-            contrib, CT, h->perm, nrhs, c0, Y, ldy, nullptr);
+        if constexpr (NR == 1) {
+            // one right-hand side: the kernel function fixed at compile time
+            switch (h->kp.kind) {
+#define HODLR_GATHER(K)                                                                         \
+    case K:                                                                                     \
+        k_gather_near<XT, C, NR, K><<<(unsigned)h->n_near_items, TG, 0, s>>>(                   \
+            h->near_items, h->leaf_seg, h->near_rng, h->kappa, h->pts, N, h->d, h->kp, x,       \
+            contrib, CT, h->perm, nrhs, c0, Y, ldy, nullptr);                                   \
+        break;
+                HODLR_GATHER(HODLR_K_LOG)
+                HODLR_GATHER(HODLR_K_INV_R)
+                HODLR_GATHER(HODLR_K_INV_R2)
+                HODLR_GATHER(HODLR_K_GAUSS)
+                HODLR_GATHER(HODLR_K_EXP)
+                HODLR_GATHER(HODLR_K_R)
+                HODLR_GATHER(HODLR_K_SIN)
+                default:
+                HODLR_GATHER(HODLR_K_INV_SQRT1P)
+#undef HODLR_GATHER
+            }
+        } else {
+            k_gather_near<XT, C, NR><<<(unsigned)h->n_near_items, TG, 0, s>>>(
+                h->near_items, h->leaf_seg, h->near_rng, h->kappa, h->pts, N, h->d, h->kp, x,
+                contrib, CT, h->perm, nrhs, c0, Y, ldy, nullptr);
+        }
         HIP_CHECK(hipGetLastError());
     }
     if (ev) HIP_CHECK(hipEventRecord(ev[4], s));

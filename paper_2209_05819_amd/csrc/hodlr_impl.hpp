@@ -40,12 +40,25 @@ struct KParams {
     double diag;
 };
 
+// 1/sqrt(x), x > 0, in FP64: the hardware estimate refined by two Newton
+// steps y <- y + y (1 - x y^2) / 2, each of which roughly doubles the number
+// of correct bits.
+__device__ __forceinline__ double rsqrt_fp64(double x) {
+    double y = __builtin_amdgcn_rsq(x);
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        const double r = fma(-(x * y), y, 1.0);
+        y = fma(0.5 * y, r, y);
+    }
+    return y;
+}
+
 // r2 = |x - y|^2; returns scale * f(r).  FP64 and FP32 variants.
 __device__ __forceinline__ double kfun(const KParams& k, double r2) {
     double f;
     switch (k.kind) {
     case HODLR_K_LOG: f = 0.5 * log(r2); break;
-    case HODLR_K_INV_R: f = 1.0 / sqrt(r2); break;
+    case HODLR_K_INV_R: f = rsqrt_fp64(r2); break;
     case HODLR_K_INV_R2: f = 1.0 / r2; break;
     case HODLR_K_GAUSS: f = exp(-r2 * k.inv_h2); break;
     case HODLR_K_EXP: f = exp(-sqrt(r2) * k.inv_h); break;
@@ -69,6 +82,19 @@ __device__ __forceinline__ float kfun(const KParams& k, float r2) {
     default: f = rsqrtf(1.0f + sqrtf(r2)); break;
     }
     return (float)k.scale * f;
+}
+
+// the same with the kernel function fixed at compile time (KIND < 0: chosen
+// at run time)
+template <int KIND, typename T>
+__device__ __forceinline__ T kfun_k(const KParams& k, T r2) {
+    if constexpr (KIND < 0) {
+        return kfun(k, r2);
+    } else {
+        KParams kk = k;
+        kk.kind = KIND;   // a constant: the switch folds away
+        return kfun(kk, r2);
+    }
 }
 
 // A device address held as an integer, as a pointer into the global address

@@ -86,10 +86,15 @@ typedef struct {
     int max_rank;         /* cap on every ACA rank; 0 = min(|I|,|J|) */
     int skip_aca;         /* 1: tree and lists only; factors come from hodlr_import_factors */
     size_t mem_budget_bytes;  /* cap on device memory held by the handle; 0 = none */
+    /* admissibility (sec. 5): adjacent boxes sharing a hyper-surface of
+     * dimension <= adm_dim are compressed, far ones always; -1 = far field
+     * only (strong admissibility of H-matrices), 0 = HODLRdD (vertex sharing,
+     * the default), d-1 = every pair (weak admissibility of HODLR) */
+    int adm_dim;
 } hodlr_opts;
 
 /* Defaults: level_rule 1, bounding cube, FP64 storage, symmetric 1,
- * max_rank 0, skip_aca 0, no budget. */
+ * max_rank 0, skip_aca 0, no budget, adm_dim 0. */
 void hodlr_default_opts(hodlr_opts* opts);
 
 /* Build the HODLRdD representation (Alg. "HODLRdD Initialization"): the
@@ -98,7 +103,7 @@ void hodlr_default_opts(hodlr_opts* opts);
  * HODLRdD admissibility definition), and the ACA factors of every admissible
  * block (eq. keq1) to relative tolerance tol.
  *   points    host pointer, N x d row-major FP64, user order; copied.
- *   N >= 1, 1 <= d <= 8, leaf_size >= 1, 0 <= tol < 1.
+ *   N >= 1, 1 <= d <= 8, leaf_size >= 1, 0 <= tol < 1, -1 <= opts->adm_dim <= d-1.
  *   kernel    host pointer; h > 0 for GAUSS and EXP.
  *   opts      host pointer or NULL for the defaults.
  *   stream    work is queued on it; the call returns after the build finished.

@@ -52,6 +52,9 @@ def lib():
     if _lib is None:
         build(force=False)
         L = C.CDLL(LIB)
+        L.ohodlr_create_adm.restype = _P
+        L.ohodlr_create_adm.argtypes = [_P, _i64, C.c_int, C.c_int, _P, C.c_double, C.c_int,
+                                        C.c_int, C.c_int, C.POINTER(C.c_int)]
         L.ohodlr_create.restype = _P
         L.ohodlr_create.argtypes = [_P, _i64, C.c_int, C.c_int, _P, C.c_double,
                                     C.c_int, C.c_int, C.POINTER(C.c_int)]
@@ -151,20 +154,19 @@ def aca_dense(M: np.ndarray, tol: float, max_rank: int = 0):
 class OracleHODLR:
     """Tree, lists, ACA factors and matvec of the HODLRdD method (FP64, CPU)."""
 
-    def __init__(self, points, leaf: int, level_rule: int = 0, domain=None):
+    def __init__(self, points, leaf: int, level_rule: int = 0, domain=None, adm_dim: int = 0):
         P = np.ascontiguousarray(points, dtype=np.float64)
         self.points = P
         self.N, self.d = P.shape
         st = C.c_int(0)
+        lo = np.zeros(8)
         if domain is None:
-            lo = np.zeros(8)
-            h = lib().ohodlr_create(_ptr(P), self.N, self.d, 0, _ptr(lo), 1.0, leaf, level_rule,
-                                    C.byref(st))
+            h = lib().ohodlr_create_adm(_ptr(P), self.N, self.d, 0, _ptr(lo), 1.0, leaf,
+                                        level_rule, adm_dim, C.byref(st))
         else:
-            lo = np.zeros(8)
             lo[: self.d] = np.asarray(domain[0], dtype=np.float64)
-            h = lib().ohodlr_create(_ptr(P), self.N, self.d, 1, _ptr(lo), float(domain[1]), leaf,
-                                    level_rule, C.byref(st))
+            h = lib().ohodlr_create_adm(_ptr(P), self.N, self.d, 1, _ptr(lo), float(domain[1]),
+                                        leaf, level_rule, adm_dim, C.byref(st))
         if not h:
             raise ValueError(f"oracle tree build failed (status {st.value})")
         self.h = h

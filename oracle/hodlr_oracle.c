@@ -86,6 +86,7 @@ typedef struct {
 struct ohodlr_s {
     int64_t N;
     int d, Lmax, kappa, leaf, rule;
+    int adm;            /* largest shared hyper-surface dimension that is admissible */
     double lo[8], side;
     double* pts_user;   /* N*d user order */
     double* pts;        /* N*d tree order */
@@ -148,13 +149,20 @@ static int64_t level_max_count(const ohodlr* h, int l)
     return best;
 }
 
-/* HODLRdD interaction list membership (clan intersected with vertex-sharing
- * or far-field; the parent's neighbours contribute children only when they
- * share a hyper-surface of dimension >= 1 with the parent -- see the reading
- * of "clan" documented with the library). */
-static int in_il(const int32_t* A, const int32_t* B, int d)
+/* Interaction list membership at one level (table of notations and the
+ * admissibility definitions of sec. 5).  Two distinct boxes are admissible
+ * when they are far apart (at least one box between them) or adjacent and
+ * sharing a hyper-surface of dimension <= t (the number of equal integer
+ * coordinates): t = 0 is the HODLRdD condition (vertex sharing), t = -1
+ * keeps only the far field (strong admissibility of H-matrices), t = d-1
+ * admits every pair (weak admissibility of HODLR).  A pair enters the list
+ * of the level where it first becomes admissible: its parents must not be
+ * admissible (equal, or adjacent sharing a hyper-surface of dimension > t).
+ * With t = 0 the parents' condition is the "clan" read with d' >= 1 (the
+ * reading documented with the library). */
+static int in_il(const int32_t* A, const int32_t* B, int d, int t)
 {
-    int same = 1, par_max = 0, par_eq = 0, all_one = 1, chd_max = 0;
+    int same = 1, par_max = 0, par_eq = 0, chd_max = 0, chd_eq = 0;
     for (int a = 0; a < d; ++a) {
         if (A[a] != B[a]) same = 0;
         int32_t P = A[a] >> 1, Q = B[a] >> 1;
@@ -162,21 +170,18 @@ static int in_il(const int32_t* A, const int32_t* B, int d)
         if (dp > par_max) par_max = dp;
         if (P == Q) ++par_eq;
         int dc = abs(A[a] - B[a]);
-        if (dc != 1) all_one = 0;
         if (dc > chd_max) chd_max = dc;
+        if (dc == 0) ++chd_eq;
     }
     if (same) return 0;
-    /* clan: parents equal (siblings) or parents adjacent sharing >= 1 coordinate */
-    int clan = (par_max == 0) || (par_max == 1 && par_eq >= 1);
-    if (!clan) return 0;
-    int vertex = all_one;
-    int far = chd_max >= 2;
-    return vertex || far;
+    int parents_open = (par_max == 0) || (par_max == 1 && par_eq > t);
+    if (!parents_open) return 0;
+    return chd_max >= 2 || (chd_max == 1 && chd_eq <= t);
 }
 
-/* near field at the leaves: the box itself and boxes sharing a hyper-surface
- * of dimension 1..d-1 (adjacent with at least one equal coordinate). */
-static int in_near(const int32_t* A, const int32_t* B, int d)
+/* near field at the leaves: the box itself and the adjacent boxes that are
+ * not admissible (sharing a hyper-surface of dimension > t). */
+static int in_near(const int32_t* A, const int32_t* B, int d, int t)
 {
     int mx = 0, eq = 0;
     for (int a = 0; a < d; ++a) {
@@ -185,7 +190,7 @@ static int in_near(const int32_t* A, const int32_t* B, int d)
         if (dc == 0) ++eq;
     }
     if (mx == 0) return 1;
-    return mx == 1 && eq >= 1;
+    return mx == 1 && eq > t;
 }
 
 static void build_lists(ohodlr* h, int l)
@@ -199,7 +204,7 @@ static void build_lists(ohodlr* h, int l)
     for (int64_t A = 0; A < nb; ++A) {
         int64_t c = 0;
         for (int64_t B = 0; B < nb; ++B)
-            if (in_il(L->coord + A * d, L->coord + B * d, d)) ++c;
+            if (in_il(L->coord + A * d, L->coord + B * d, d, h->adm)) ++c;
         L->il_ptr[A + 1] = c;
     }
     for (int64_t A = 0; A < nb; ++A) L->il_ptr[A + 1] += L->il_ptr[A];
@@ -209,7 +214,7 @@ static void build_lists(ohodlr* h, int l)
     for (int64_t A = 0; A < nb; ++A) {
         int64_t c = L->il_ptr[A];
         for (int64_t B = 0; B < nb; ++B)
-            if (in_il(L->coord + A * d, L->coord + B * d, d)) L->il_col[c++] = (int32_t)B;
+            if (in_il(L->coord + A * d, L->coord + B * d, d, h->adm)) L->il_col[c++] = (int32_t)B;
     }
     L->rank = (int32_t*)malloc(sizeof(int32_t) * (nnz ? nnz : 1));
     L->U = (double**)calloc(nnz ? nnz : 1, sizeof(double*));
@@ -227,7 +232,7 @@ static void build_near(ohodlr* h)
     for (int64_t A = 0; A < nb; ++A) {
         int64_t c = 0;
         for (int64_t B = 0; B < nb; ++B)
-            if (in_near(L->coord + A * d, L->coord + B * d, d)) ++c;
+            if (in_near(L->coord + A * d, L->coord + B * d, d, h->adm)) ++c;
         h->near_ptr[A + 1] = c;
     }
     for (int64_t A = 0; A < nb; ++A) h->near_ptr[A + 1] += h->near_ptr[A];
@@ -237,7 +242,7 @@ static void build_near(ohodlr* h)
     for (int64_t A = 0; A < nb; ++A) {
         int64_t c = h->near_ptr[A];
         for (int64_t B = 0; B < nb; ++B)
-            if (in_near(L->coord + A * d, L->coord + B * d, d)) h->near_col[c++] = (int32_t)B;
+            if (in_near(L->coord + A * d, L->coord + B * d, d, h->adm)) h->near_col[c++] = (int32_t)B;
     }
 }
 
@@ -245,12 +250,20 @@ ohodlr* ohodlr_create(const double* points, int64_t N, int d, int has_domain,
                       const double* lo, double side, int leaf, int level_rule,
                       int* status)
 {
+    return ohodlr_create_adm(points, N, d, has_domain, lo, side, leaf, level_rule, 0, status);
+}
+
+ohodlr* ohodlr_create_adm(const double* points, int64_t N, int d, int has_domain,
+                          const double* lo, double side, int leaf, int level_rule, int adm_dim,
+                          int* status)
+{
     *status = ORK_EINVAL;
     if (N < 1 || d < 1 || d > 8 || leaf < 1) return NULL;
+    if (adm_dim < -1 || adm_dim > d - 1) return NULL;
     for (int64_t i = 0; i < N * d; ++i)
         if (!isfinite(points[i])) return NULL;
     ohodlr* h = (ohodlr*)calloc(1, sizeof(ohodlr));
-    h->N = N; h->d = d; h->leaf = leaf; h->rule = level_rule;
+    h->N = N; h->d = d; h->leaf = leaf; h->rule = level_rule; h->adm = adm_dim;
     h->Lmax = 63 / d < 30 ? 63 / d : 30;
 
     /* computational hyper-cube C (sec. 5.2) */

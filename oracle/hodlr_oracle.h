@@ -59,6 +59,12 @@ void ohodlr_kernel_block(const ork_kernel* k, const double* X, int64_t m,
 ohodlr* ohodlr_create(const double* points, int64_t N, int d, int has_domain,
                       const double* lo, double side, int leaf, int level_rule,
                       int* status);
+/* The same with another admissibility: adjacent boxes sharing a hyper-surface
+ * of dimension <= adm_dim are admissible (-1: far field only; 0: HODLRdD,
+ * as ohodlr_create; d-1: every pair, HODLR). */
+ohodlr* ohodlr_create_adm(const double* points, int64_t N, int d, int has_domain,
+                          const double* lo, double side, int leaf, int level_rule, int adm_dim,
+                          int* status);
 void ohodlr_destroy(ohodlr* h);
 
 int     ohodlr_kappa(const ohodlr* h);

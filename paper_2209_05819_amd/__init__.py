@@ -37,7 +37,7 @@ class Opts(C.Structure):
     _fields_ = [("level_rule", C.c_int), ("has_domain", C.c_int),
                 ("domain_lo", C.c_double * 8), ("domain_side", C.c_double),
                 ("storage", C.c_int), ("symmetric", C.c_int), ("max_rank", C.c_int),
-                ("skip_aca", C.c_int), ("mem_budget_bytes", C.c_size_t)]
+                ("skip_aca", C.c_int), ("mem_budget_bytes", C.c_size_t), ("adm_dim", C.c_int)]
 
 
 class Info(C.Structure):
@@ -331,9 +331,10 @@ class HODLR:
 
     def __init__(self, points, kernel: Kernel, leaf_size: int, tol: float, *, level_rule=1,
                  domain=None, storage=FP64, symmetric=True, max_rank=0, skip_aca=False,
-                 mem_budget_bytes=0, stream=None):
+                 mem_budget_bytes=0, adm_dim=0, stream=None):
         o = default_opts()
         o.level_rule = level_rule
+        o.adm_dim = int(adm_dim)
         if domain is not None:
             o.has_domain = 1
             lo = np.asarray(domain[0], dtype=np.float64)

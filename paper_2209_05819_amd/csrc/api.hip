@@ -81,6 +81,7 @@ void hodlr_default_opts(hodlr_opts* o) {
     o->max_rank = 0;
     o->skip_aca = 0;
     o->mem_budget_bytes = 0;
+    o->adm_dim = 0;
 }
 
 hodlr_status hodlr_build(const double* points, int64_t N, int d, const hodlr_kernel* kernel,
@@ -104,6 +105,8 @@ hodlr_status hodlr_build(const double* points, int64_t N, int d, const hodlr_ker
     if (o.has_domain && !(o.domain_side > 0.0 && std::isfinite(o.domain_side)))
         return set_error(HODLR_EINVAL, "domain_side must be > 0");
     if (o.max_rank < 0) return set_error(HODLR_EINVAL, "max_rank must be >= 0");
+    if (o.adm_dim < -1 || o.adm_dim > d - 1)
+        return set_error(HODLR_EINVAL, "adm_dim must be in -1 .. d-1");
 
     hodlr_t h = new (std::nothrow) hodlr_handle_s();
     if (!h) return set_error(HODLR_ENOMEM, "host allocation failed");

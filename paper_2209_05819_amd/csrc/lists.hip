@@ -41,7 +41,7 @@ __device__ __forceinline__ int64_t lower_bound(const uint64_t* __restrict__ key,
 }
 
 // count (ptr == nullptr: out[A] = count) or fill (out = columns)
-__global__ void k_il(int level, int d, int64_t nb, const uint64_t* __restrict__ key,
+__global__ void k_il(int level, int d, int adm, int64_t nb, const uint64_t* __restrict__ key,
                      const int32_t* __restrict__ coord, const int64_t* __restrict__ ptr,
                      int32_t* __restrict__ out) {
     int64_t A = blockIdx.x * (int64_t)T + threadIdx.x;
@@ -58,28 +58,32 @@ __global__ void k_il(int level, int d, int64_t nb, const uint64_t* __restrict__ 
     const int64_t base = ptr ? ptr[A] : 0;
     for (int t = 0; t < ncand; ++t) {
         int tt = t;
-        bool ok = true, zero_any = false;
+        bool ok = true;
+        int nzero = 0;
         for (int k = 0; k < d; ++k) {
             int dl = tt % 3 - 1;
             tt /= 3;
             Q[k] = P[k] + dl;
             if (Q[k] < 0 || Q[k] >= np) ok = false;
-            if (dl == 0) zero_any = true;
+            if (dl == 0) ++nzero;
         }
-        if (!ok || !zero_any) continue;
+        // the parents' pair must not be admissible itself: the same parent,
+        // or neighbours sharing a hyper-surface of dimension > adm
+        if (!ok || nzero <= adm) continue;
         const uint64_t kq = interleave(Q, level - 1, d);
         const int64_t lo = lower_bound(key, nb, kq << d);
         const int64_t hi = lower_bound(key, nb, (kq + 1) << d);
         for (int64_t B = lo; B < hi; ++B) {
             if (B == A) continue;
-            bool vertex = true;
-            int mx = 0;
+            int mx = 0, eq = 0;
             for (int k = 0; k < d; ++k) {
                 int dc = abs(coord[B * d + k] - a[k]);
-                if (dc != 1) vertex = false;
                 mx = max(mx, dc);
+                if (dc == 0) ++eq;
             }
-            if (vertex || mx >= 2) {
+            // admissible: far apart, or adjacent sharing a hyper-surface of
+            // dimension <= adm (adm = 0: vertex sharing)
+            if (mx >= 2 || (mx == 1 && eq <= adm)) {
                 if (ptr) out[base + cnt] = (int32_t)B;
                 ++cnt;
             }
@@ -88,7 +92,7 @@ __global__ void k_il(int level, int d, int64_t nb, const uint64_t* __restrict__ 
     if (!ptr) out[A] = (int32_t)cnt;
 }
 
-__global__ void k_near(int level, int d, int64_t nb, const uint64_t* __restrict__ key,
+__global__ void k_near(int level, int d, int adm, int64_t nb, const uint64_t* __restrict__ key,
                        const int32_t* __restrict__ coord, const int64_t* __restrict__ ptr,
                        int32_t* __restrict__ out) {
     int64_t A = blockIdx.x * (int64_t)T + threadIdx.x;
@@ -102,15 +106,17 @@ __global__ void k_near(int level, int d, int64_t nb, const uint64_t* __restrict_
     const int64_t base = ptr ? ptr[A] : 0;
     for (int t = 0; t < ncand; ++t) {
         int tt = t;
-        bool ok = true, zero_any = false;
+        bool ok = true;
+        int nzero = 0;
         for (int k = 0; k < d; ++k) {
             int dl = tt % 3 - 1;
             tt /= 3;
             B[k] = a[k] + dl;
             if (B[k] < 0 || B[k] >= ns) ok = false;
-            if (dl == 0) zero_any = true;
+            if (dl == 0) ++nzero;
         }
-        if (!ok || !zero_any) continue;
+        // the box itself and the adjacent boxes that are not admissible
+        if (!ok || nzero <= adm) continue;
         const uint64_t kb = interleave(B, level, d);
         const int64_t pos = lower_bound(key, nb, kb);
         if (pos < nb && key[pos] == kb) {
@@ -201,9 +207,11 @@ void build_csr(hodlr_t h, int level, bool near, int64_t** ptr_out, int32_t** col
     int32_t* off32 = (int32_t*)dalloc(h, sizeof(int32_t) * (nb + 1));
     int64_t* ptr = (int64_t*)dalloc(h, sizeof(int64_t) * (nb + 1));
     if (near)
-        k_near<<<nblk(nb, T), T, 0, s>>>(level, h->d, nb, Lv.key, Lv.coord, nullptr, cnt);
+        k_near<<<nblk(nb, T), T, 0, s>>>(level, h->d, h->opts.adm_dim, nb, Lv.key, Lv.coord, nullptr,
+                                         cnt);
     else
-        k_il<<<nblk(nb, T), T, 0, s>>>(level, h->d, nb, Lv.key, Lv.coord, nullptr, cnt);
+        k_il<<<nblk(nb, T), T, 0, s>>>(level, h->d, h->opts.adm_dim, nb, Lv.key, Lv.coord, nullptr,
+                                       cnt);
     HIP_CHECK(hipGetLastError());
     // row counts fit in 32 bits; the offsets are widened before they can overflow
     int64_t* cnt64 = (int64_t*)dalloc(h, sizeof(int64_t) * (nb + 1));
@@ -219,9 +227,10 @@ void build_csr(hodlr_t h, int level, bool near, int64_t** ptr_out, int32_t** col
     int32_t* col = (int32_t*)dalloc(h, sizeof(int32_t) * std::max<int64_t>(nnz, 1));
     int32_t* tmp = (int32_t*)dalloc(h, sizeof(int32_t) * std::max<int64_t>(nnz, 1));
     if (near)
-        k_near<<<nblk(nb, T), T, 0, s>>>(level, h->d, nb, Lv.key, Lv.coord, ptr, tmp);
+        k_near<<<nblk(nb, T), T, 0, s>>>(level, h->d, h->opts.adm_dim, nb, Lv.key, Lv.coord, ptr,
+                                         tmp);
     else
-        k_il<<<nblk(nb, T), T, 0, s>>>(level, h->d, nb, Lv.key, Lv.coord, ptr, tmp);
+        k_il<<<nblk(nb, T), T, 0, s>>>(level, h->d, h->opts.adm_dim, nb, Lv.key, Lv.coord, ptr, tmp);
     HIP_CHECK(hipGetLastError());
     if (nnz > 0) segmented_sort_i32(tmp, col, nnz, nb, ptr, s);
     dfree(h, tmp);

@@ -36,7 +36,7 @@ def test_struct_layouts_match_header():
     import paper_2209_05819_amd as P
     # sizes implied by the C declarations on x86-64
     assert C.sizeof(P.Kernel) == 32
-    assert C.sizeof(P.Opts) == 4 * 2 + 8 * 8 + 8 + 4 * 4 + 8
+    assert C.sizeof(P.Opts) == 4 * 2 + 8 * 8 + 8 + 4 * 4 + 8 + 8
     assert P.Info.build_ms.offset + 32 == P.Info.mfma_proj_jobs.offset
     assert P.Info.mfma_proj_elems.offset + 8 == C.sizeof(P.Info)
     assert C.sizeof(P.SolveOpts) == 8 * 2 + 4 * 4
@@ -51,7 +51,7 @@ def test_default_opts_and_errors_without_gpu():
     if not os.path.exists(P.LIB_PATH):
         pytest.skip("library not built")
     o = P.default_opts()
-    assert o.symmetric == 1 and o.storage == P.FP64 and o.level_rule == 1
+    assert o.symmetric == 1 and o.storage == P.FP64 and o.level_rule == 1 and o.adm_dim == 0
     L = P.lib()
     # argument errors are reported before any device work
     st = L.hodlr_build(None, 10, 3, None, 8, 1e-6, None, None, None)

@@ -194,6 +194,90 @@ def test_one_dimension_is_hodlr(orc):
 
 
 # ---------------------------------------------------------------------------
+# Other admissibility conditions (sec. 5: strong admissibility of H-matrices,
+# weak admissibility of HODLR, and the hyper-surface dimensions in between)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("d,N,leaf,adm", [
+    (2, 1500, 8, -1), (2, 1500, 8, 1), (3, 1500, 6, -1), (3, 1500, 6, 1), (3, 1200, 5, 2),
+    (4, 900, 3, -1), (4, 900, 3, 2),
+])
+def test_admissibility_variants_cover_every_pair_once(orc, d, N, leaf, adm):
+    P = W.uniform_points(N, d, seed=40 + d)
+    o = orc.OracleHODLR(P, leaf, 0, adm_dim=adm)
+    assert o.kappa >= 2
+    cov = _cover(o)
+    assert cov.min() == 1 and cov.max() == 1
+
+
+@pytest.mark.parametrize("d", [2, 3])
+def test_all_pairs_admissible_is_hodlr(orc, d):
+    """adm_dim = d-1: every box interacts with all its siblings and the leaves
+    only with themselves, in any dimension (weak admissibility)."""
+    P = W.uniform_points(2000, d, 9)
+    o = orc.OracleHODLR(P, 16, 0, adm_dim=d - 1)
+    for l in range(1, o.kappa + 1):
+        start, key, coord = o.boxes(l)
+        ptr, col = o.il(l)
+        for A in range(len(start) - 1):
+            row = col[ptr[A]:ptr[A + 1]]
+            sib = [B for B in range(len(start) - 1)
+                   if B != A and np.all(coord[B] >> 1 == coord[A] >> 1)]
+            assert row.tolist() == sib
+    ptr, col = o.near()
+    assert np.all(col == np.arange(len(ptr) - 1))
+
+
+@pytest.mark.parametrize("d", [2, 3])
+def test_far_field_only_interior_counts(orc, d):
+    """adm_dim = -1 (strong admissibility): an interior box interacts with the
+    6^d - 3^d children of its parent's neighbours that are not adjacent to it,
+    and its near list is the 3^d adjacent boxes (itself included)."""
+    nside = {2: 16, 3: 8}[d]
+    g = (np.arange(nside) + 0.5) / nside
+    mesh = np.meshgrid(*([g] * d), indexing="ij")
+    P = np.stack([m.reshape(-1) for m in mesh], axis=1)
+    o = orc.OracleHODLR(P, 1, 0, domain=(np.zeros(d), 1.0), adm_dim=-1)
+    kap = o.kappa
+    for l in range(2, kap + 1):
+        start, key, coord = o.boxes(l)
+        ptr, col = o.il(l)
+        n = 2 ** l
+        for A in range(len(start) - 1):
+            par = coord[A] >> 1
+            if np.all(par >= 1) and np.all(par <= n // 2 - 2):
+                row = col[ptr[A]:ptr[A + 1]]
+                assert len(row) == 6 ** d - 3 ** d
+                assert all(np.max(np.abs(coord[B] - coord[A])) >= 2 for B in row)
+    start, key, coord = o.boxes(kap)
+    ptr, col = o.near()
+    n = 2 ** kap
+    for A in range(len(start) - 1):
+        if np.all(coord[A] >= 1) and np.all(coord[A] <= n - 2):
+            assert ptr[A + 1] - ptr[A] == 3 ** d
+
+
+@pytest.mark.parametrize("adm", [-1, 1])
+def test_admissibility_variants_matvec_within_tolerance(orc, adm):
+    P = W.uniform_points(1500, 2, 44)
+    k = orc.kernel("log")
+    q = W.rhs_uniform(1500, 1, 45)[:, 0]
+    o = orc.OracleHODLR(P, 16, 0, adm_dim=adm)
+    o.compress(k, 1e-9)
+    b = o.matvec(k, q)
+    bd = orc.direct(P, k, q)
+    # the per-block ACA estimate bounds the product's error only up to a
+    # modest factor (the same allowance as the GPU pipeline tests)
+    assert np.linalg.norm(b - bd) / np.linalg.norm(bd) <= 5e-9
+
+
+def test_admissibility_out_of_range_rejected(orc):
+    with pytest.raises(ValueError):
+        orc.OracleHODLR(W.uniform_points(100, 2, 1), 8, 0, adm_dim=2)
+    with pytest.raises(ValueError):
+        orc.OracleHODLR(W.uniform_points(100, 2, 1), 8, 0, adm_dim=-2)
+
+
+# ---------------------------------------------------------------------------
 # ACA (eq. keq1)
 # ---------------------------------------------------------------------------
 @pytest.mark.parametrize("m,n,k", [(60, 80, 5), (200, 150, 17), (300, 300, 40), (31, 400, 31)])

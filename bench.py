@@ -13,7 +13,8 @@ the mixed figures are in `mixed`.  `multi_rhs` times the matrix-core path on
 its own workload (2^19 points in 4D, 1/r^2, 32 right-hand sides, BF16
 factors); `solve` times GMRES with FP64 iterative refinement on the 2^20-point
 Gaussian-mixture workload; `serve` reports p50/p99 latency of a Poisson
-request stream on resident point sets.  Prints one JSON line.
+request stream on resident point sets; `admissibility` compares the
+admissibility conditions on a 4D workload.  Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -273,6 +274,49 @@ def class_gbs(info, cls_ms, sf, sc):
     return out
 
 
+def adm_bench(P, torch, W, N=1 << 15):
+    """The admissibility conditions side by side (the comparison of sec. 6.1:
+    4D, log r, ACA 1e-6): N points uniform in [-1,1]^4, leaf 128, one N(0,1)
+    right-hand side, FP64; per condition the build time, factor bytes,
+    largest rank, product time and error against the direct sum on 256
+    sampled rows."""
+    import oracle
+    pts = W.uniform_points(N, 4, 3)
+    q = W.rhs_normal(N, 1, 103)[:, 0]
+    k = P.make_kernel("log")
+    rows = np.sort(W.rng(203).choice(N, 256, replace=False))
+    oracle.build(force=False)
+    bd = oracle.direct(pts, oracle.kernel("log"), q, rows=rows)
+    X = torch.tensor(q, device="cuda")
+    out = []
+    for adm, name in ((-1, "far field only (H, strong)"), (0, "vertex sharing (HODLRdD)"),
+                      (1, "edges (d' <= 1)"), (2, "d' <= 2"), (3, "every pair (HODLR, weak)")):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        H = P.HODLR(pts, k, 128, 1e-6, domain=(np.full(4, -1.0), 2.0), adm_dim=adm)
+        torch.cuda.synchronize()
+        tb = time.perf_counter() - t0
+        info = H.info()
+        Y = H.matvec(X)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(5):
+            H.matvec(X, out=Y)
+        torch.cuda.synchronize()
+        tm = (time.perf_counter() - t0) / 5
+        y = Y.cpu().numpy()
+        out.append({
+            "adm_dim": adm, "condition": name, "build_s": round(tb, 3),
+            "factor_bytes": int(8 * sum(info.factor_elems[l] for l in range(1, info.kappa + 1))),
+            "rank_max": int(max(info.rank_max[l] for l in range(1, info.kappa + 1))),
+            "near_pairs": int(info.near_pairs), "matvec_ms": tm * 1e3,
+            "rel_err": float(np.linalg.norm(y[rows] - bd) / np.linalg.norm(bd)),
+        })
+        del H
+    return {"workload": f"{N} points uniform in [-1,1]^4, log r, leaf 128, ACA 1e-6, FP64",
+            "conditions": out}
+
+
 def factor_bytes(info, elem):
     return sum(info.factor_elems[l] for l in range(1, info.kappa + 1)) * elem
 
@@ -332,6 +376,8 @@ def main():
     ap.add_argument("--multi-rhs-n", type=int, default=0, help="override its N")
     ap.add_argument("--no-solve", action="store_true", help="skip the GMRES-IR solve")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving measurement")
+    ap.add_argument("--no-adm", action="store_true",
+                    help="skip the comparison of admissibility conditions")
     ap.add_argument("--serve-full", action="store_true",
                     help="serving with 64 sets up to 2^18 points and 256 requests")
     ap.add_argument("--solve-n", type=int, default=0, help="override the solve's N")
@@ -437,6 +483,10 @@ def main():
     if not args.no_serve:
         serve = serve_bench(P, torch, W, args.serve_full)
 
+    adm = None
+    if not args.no_adm:
+        adm = adm_bench(P, torch, W)
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu, crow, cb = cpu_baseline(w, pts, q, args.level_rule)
@@ -495,6 +545,7 @@ def main():
         "multi_rhs": mrhs,
         "solve": solve,
         "serve": serve,
+        "admissibility": adm,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))

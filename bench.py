@@ -9,7 +9,9 @@ level, near field evaluated on the fly, permutation back.
 
 Two precisions are timed on the same inputs: FP64 (factors and arithmetic)
 and mixed (FP32 factors, FP32 arithmetic).  `value` is the FP64 throughput;
-the mixed figures are in `mixed`.  `multi_rhs` times the matrix-core path on
+the mixed figures are in `mixed`; `skeleton` times the same product with
+the skeleton storage form (pivots and LU of K(sigma, tau), kernel evaluated
+on the fly).  `multi_rhs` times the matrix-core path on
 its own workload (2^19 points in 4D, 1/r^2, 32 right-hand sides, BF16
 factors); `solve` times GMRES with FP64 iterative refinement on the 2^20-point
 Gaussian-mixture workload; `serve` reports p50/p99 latency of a Poisson
@@ -317,6 +319,31 @@ def adm_bench(P, torch, W, N=1 << 15):
             "conditions": out}
 
 
+def skeleton_bench(P, torch, w, pts, q, steps, warmup, level_rule, bd, rows):
+    """The skeleton storage form on the main workload: FP64, the kernel
+    evaluated on the fly for K(I, tau) and K(sigma, J)."""
+    t0 = time.perf_counter()
+    H = P.HODLR(pts, P.make_kernel(w.kernel, h=w.h, diag=w.diag), w.leaf, w.tol,
+                domain=w.domain, level_rule=level_rule, skeleton=True)
+    torch.cuda.synchronize()
+    build = time.perf_counter() - t0
+    info = H.info()
+    X = torch.tensor(q, dtype=torch.float64, device="cuda")
+    Y = torch.empty_like(X)
+    wall, per, _, lat = time_matvecs(P, torch, H, X, Y, P.FP64, warmup, steps)
+    y = Y.cpu().numpy()
+    se = sum(info.factor_elems[l] for l in range(1, info.kappa + 1))
+    del H
+    return {
+        "value": w.N / (wall / steps), "unit": "N*nrhs/s", "ms_per_step": wall / steps * 1e3,
+        "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+        "stage_ms": [round(float(v), 4) for v in per.mean(axis=0)],
+        "stored_bytes": int(8 * se), "device_bytes": int(info.device_bytes),
+        "build_s": round(build, 2), "rel_err": rel_err_rows(y, bd, rows),
+        "dtype": "f64",
+    }
+
+
 def factor_bytes(info, elem):
     return sum(info.factor_elems[l] for l in range(1, info.kappa + 1)) * elem
 
@@ -376,6 +403,7 @@ def main():
     ap.add_argument("--multi-rhs-n", type=int, default=0, help="override its N")
     ap.add_argument("--no-solve", action="store_true", help="skip the GMRES-IR solve")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving measurement")
+    ap.add_argument("--no-skeleton", action="store_true", help="skip the skeleton form")
     ap.add_argument("--no-adm", action="store_true",
                     help="skip the comparison of admissibility conditions")
     ap.add_argument("--serve-full", action="store_true",
@@ -471,6 +499,11 @@ def main():
     if mixed is not None:
         mixed["rel_err"] = rel_err_rows(y32, bd, rows)
 
+    skel = None
+    if not args.no_skeleton:
+        skel = skeleton_bench(P, torch, w, pts, q, args.steps, args.warmup, args.level_rule, bd,
+                              rows)
+
     mrhs = None
     if not args.no_multi_rhs:
         mrhs = multi_rhs(P, torch, W, max(3, args.steps // 4), 1, args.multi_rhs_n)
@@ -542,6 +575,7 @@ def main():
         "matvec_roofline": {"achieved": matvec_gbs, "frac": matvec_gbs / HBM_PEAK_GBS,
                             "bytes": int(fb64 + vec_bytes)},
         "mixed": mixed,
+        "skeleton": skel,
         "multi_rhs": mrhs,
         "solve": solve,
         "serve": serve,

@@ -91,10 +91,19 @@ typedef struct {
      * only (strong admissibility of H-matrices), 0 = HODLRdD (vertex sharing,
      * the default), d-1 = every pair (weak admissibility of HODLR) */
     int adm_dim;
+    /* 1: store each block in the skeleton form of eqs. keq1/keq2 (the ACA
+     * pivots sigma, tau and the LU of K(sigma, tau): r^2 elements instead of
+     * r (|I| + |J|)) and evaluate K(I, tau) and K(sigma, J) inside every
+     * product.  FP64 storage and FP64 arithmetic only: the pivots on the
+     * diagonal of L span the tolerance's range, so the solves cancel unless
+     * K(sigma, J) x is accurate to about tol.  One right-hand side per pass;
+     * only the ranks can be exported, nothing imported.  0: store U and V
+     * (default). */
+    int skeleton;
 } hodlr_opts;
 
 /* Defaults: level_rule 1, bounding cube, FP64 storage, symmetric 1,
- * max_rank 0, skip_aca 0, no budget, adm_dim 0. */
+ * max_rank 0, skip_aca 0, no budget, adm_dim 0, skeleton 0. */
 void hodlr_default_opts(hodlr_opts* opts);
 
 /* Build the HODLRdD representation (Alg. "HODLRdD Initialization"): the
@@ -128,7 +137,7 @@ hodlr_status hodlr_build(const double* points, int64_t N, int d, const hodlr_ker
  *   Asynchronous on stream; owns a workspace inside the handle, so calls on
  *   one handle must not overlap in time (serialize them on one stream).
  * Errors: EINVAL (nrhs < 1, ld < N, bad prec, BF16 storage with FP64
- * compute, factors missing), EDEVICE. */
+ * compute, skeleton form with FP32 compute, factors missing), EDEVICE. */
 hodlr_status hodlr_matvec(hodlr_t h, const void* X, int64_t ldx, int nrhs, int x_prec,
                           void* Y, int64_t ldy, int compute_prec, void* stream);
 
@@ -276,7 +285,7 @@ typedef struct {
     int64_t stored_blocks[32];/* factor pairs held per level */
     int32_t rank_min[32], rank_max[32];
     double rank_mean[32];     /* over stored blocks */
-    int64_t factor_elems[32]; /* sum over stored blocks of r(|I|+|J|) */
+    int64_t factor_elems[32]; /* stored factor elements: sum of r(|I|+|J|) (r^2 in the skeleton form) */
     /* blocks applied by one workgroup, by size class (0, 1: at most 8 / 16
      * rows, columns and terms; 2..5: |A|, |B| up to 64, 128, 1024, 4608),
      * their factor elements sum r(|I|+|J|) and vector elements 2(|I|+|J|) */

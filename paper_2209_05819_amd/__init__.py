@@ -37,7 +37,8 @@ class Opts(C.Structure):
     _fields_ = [("level_rule", C.c_int), ("has_domain", C.c_int),
                 ("domain_lo", C.c_double * 8), ("domain_side", C.c_double),
                 ("storage", C.c_int), ("symmetric", C.c_int), ("max_rank", C.c_int),
-                ("skip_aca", C.c_int), ("mem_budget_bytes", C.c_size_t), ("adm_dim", C.c_int)]
+                ("skip_aca", C.c_int), ("mem_budget_bytes", C.c_size_t), ("adm_dim", C.c_int),
+                ("skeleton", C.c_int)]
 
 
 class Info(C.Structure):
@@ -314,6 +315,15 @@ def hodlr_export_factors(h: int, level: int, nnz: int):
     return ranks[:nnz], U[:nu.value], V[:nv.value]
 
 
+def hodlr_export_ranks(h: int, level: int, nnz: int):
+    """ranks of the interaction-list entries of a level (any storage form)"""
+    ranks = np.empty(max(nnz, 1), dtype=np.int32)
+    nu, nv = C.c_int64(), C.c_int64()
+    _check(lib().hodlr_export_factors(C.c_void_p(h), level, _np_ptr(ranks), C.byref(nu),
+                                      C.byref(nv), None, None))
+    return ranks[:nnz]
+
+
 def hodlr_import_factors(h: int, level: int, ranks, U, V) -> None:
     r = np.ascontiguousarray(ranks, dtype=np.int32)
     Ua = np.ascontiguousarray(U, dtype=np.float64)
@@ -331,10 +341,11 @@ class HODLR:
 
     def __init__(self, points, kernel: Kernel, leaf_size: int, tol: float, *, level_rule=1,
                  domain=None, storage=FP64, symmetric=True, max_rank=0, skip_aca=False,
-                 mem_budget_bytes=0, adm_dim=0, stream=None):
+                 mem_budget_bytes=0, adm_dim=0, skeleton=False, stream=None):
         o = default_opts()
         o.level_rule = level_rule
         o.adm_dim = int(adm_dim)
+        o.skeleton = 1 if skeleton else 0
         if domain is not None:
             o.has_domain = 1
             lo = np.asarray(domain[0], dtype=np.float64)

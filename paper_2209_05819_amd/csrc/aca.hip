@@ -32,6 +32,7 @@ struct AcaJob {
     int32_t cap;    // columns available in the workspace
     int64_t ws;     // offset (in doubles) of the job's workspace
     int64_t block;  // global block index
+    int64_t pv;     // offset of the job's pivot pairs (row, column) per term
 };
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -60,7 +61,8 @@ template <bool kLds>
 __global__ __launch_bounds__(T) void k_aca(const double* __restrict__ pts, int64_t N, int d,
                                            KParams kp, double tol, const AcaJob* __restrict__ jobs,
                                            double* __restrict__ wsbase, int32_t* __restrict__ ranks,
-                                           int32_t* __restrict__ overflow) {
+                                           int32_t* __restrict__ overflow,
+                                           int32_t* __restrict__ pivots) {
     extern __shared__ double dyn[];
     __shared__ double red_v[NW], red_w[NW], red_x[NW];
     __shared__ int red_i[NW], red_j[NW];
@@ -252,6 +254,9 @@ __global__ __launch_bounds__(T) void k_aca(const double* __restrict__ pts, int64
             } else {
                 sh_S2 = S2new;
                 sh_k = k + 1;
+                // the accepted term's pivots: row istar of A, column jstar of B
+                pivots[J.pv + 2 * k] = istar;
+                pivots[J.pv + 2 * k + 1] = jstar;
                 // ix is out of range only if every untried |u_i| is non-finite
                 if (sh_nused == m || ix < 0 || ix >= m)
                     sh_done = 1;
@@ -335,6 +340,42 @@ __global__ void k_sizes(const AcaJob* __restrict__ jobs, const int32_t* __restri
     sv[t] = ((int64_t)ranks[t] * lv + align - 1) / align * align;
 }
 
+// skeleton form (eq. keq1 with the LU of eq. keq2): the r x r matrix
+// K(sigma, tau) = U(sigma, :) V(:, tau) stored as one LU array: on and below
+// the diagonal L[i][k] = U(sigma_i, k) (lower, the pivots on the diagonal),
+// above it V(i, tau_k) (unit upper); then the pivots sigma (rows of A) and
+// tau (columns of B) as int32
+template <typename S>
+__global__ void k_pack_skel(const AcaJob* __restrict__ jobs, const double* __restrict__ wsbase,
+                            const int32_t* __restrict__ ranks, const int32_t* __restrict__ pivots,
+                            const int64_t* __restrict__ moff, const int64_t* __restrict__ poff,
+                            S* __restrict__ arena_m, int32_t* __restrict__ arena_p,
+                            BlockDesc* __restrict__ blocks) {
+    const AcaJob J = jobs[blockIdx.x];
+    const int r = ranks[blockIdx.x];
+    const double* gU = wsbase + J.ws;
+    const double* gV = gU + (int64_t)J.cap * J.m;
+    const int32_t* pv = pivots + J.pv;
+    S* M = arena_m + moff[blockIdx.x];
+    int32_t* P = arena_p + poff[blockIdx.x];
+    for (int64_t e = threadIdx.x; e < (int64_t)r * r; e += blockDim.x) {
+        const int i = (int)(e / r), k = (int)(e - (int64_t)i * r);
+        const double v = k <= i ? gU[(int64_t)k * J.m + pv[2 * i]]
+                                : gV[(int64_t)i * J.n + pv[2 * k + 1]];
+        M[e] = to_storage<S>(v);
+    }
+    for (int k = threadIdx.x; k < r; k += blockDim.x) {
+        P[k] = pv[2 * k];
+        P[r + k] = pv[2 * k + 1];
+    }
+    if (threadIdx.x == 0) {
+        BlockDesc& b = blocks[J.block];
+        b.rank = r;
+        b.U = reinterpret_cast<uint64_t>(M);
+        b.V = reinterpret_cast<uint64_t>(P);
+    }
+}
+
 size_t job_lds_bytes(const AcaJob& j) {
     return sizeof(double) * (2 * (size_t)j.cap + (size_t)j.cap * (j.m + j.n)) + (size_t)j.m + 8;
 }
@@ -381,11 +422,14 @@ struct ChunkResult {
 void run_chunk(hodlr_t h, std::vector<AcaJob>& jobs, bool lds, size_t lds_bytes,
                std::vector<int32_t>& ranks_out, std::vector<int32_t>& ovf_out, hipStream_t s) {
     const int64_t nj = (int64_t)jobs.size();
-    size_t ws_total = 0;
+    size_t ws_total = 0, pv_total = 0;
     for (auto& j : jobs) {
         j.ws = (int64_t)ws_total;
         ws_total += job_ws_doubles(j);
+        j.pv = (int64_t)pv_total;
+        pv_total += 2 * (size_t)j.cap;
     }
+    int32_t* dpiv = (int32_t*)dalloc(h, sizeof(int32_t) * std::max<size_t>(pv_total, 1));
     AcaJob* djobs = (AcaJob*)dalloc(h, sizeof(AcaJob) * nj);
     double* ws = (double*)dalloc(h, sizeof(double) * std::max<size_t>(ws_total, 1));
     int32_t* dr = (int32_t*)dalloc(h, sizeof(int32_t) * nj);
@@ -396,14 +440,14 @@ void run_chunk(hodlr_t h, std::vector<AcaJob>& jobs, bool lds, size_t lds_bytes,
         HIP_CHECK(hipFuncSetAttribute((const void*)k_aca<true>,
                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes));
         k_aca<true><<<(unsigned)nj, T, lds_bytes, s>>>(h->pts, h->N, h->d, h->kp, tol, djobs, ws,
-                                                       dr, dov);
+                                                       dr, dov, dpiv);
     } else {
         size_t small = 0;
         for (auto& j : jobs) small = std::max(small, sizeof(double) * 2 * (size_t)j.cap);
         HIP_CHECK(hipFuncSetAttribute((const void*)k_aca<false>,
                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)small));
         k_aca<false><<<(unsigned)nj, T, small, s>>>(h->pts, h->N, h->d, h->kp, tol, djobs, ws,
-                                                    dr, dov);
+                                                    dr, dov, dpiv);
     }
     HIP_CHECK(hipGetLastError());
     ranks_out.resize(nj);
@@ -420,7 +464,36 @@ void run_chunk(hodlr_t h, std::vector<AcaJob>& jobs, bool lds, size_t lds_bytes,
             okr.push_back(ranks_out[t]);
         }
     const int64_t nk = (int64_t)ok.size();
-    if (nk > 0) {
+    if (nk > 0 && h->opts.skeleton) {
+        HIP_CHECK(hipMemcpyAsync(djobs, ok.data(), sizeof(AcaJob) * nk, hipMemcpyHostToDevice, s));
+        HIP_CHECK(hipMemcpyAsync(dr, okr.data(), sizeof(int32_t) * nk, hipMemcpyHostToDevice, s));
+        const size_t es = storage_size(h->opts.storage);
+        std::vector<int64_t> mo(nk), po(nk);
+        int64_t tm = 0, tp = 0;
+        for (int64_t t = 0; t < nk; ++t) {
+            mo[t] = tm;
+            po[t] = tp;
+            tm += padded((int64_t)okr[t] * okr[t], es);
+            tp += padded(2 * (int64_t)okr[t], 4);
+        }
+        int64_t* dmo = (int64_t*)dalloc(h, sizeof(int64_t) * nk);
+        int64_t* dpo = (int64_t*)dalloc(h, sizeof(int64_t) * nk);
+        HIP_CHECK(hipMemcpyAsync(dmo, mo.data(), sizeof(int64_t) * nk, hipMemcpyHostToDevice, s));
+        HIP_CHECK(hipMemcpyAsync(dpo, po.data(), sizeof(int64_t) * nk, hipMemcpyHostToDevice, s));
+        char* arena = (char*)dalloc(h, es * (size_t)tm + 4 * (size_t)tp + 16);
+        h->arenas.push_back(arena);
+        int32_t* ap = reinterpret_cast<int32_t*>(arena + es * (size_t)tm);
+        if (h->opts.storage == HODLR_FP32)
+            k_pack_skel<float><<<(unsigned)nk, 256, 0, s>>>(djobs, ws, dr, dpiv, dmo, dpo,
+                                                            (float*)arena, ap, h->blocks);
+        else
+            k_pack_skel<double><<<(unsigned)nk, 256, 0, s>>>(djobs, ws, dr, dpiv, dmo, dpo,
+                                                             (double*)arena, ap, h->blocks);
+        HIP_CHECK(hipGetLastError());
+        HIP_CHECK(hipStreamSynchronize(s));
+        dfree(h, dmo);
+        dfree(h, dpo);
+    } else if (nk > 0) {
         HIP_CHECK(hipMemcpyAsync(djobs, ok.data(), sizeof(AcaJob) * nk, hipMemcpyHostToDevice, s));
         HIP_CHECK(hipMemcpyAsync(dr, okr.data(), sizeof(int32_t) * nk, hipMemcpyHostToDevice, s));
         int64_t* su = (int64_t*)dalloc(h, sizeof(int64_t) * nk);
@@ -461,6 +534,7 @@ void run_chunk(hodlr_t h, std::vector<AcaJob>& jobs, bool lds, size_t lds_bytes,
     dfree(h, ws);
     dfree(h, dr);
     dfree(h, dov);
+    dfree(h, dpiv);
 }
 
 }  // namespace

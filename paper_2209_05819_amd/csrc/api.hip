@@ -82,6 +82,7 @@ void hodlr_default_opts(hodlr_opts* o) {
     o->skip_aca = 0;
     o->mem_budget_bytes = 0;
     o->adm_dim = 0;
+    o->skeleton = 0;
 }
 
 hodlr_status hodlr_build(const double* points, int64_t N, int d, const hodlr_kernel* kernel,
@@ -107,6 +108,12 @@ hodlr_status hodlr_build(const double* points, int64_t N, int d, const hodlr_ker
     if (o.max_rank < 0) return set_error(HODLR_EINVAL, "max_rank must be >= 0");
     if (o.adm_dim < -1 || o.adm_dim > d - 1)
         return set_error(HODLR_EINVAL, "adm_dim must be in -1 .. d-1");
+    if (o.skeleton != 0 && o.skeleton != 1) return set_error(HODLR_EINVAL, "skeleton must be 0 or 1");
+    if (o.skeleton && o.storage != HODLR_FP64)
+        return set_error(HODLR_EINVAL, "the skeleton form stores FP64 (its solves with "
+                                       "K(sigma, tau) need the products to full precision)");
+    if (o.skeleton && o.skip_aca)
+        return set_error(HODLR_EINVAL, "the skeleton form takes its factors from ACA (skip_aca = 0)");
 
     hodlr_t h = new (std::nothrow) hodlr_handle_s();
     if (!h) return set_error(HODLR_ENOMEM, "host allocation failed");
@@ -163,6 +170,8 @@ hodlr_status matvec_checked(hodlr_t h, const void* X, int64_t ldx, int nrhs, int
         return set_error(HODLR_EINVAL, "compute_prec must be FP64 or FP32");
     if (h->opts.storage == HODLR_BF16 && compute_prec != HODLR_FP32)
         return set_error(HODLR_EINVAL, "BF16 factors are applied in FP32 arithmetic");
+    if (h->opts.skeleton && compute_prec != HODLR_FP64)
+        return set_error(HODLR_EINVAL, "the skeleton form is applied in FP64 arithmetic");
     if (events && nevents != 5 && nevents != 5 + hodlr::kApplyClasses)
         return set_error(HODLR_EINVAL, "events must hold 5 or 11 entries");
     for (int l = 1; l <= h->kappa; ++l)
@@ -357,7 +366,8 @@ hodlr_status hodlr_get_info(hodlr_t h, hodlr_info* info) {
             rmin = std::min(rmin, bd.rank);
             rmax = std::max(rmax, bd.rank);
             rs += bd.rank;
-            fe += (int64_t)std::max(bd.rank, 0) * (bd.m + bd.n);
+            fe += (int64_t)std::max(bd.rank, 0) *
+                  (h->opts.skeleton ? (int64_t)std::max(bd.rank, 0) : (int64_t)(bd.m + bd.n));
         }
         info->rank_min[l] = h->lev[l].nblk ? rmin : 0;
         info->rank_max[l] = rmax;
@@ -448,6 +458,8 @@ hodlr_status hodlr_export_factors(hodlr_t h, int level, int32_t* ranks, int64_t*
                                   int64_t* v_elems, double* U, double* V) {
     if (!h) return set_error(HODLR_EINVAL, "null handle");
     if (level < 1 || level > h->kappa) return set_error(HODLR_EINVAL, "level out of range");
+    if (h->opts.skeleton && (U || V))
+        return set_error(HODLR_EUNSUPPORTED, "skeleton form: only the ranks can be exported");
     return guarded([&] { hodlr::export_level(h, level, ranks, u_elems, v_elems, U, V, nullptr); });
 }
 
@@ -455,6 +467,7 @@ hodlr_status hodlr_import_factors(hodlr_t h, int level, const int32_t* ranks, co
                                   const double* V) {
     if (!h || !ranks) return set_error(HODLR_EINVAL, "null pointer argument");
     if (level < 1 || level > h->kappa) return set_error(HODLR_EINVAL, "level out of range");
+    if (h->opts.skeleton) return set_error(HODLR_EUNSUPPORTED, "skeleton form: no factor import");
     return guarded([&] { hodlr::import_level(h, level, ranks, U, V, nullptr); });
 }
 

@@ -950,6 +950,148 @@ __global__ __launch_bounds__(TG) void k_gather_near(
     }
 }
 
+// Skeleton form (eqs. keq1/keq2): a stored block is its ACA pivots sigma
+// (rows of A), tau (columns of B) and the LU of K(sigma, tau) (L on and below
+// the diagonal, unit upper above), and
+//   K~(A,B) x_B = K(A, tau) U^-1 L^-1 K(sigma, B) x_B,
+//   K~(A,B)^T x_A = K(B, sigma) L^-T U^-T K(tau, A) x_A   (symmetric kernel).
+// One workgroup per block: the four kernel-matrix products are evaluated on
+// the fly (g threads per output, partial sums reduced in the group), the two
+// triangular pairs are solved by waves 0 and 1 in LDS.
+constexpr int kSkelMaxR = 1024;
+
+// out[k] = sum_j K(p_k, q_j) w_j for k < nt, targets p_k = pts[tidx(k)],
+// sources q_j = pts[sidx(j)] with weights wfn(j).  The sources are staged
+// through LDS 256 at a time (coordinates in FP64, weights in C) by the whole
+// workgroup; g threads share a target and split each tile, their partial sums
+// reduced in the group.  Every thread of the workgroup must call it.
+constexpr int kSkelTile = 256;
+
+template <typename C, int KIND, typename TI, typename SI, typename WF, typename OF>
+__device__ __forceinline__ void skel_products(const double* __restrict__ pts, int64_t N, int d,
+                                              const KParams& kp, int nt, TI tidx, int ns,
+                                              SI sidx, WF wfn, OF ofn, double (*s_q)[kSkelTile],
+                                              C* s_w, int64_t* s_i) {
+    int g = 1;
+    while (g < 64 && g * 2 * nt <= (int)blockDim.x) g *= 2;
+    const int per = blockDim.x / g;
+    const int sub = threadIdx.x & (g - 1);
+    for (int k0 = 0; k0 < nt; k0 += per) {
+        const int k = k0 + (int)threadIdx.x / g;
+        const bool act = k < nt;
+        double xt[kMaxD];
+        int64_t tp = -1;
+        if (act) {
+            tp = tidx(k);
+            for (int a = 0; a < d; ++a) xt[a] = pts[a * N + tp];
+        }
+        C acc = 0;
+        for (int j0 = 0; j0 < ns; j0 += kSkelTile) {
+            const int tn = min(kSkelTile, ns - j0);
+            __syncthreads();   // the previous tile is no longer read
+            for (int q = threadIdx.x; q < tn; q += blockDim.x) {
+                const int64_t sp = sidx(j0 + q);
+                s_i[q] = sp;
+                for (int a = 0; a < d; ++a) s_q[a][q] = pts[a * N + sp];
+                s_w[q] = wfn(j0 + q);
+            }
+            __syncthreads();
+            if (act) {
+#pragma unroll 4
+                for (int q = sub; q < tn; q += g) {
+                    C kij;
+                    if (s_i[q] == tp) {
+                        kij = (C)kp.diag;
+                    } else {
+                        C r2 = 0;
+                        for (int a = 0; a < d; ++a) {
+                            const C dx = (C)(xt[a] - s_q[a][q]);
+                            r2 += dx * dx;
+                        }
+                        kij = kfun_k<KIND>(kp, r2);
+                    }
+                    acc += kij * s_w[q];
+                }
+            }
+        }
+        for (int o = g / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+        if (act && sub == 0) ofn(k, acc);
+    }
+}
+
+template <typename S, typename C, int KIND>
+__global__ __launch_bounds__(256) void k_skel(const BlockDesc* __restrict__ blocks, int sym,
+                                              const double* __restrict__ pts, int64_t N, int d,
+                                              KParams kp, const C* __restrict__ x,
+                                              C* __restrict__ contrib) {
+    __shared__ C s_f[kSkelMaxR], s_t[kSkelMaxR];   // forward: w, then z; transposed: w', then s
+    __shared__ double s_q[kMaxD][kSkelTile];         // staged source coordinates
+    __shared__ C s_w[kSkelTile];
+    __shared__ int64_t s_i[kSkelTile];
+    const BlockDesc b = blocks[blockIdx.x];
+    const int r = b.rank, m = b.m, n = b.n;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const gptr_t<S> M = as_global<S>(b.U);
+    const int32_t* __restrict__ sig = reinterpret_cast<const int32_t*>(b.V);
+    const int32_t* __restrict__ tau = sig + r;
+    const C* __restrict__ xA = x + b.a0;
+    const C* __restrict__ xB = x + b.b0;
+    // w = K(sigma, B) x_B and w' = K(tau, A) x_A
+    skel_products<C, KIND>(
+        pts, N, d, kp, r, [&](int k) { return (int64_t)b.a0 + sig[k]; }, n,
+        [&](int j) { return (int64_t)b.b0 + j; }, [&](int j) { return xB[j]; },
+        [&](int k, C v) { s_f[k] = v; }, s_q, s_w, s_i);
+    if (sym)
+        skel_products<C, KIND>(
+            pts, N, d, kp, r, [&](int k) { return (int64_t)b.b0 + tau[k]; }, m,
+            [&](int i) { return (int64_t)b.a0 + i; }, [&](int i) { return xA[i]; },
+            [&](int k, C v) { s_t[k] = v; }, s_q, s_w, s_i);
+    __syncthreads();
+    if (wv == 0) {
+        // L z1 = w (rows of L), then U z = z1 (rows of the unit upper part)
+        for (int i = 0; i < r; ++i) {
+            C a = 0;
+            for (int k = lane; k < i; k += 64) a += ldf<C>(M, (int64_t)i * r + k) * s_f[k];
+            a = wsum(a);
+            if (lane == 0) s_f[i] = (s_f[i] - a) / ldf<C>(M, (int64_t)i * r + i);
+            wave_lds_fence();
+        }
+        for (int i = r - 1; i >= 0; --i) {
+            C a = 0;
+            for (int k = i + 1 + lane; k < r; k += 64) a += ldf<C>(M, (int64_t)i * r + k) * s_f[k];
+            a = wsum(a);
+            if (lane == 0) s_f[i] -= a;
+            wave_lds_fence();
+        }
+    } else if (wv == 1 && sym) {
+        // U^T s1 = w' (unit lower: row k of U updates the later entries), then
+        // L^T s = s1 (upper: row k of L updates the earlier entries)
+        for (int k = 0; k < r; ++k) {
+            const C sk = s_t[k];
+            for (int i = k + 1 + lane; i < r; i += 64) s_t[i] -= ldf<C>(M, (int64_t)k * r + i) * sk;
+            wave_lds_fence();
+        }
+        for (int k = r - 1; k >= 0; --k) {
+            const C sk = s_t[k] / ldf<C>(M, (int64_t)k * r + k);
+            wave_lds_fence();
+            if (lane == 0) s_t[k] = sk;
+            for (int i = lane; i < k; i += 64) s_t[i] -= ldf<C>(M, (int64_t)k * r + i) * sk;
+            wave_lds_fence();
+        }
+    }
+    __syncthreads();
+    // c_A = K(A, tau) z and c_B = K(B, sigma) s
+    skel_products<C, KIND>(
+        pts, N, d, kp, m, [&](int i) { return (int64_t)b.a0 + i; }, r,
+        [&](int k) { return (int64_t)b.b0 + tau[k]; }, [&](int k) { return s_f[k]; },
+        [&](int i, C v) { contrib[b.cfwd + i] = v; }, s_q, s_w, s_i);
+    if (sym)
+        skel_products<C, KIND>(
+            pts, N, d, kp, n, [&](int j) { return (int64_t)b.b0 + j; }, r,
+            [&](int k) { return (int64_t)b.a0 + sig[k]; }, [&](int k) { return s_t[k]; },
+            [&](int j, C v) { contrib[b.cbwd + j] = v; }, s_q, s_w, s_i);
+}
+
 // Near field on matrix cores (BF16 factors, several right-hand sides):
 // y_A += K(A, near(A)) x, K evaluated on the fly in FP32 and rounded to BF16,
 // times x in BF16, FP32 accumulation.  One workgroup of 4 waves per 64-row
@@ -1446,6 +1588,38 @@ void run_matvec(hodlr_t h, const XT* X, int64_t ldx, int nrhs, XT* Y, int64_t ld
             HIP_CHECK(hipGetLastError());
             continue;
         } else {
+        if constexpr (NR == 1 && !std::is_same<S, bf16>::value) {
+            if (h->opts.skeleton) {
+                // skeleton form: every stored block, the kernel evaluated on the fly
+                const C* xc = x + (int64_t)c0 * N;
+                if (h->nblocks) {
+                    switch (h->kp.kind) {
+#define HODLR_SKEL(K)                                                                           \
+    case K:                                                                                     \
+        k_skel<S, C, K><<<(unsigned)h->nblocks, 256, 0, s>>>(h->blocks, sym, h->pts, N, h->d,   \
+                                                             h->kp, xc, contrib);              \
+        break;
+                        HODLR_SKEL(HODLR_K_LOG)
+                        HODLR_SKEL(HODLR_K_INV_R)
+                        HODLR_SKEL(HODLR_K_INV_R2)
+                        HODLR_SKEL(HODLR_K_GAUSS)
+                        HODLR_SKEL(HODLR_K_EXP)
+                        HODLR_SKEL(HODLR_K_R)
+                        HODLR_SKEL(HODLR_K_SIN)
+                        default:
+                        HODLR_SKEL(HODLR_K_INV_SQRT1P)
+#undef HODLR_SKEL
+                    }
+                    HIP_CHECK(hipGetLastError());
+                }
+                if (ev && c0 == 0) {
+                    for (int c = 0; c < kNumClasses; ++c) HIP_CHECK(hipEventRecord(ev[5 + c], s));
+                    HIP_CHECK(hipEventRecord(ev[2], s));
+                    HIP_CHECK(hipEventRecord(ev[3], s));
+                }
+                goto gather;
+            }
+        }
         if (NR == 1) {
             // one launch per size class
             for (int c = 0; c < kNumClasses; ++c) {
@@ -1497,6 +1671,7 @@ void run_matvec(hodlr_t h, const XT* X, int64_t ldx, int nrhs, XT* Y, int64_t ld
         HIP_CHECK(hipGetLastError());
         if (ev && c0 == 0) HIP_CHECK(hipEventRecord(ev[3], s));
         }
+    gather:
         if constexpr (NR == 1) {
             // one right-hand side: the kernel function fixed at compile time
             switch (h->kp.kind) {
@@ -1540,7 +1715,7 @@ void dispatch_nr(hodlr_t h, const XT* X, int64_t ldx, int nrhs, XT* Y, int64_t l
             run_matvec<XT, S, C, 32>(h, X, ldx, nrhs, Y, ldy, ws, ev, nev, s);
         return;
     }
-    if (nrhs == 1)
+    if (nrhs == 1 || h->opts.skeleton)   // the skeleton form takes one column per pass
         run_matvec<XT, S, C, 1>(h, X, ldx, nrhs, Y, ldy, ws, ev, nev, s);
     else if (nrhs <= 4)
         run_matvec<XT, S, C, 4>(h, X, ldx, nrhs, Y, ldy, ws, ev, nev, s);
@@ -1556,7 +1731,8 @@ void reserve_workspace(hodlr_t h, int nrhs, int compute_prec, hipStream_t s) {
     const int64_t TT = std::max<int64_t>(h->t_total, 1);
     const int64_t CT = std::max<int64_t>(h->contrib_total, 1);
     const bool b16 = h->opts.storage == HODLR_BF16;
-    const int nr = nrhs == 1 ? 1 : b16 ? (nrhs <= 16 ? 16 : 32) : (nrhs <= 4 ? 4 : 8);
+    const int nr = (nrhs == 1 || h->opts.skeleton) ? 1
+                   : b16 ? (nrhs <= 16 ? 16 : 32) : (nrhs <= 4 ? 4 : 8);
     size_t need;
     if (b16 && nr >= 16)   // x, x rows, level sums, projections, panel partials
         need = align256(cs * (size_t)N * nrhs) + align256(2 * (size_t)N * nr) + align256(4 * (size_t)N * nr) +

@@ -52,6 +52,7 @@ def test_default_opts_and_errors_without_gpu():
         pytest.skip("library not built")
     o = P.default_opts()
     assert o.symmetric == 1 and o.storage == P.FP64 and o.level_rule == 1 and o.adm_dim == 0
+    assert o.skeleton == 0
     L = P.lib()
     # argument errors are reported before any device work
     st = L.hodlr_build(None, 10, 3, None, 8, 1e-6, None, None, None)

@@ -825,7 +825,10 @@ __global__ __launch_bounds__(TG) void k_gather_near(
         // then every lane reads them as broadcasts
         __shared__ int s_pre[kNearTileRanges + 1], s_rs[kNearTileRanges];
         __shared__ int s_j[kNearTile];
-        __shared__ C s_pt[4][kNearTile];
+        struct alignas(4 * sizeof(C)) C4 {
+            C v[4];
+        };
+        __shared__ C4 s_pt[kNearTile];   // one 4-coordinate record per source (one LDS read)
         __shared__ C s_x[NR][kNearTile];
         // coordinates in the compute type: FP64 as they are; FP32 relative to
         // the leaf's first point, so that differences of nearby points keep
@@ -868,8 +871,10 @@ __global__ __launch_bounds__(TG) void k_gather_near(
                 }
                 const int j = s_rs[lo] + (sidx - s_pre[lo]);
                 s_j[q] = j;
+                C4 pq;
 #pragma unroll
-                for (int a = 0; a < 4; ++a) s_pt[a][q] = a < d ? (C)(pts[a * N + j] - ref[a]) : (C)0;
+                for (int a = 0; a < 4; ++a) pq.v[a] = a < d ? (C)(pts[a * N + j] - ref[a]) : (C)0;
+                s_pt[q] = pq;
 #pragma unroll
                 for (int c = 0; c < NR; ++c) s_x[c][q] = c < nc ? x[(int64_t)(c0 + c) * N + j] : (C)0;
             }
@@ -881,10 +886,11 @@ __global__ __launch_bounds__(TG) void k_gather_near(
                     if (s_j[q] == i) {
                         kij = (C)kp.diag;
                     } else {
+                        const C4 pq = s_pt[q];
                         C r2 = 0;
 #pragma unroll
                         for (int a = 0; a < 4; ++a) {
-                            const C dx = xc[a] - s_pt[a][q];
+                            const C dx = xc[a] - pq.v[a];
                             r2 += dx * dx;
                         }
                         kij = kfun_k<KIND>(kp, r2);

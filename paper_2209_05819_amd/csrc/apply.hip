@@ -29,39 +29,145 @@ constexpr int KB = 16;    // rows reduced together in the fused projection
 constexpr int kFusedMaxRank = 256;  // projections a fused wave keeps in LDS at once
 constexpr int kNumClasses = kApplyClasses;  // block size classes of the one-workgroup kernels
 
-template <typename C>
-__device__ __forceinline__ C wsum(C v) {
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
+
+// Cross-lane moves that stay in the vector ALU: DPP row permutations for
+// lane distances up to 8, and the permlane swaps of CDNA4 for 16 and 32
+// (lanes exchange whole 16- or 32-lane halves between two registers).  None
+// of them goes through the LDS crossbar, unlike a general shuffle.
+template <int OFF>
+__device__ __forceinline__ int dpp_xor(int v) {
+    static_assert(OFF == 1 || OFF == 2 || OFF == 4 || OFF == 8, "DPP distance");
+    if constexpr (OFF == 1) return __builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, false);  // quad [1,0,3,2]
+    if constexpr (OFF == 2) return __builtin_amdgcn_mov_dpp(v, 0x4E, 0xF, 0xF, false);  // quad [2,3,0,1]
+    if constexpr (OFF == 4)   // quad [3,2,1,0] then mirror within 8 lanes: l -> l ^ 4
+        return __builtin_amdgcn_mov_dpp(__builtin_amdgcn_mov_dpp(v, 0x1B, 0xF, 0xF, false),
+                                        0x141, 0xF, 0xF, false);
+    if constexpr (OFF == 8) return __builtin_amdgcn_mov_dpp(v, 0x128, 0xF, 0xF, false);  // rotate row by 8
 }
 
-// Reduce KB = 2^q partial sums per lane over the 64 lanes at once: at each
-// halving step a lane keeps half of its values and sends the other half to
-// its partner, so KB sums cost KB-1 exchanges plus 6-q plain steps (instead
-// of 6 KB).  On return lane L holds the full sum of row (L >> (6 - q)).
+template <int OFF, typename C>
+__device__ __forceinline__ C lane_xor(C v) {
+    if constexpr (sizeof(C) == 4) {
+        return __int_as_float(dpp_xor<OFF>(__float_as_int(v)));
+    } else {
+        const long long b = __double_as_longlong(v);
+        const int lo = dpp_xor<OFF>((int)(b & 0xffffffffLL)), hi = dpp_xor<OFF>((int)(b >> 32));
+        return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+    }
+}
+
+// Given a and b in every lane, returns in lane L the sum a_L + a_{L^OFF}
+// when bit OFF of L is clear and b_L + b_{L^OFF} when it is set (OFF = 16 or
+// 32).  One swap moves a's upper halves and b's lower halves across, so the
+// sum is a single add.
+template <int OFF>
+__device__ __forceinline__ void half_swap(unsigned int& a, unsigned int& b) {
+    if constexpr (OFF == 32) {
+        const auto r = __builtin_amdgcn_permlane32_swap(a, b, false, false);
+        a = r[0];
+        b = r[1];
+    } else {
+        static_assert(OFF == 16, "swap distance");
+        const auto r = __builtin_amdgcn_permlane16_swap(a, b, false, false);
+        a = r[0];
+        b = r[1];
+    }
+}
+
+template <int OFF, typename C>
+__device__ __forceinline__ C pair_sum(C a, C b) {
+    if constexpr (sizeof(C) == 4) {
+        unsigned int x = __float_as_uint(a), y = __float_as_uint(b);
+        half_swap<OFF>(x, y);
+        return __uint_as_float(x) + __uint_as_float(y);
+    } else {
+        const unsigned long long ab = (unsigned long long)__double_as_longlong(a);
+        const unsigned long long bb = (unsigned long long)__double_as_longlong(b);
+        unsigned int alo = (unsigned int)ab, ahi = (unsigned int)(ab >> 32);
+        unsigned int blo = (unsigned int)bb, bhi = (unsigned int)(bb >> 32);
+        half_swap<OFF>(alo, blo);
+        half_swap<OFF>(ahi, bhi);
+        return __longlong_as_double((long long)(((unsigned long long)ahi << 32) | alo)) +
+               __longlong_as_double((long long)(((unsigned long long)bhi << 32) | blo));
+    }
+}
+
+// One halving step of multi_reduce at lane distance OFF over the first
+// 2 HALF values: afterwards p[kk] (kk < HALF) holds row kk's pair sum in
+// lanes with bit OFF clear and row HALF + kk's in lanes with it set.
+template <int OFF, int HALF, typename C, int K>
+__device__ __forceinline__ void reduce_step(C (&p)[K]) {
+    if constexpr (OFF >= 16) {
+#pragma unroll
+        for (int kk = 0; kk < HALF; ++kk) p[kk] = pair_sum<OFF>(p[kk], p[HALF + kk]);
+    } else {
+        const bool upper = ((threadIdx.x & 63) & OFF) != 0;
+#pragma unroll
+        for (int kk = 0; kk < HALF; ++kk) {
+            const C keep = upper ? p[HALF + kk] : p[kk];
+            const C give = upper ? p[kk] : p[HALF + kk];
+            p[kk] = keep + lane_xor<OFF>(give);
+        }
+    }
+}
+
+// Sum of v over groups of 2 OFF lanes (then OFF / 2, ... down to 1 lane).
+template <int OFF, typename C>
+__device__ __forceinline__ C lane_sum_to(C v) {
+    if constexpr (OFF >= 16) {
+        v = pair_sum<OFF>(v, v);
+    } else {
+        v += lane_xor<OFF>(v);
+    }
+    if constexpr (OFF > 1) {
+        return lane_sum_to<OFF / 2>(v);
+    } else {
+        return v;
+    }
+}
+
+// Reduce K = 2^q partial sums per lane over the 64 lanes at once: at each
+// halving step a lane keeps half of its values and receives its partner's
+// matching half, so K sums cost K-1 exchanges plus 6-q plain steps (instead
+// of 6 K).  On return lane L holds the full sum of row (L >> (6 - q)).
+template <int OFF, int WIDTH, typename C, int K>
+__device__ __forceinline__ C multi_reduce_from(C (&p)[K]) {
+    if constexpr (WIDTH > 1) {
+        reduce_step<OFF, WIDTH / 2>(p);
+        return multi_reduce_from<OFF / 2, WIDTH / 2>(p);
+    } else {
+        return lane_sum_to<OFF>(p[0]);
+    }
+}
+
 template <typename C, int K>
 __device__ __forceinline__ C multi_reduce(C (&p)[K]) {
-    const int lane = threadIdx.x & 63;
-    int width = K;
-    int off = 32;
-#pragma unroll
-    for (int step = 0; (1 << step) < K; ++step) {
-        const int half = width >> 1;
-        const bool upper = (lane & off) != 0;
-#pragma unroll
-        for (int kk = 0; kk < K / 2; ++kk) {
-            if (kk < half) {
-                const C keep = upper ? p[half + kk] : p[kk];
-                const C give = upper ? p[kk] : p[half + kk];
-                p[kk] = keep + __shfl_xor(give, off, 64);
-            }
-        }
-        width = half;
-        off >>= 1;
+    return multi_reduce_from<32, K>(p);
+}
+
+template <typename C>
+__device__ __forceinline__ C wsum(C v) {
+    return lane_sum_to<32>(v);
+}
+
+// Value of v in lane L (a compile-time constant) as a wave-uniform scalar.
+template <int L, typename C>
+__device__ __forceinline__ C lane_value(C v) {
+    if constexpr (sizeof(C) == 4) {
+        return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), L));
+    } else {
+        const long long b = __double_as_longlong(v);
+        const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), L);
+        const int hi = __builtin_amdgcn_readlane((int)(b >> 32), L);
+        return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
     }
-    C v = p[0];
-    for (; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
+}
+
+// out[k] = v in lane k 2^(6-Q), k < K: the row sums multi_reduce leaves.
+template <int Q, int KK = 0, typename C, int K>
+__device__ __forceinline__ void row_values(C v, C (&out)[K]) {
+    out[KK] = lane_value<(KK << (6 - Q))>(v);
+    if constexpr (KK + 1 < K) row_values<Q, KK + 1>(v, out);
 }
 
 template <int K>
@@ -238,10 +344,12 @@ __device__ __forceinline__ void stream_step(const StreamBatch<S, C, W, CH, KB>& 
     const C sv = sym ? multi_reduce<C, KB>(ps) : (C)0;
     C tk[KB], sk[KB];
     if (W == 1) {
+        row_values<Q>(tv, tk);
+        if (sym) {
+            row_values<Q>(sv, sk);
+        } else {
 #pragma unroll
-        for (int kk = 0; kk < KB; ++kk) {
-            tk[kk] = __shfl(tv, kk << (6 - Q), 64);
-            sk[kk] = __shfl(sv, kk << (6 - Q), 64);
+            for (int kk = 0; kk < KB; ++kk) sk[kk] = 0;
         }
     } else {
         const int row = lane >> (6 - Q);

@@ -319,8 +319,8 @@ __device__ __forceinline__ void stream_load(StreamBatch<S, C, W, CH, KB>& bt, gp
 #pragma unroll
         for (int c = 0; c < CH; ++c) {
             const int i = base + c * 64;
-            bt.v[kk][c] = (kk < kr && i < n) ? ldf<C>(Vk, kk * lv + i) : (C)0;
-            bt.u[kk][c] = (kk < kr && i < m) ? ldf<C>(Uk, kk * lu + i) : (C)0;
+            bt.v[kk][c] = (kk < kr && i < n) ? ldf_once<C>(Vk, kk * lv + i) : (C)0;
+            bt.u[kk][c] = (kk < kr && i < m) ? ldf_once<C>(Uk, kk * lu + i) : (C)0;
         }
 }
 
@@ -932,12 +932,14 @@ __global__ __launch_bounds__(TG) void k_gather_near(
         // sources staged through LDS in tiles: coalesced cooperative loads,
         // then every lane reads them as broadcasts
         __shared__ int s_pre[kNearTileRanges + 1], s_rs[kNearTileRanges];
-        __shared__ int s_j[kNearTile];
         struct alignas(4 * sizeof(C)) C4 {
             C v[4];
         };
-        __shared__ C4 s_pt[kNearTile];   // one 4-coordinate record per source (one LDS read)
+        // one record per source: its coordinates, and for d <= 3 with one
+        // right-hand side its x value in the fourth slot (one LDS read)
+        __shared__ C4 s_pt[kNearTile];
         __shared__ C s_x[NR][kNearTile];
+        const bool packx = NR == 1 && d <= 3;
         // coordinates in the compute type: FP64 as they are; FP32 relative to
         // the leaf's first point, so that differences of nearby points keep
         // their relative accuracy (zero beyond d)
@@ -965,6 +967,36 @@ __global__ __launch_bounds__(TG) void k_gather_near(
         }
         __syncthreads();
         const int total = s_pre[it.nn];
+        // the row's own point as a position in the concatenated sources (its
+        // leaf is one of the near ranges): the diagonal entry is found by
+        // position, without a per-source index
+        int qself = -1;
+        if (active)
+            for (int e = 0; e < it.nn; ++e) {
+                const int64_t rs = s_rs[e];
+                if (i >= rs && i < rs + (s_pre[e + 1] - s_pre[e])) qself = s_pre[e] + (int)(i - rs);
+            }
+        auto tile = [&](int t0, int tn, auto packed) {
+            constexpr bool P = decltype(packed)::value;
+            const int qs = qself - t0;
+#pragma unroll 4
+            for (int q = sg; q < tn; q += SG) {
+                const C4 pq = s_pt[q];
+                C r2 = 0;
+#pragma unroll
+                for (int a = 0; a < (P ? 3 : 4); ++a) {
+                    const C dx = xc[a] - pq.v[a];
+                    r2 += dx * dx;
+                }
+                const C kij = q == qs ? (C)kp.diag : kfun_k<KIND>(kp, r2);
+                if constexpr (P) {
+                    acc[0] += kij * pq.v[3];
+                } else {
+#pragma unroll
+                    for (int c = 0; c < NR; ++c) acc[c] += kij * s_x[c][q];
+                }
+            }
+        };
         for (int t0 = 0; t0 < total; t0 += kNearTile) {
             const int tn = min(kNearTile, total - t0);
             for (int q = threadIdx.x; q < tn; q += TG) {
@@ -978,34 +1010,23 @@ __global__ __launch_bounds__(TG) void k_gather_near(
                         hi = mid - 1;
                 }
                 const int j = s_rs[lo] + (sidx - s_pre[lo]);
-                s_j[q] = j;
                 C4 pq;
 #pragma unroll
                 for (int a = 0; a < 4; ++a) pq.v[a] = a < d ? (C)(pts[a * N + j] - ref[a]) : (C)0;
-                s_pt[q] = pq;
+                if (packx) {
+                    pq.v[3] = x[(int64_t)c0 * N + j];
+                } else {
 #pragma unroll
-                for (int c = 0; c < NR; ++c) s_x[c][q] = c < nc ? x[(int64_t)(c0 + c) * N + j] : (C)0;
+                    for (int c = 0; c < NR; ++c) s_x[c][q] = c < nc ? x[(int64_t)(c0 + c) * N + j] : (C)0;
+                }
+                s_pt[q] = pq;
             }
             __syncthreads();
             if (active) {
-#pragma unroll 4
-                for (int q = sg; q < tn; q += SG) {
-                    C kij;
-                    if (s_j[q] == i) {
-                        kij = (C)kp.diag;
-                    } else {
-                        const C4 pq = s_pt[q];
-                        C r2 = 0;
-#pragma unroll
-                        for (int a = 0; a < 4; ++a) {
-                            const C dx = xc[a] - pq.v[a];
-                            r2 += dx * dx;
-                        }
-                        kij = kfun_k<KIND>(kp, r2);
-                    }
-#pragma unroll
-                    for (int c = 0; c < NR; ++c) acc[c] += kij * s_x[c][q];
-                }
+                if (packx)
+                    tile(t0, tn, std::true_type{});
+                else
+                    tile(t0, tn, std::false_type{});
             }
             __syncthreads();
         }

@@ -75,6 +75,10 @@ def lib():
         L.ohodlr_near_nnz.argtypes = [_P]
         L.ohodlr_near_nnz.restype = _i64
         L.ohodlr_near.argtypes = [_P, _P, _P]
+        L.ohodlr_near_level_nnz.argtypes = [_P, C.c_int]
+        L.ohodlr_near_level_nnz.restype = _i64
+        L.ohodlr_near_level.argtypes = [_P, C.c_int, _P, _P]
+        L.ohodlr_box_flags.argtypes = [_P, C.c_int, _P]
         L.ohodlr_aca_dense.argtypes = [_P, _i64, _i64, C.c_double, C.c_int, _P, _P, _P, _P]
         L.ohodlr_aca_dense.restype = C.c_int
         L.ohodlr_compress.argtypes = [_P, C.POINTER(_Kernel), C.c_double, C.c_int, _i64, _i64]
@@ -222,6 +226,22 @@ class OracleHODLR:
         col = np.empty(max(nnz, 1), dtype=np.int32)
         lib().ohodlr_near(self.h, _ptr(ptr), _ptr(col))
         return ptr, col[:nnz]
+
+    def near_level(self, level: int):
+        """Dense near-field pairs of one level (CSR over the level's boxes)."""
+        nnz = lib().ohodlr_near_level_nnz(self.h, level)
+        nb = lib().ohodlr_nboxes(self.h, level)
+        ptr = np.empty(nb + 1, dtype=np.int64)
+        col = np.empty(max(nnz, 1), dtype=np.int32)
+        lib().ohodlr_near_level(self.h, level, _ptr(ptr), _ptr(col))
+        return ptr, col[:nnz]
+
+    def box_flags(self, level: int):
+        """Per box: bit 0 active (parent subdivided), bit 1 leaf."""
+        nb = lib().ohodlr_nboxes(self.h, level)
+        f = np.empty(max(nb, 1), dtype=np.uint8)
+        lib().ohodlr_box_flags(self.h, level, _ptr(f))
+        return f[:nb]
 
     def compress(self, k: _Kernel, tol: float, max_rank: int = 0, rows=None):
         r0, r1 = (0, self.N) if rows is None else rows

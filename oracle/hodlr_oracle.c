@@ -74,6 +74,10 @@ typedef struct {
     int64_t* start;   /* nb+1 */
     uint64_t* key;    /* nb */
     int32_t* coord;   /* nb*d */
+    uint8_t* flag;    /* nb: bit 0 active (its parent was subdivided), bit 1 leaf */
+    /* dense near-field pairs of this level (rows: active boxes) */
+    int64_t* near_ptr;
+    int32_t* near_col;
     /* interaction list (levels >= 1) */
     int64_t* il_ptr;
     int32_t* il_col;
@@ -94,8 +98,6 @@ struct ohodlr_s {
     uint64_t* key;      /* N, tree order */
     int64_t* perm;      /* tree position -> user index */
     olevel lev[64];
-    int64_t* near_ptr;
-    int32_t* near_col;
 };
 
 typedef struct { uint64_t key; int64_t idx; } kv;
@@ -193,10 +195,66 @@ static int in_near(const int32_t* A, const int32_t* B, int d, int t)
     return mx == 1 && eq > t;
 }
 
+/* Active and leaf boxes.  Uniform trees (rules 0, 1): every box is active
+ * and the leaves are the boxes of level kappa.  Adaptive tree (rule 2, the
+ * adaptive 2^d tree the paper mentions in sec. 5.2): a box is subdivided only
+ * while it holds more than `leaf` points, so a box is active when its parent
+ * holds more than `leaf` points (then so do all its ancestors), and an active
+ * box is a leaf when it holds at most `leaf` points or lies on level kappa.
+ * The boxes below a leaf still partition its points but take no part in the
+ * lists. */
+static void build_flags(ohodlr* h)
+{
+    for (int l = 0; l <= h->kappa; ++l) {
+        olevel* L = &h->lev[l];
+        L->flag = (uint8_t*)calloc((size_t)(L->nb ? L->nb : 1), 1);
+        const olevel* P = l > 0 ? &h->lev[l - 1] : NULL;
+        int64_t par = 0;
+        for (int64_t A = 0; A < L->nb; ++A) {
+            const int64_t cnt = L->start[A + 1] - L->start[A];
+            int act, lf;
+            if (h->rule != 2) {
+                act = 1;
+                lf = l == h->kappa;
+            } else {
+                if (P) {
+                    while (P->start[par + 1] <= L->start[A]) ++par;
+                    act = P->start[par + 1] - P->start[par] > h->leaf;
+                } else {
+                    act = 1;
+                }
+                lf = act && (cnt <= h->leaf || l == h->kappa);
+            }
+            L->flag[A] = (uint8_t)((act ? 1 : 0) | (lf ? 2 : 0));
+        }
+    }
+}
+
+static int active(const olevel* L, int64_t A) { return L->flag[A] & 1; }
+static int is_leaf(const olevel* L, int64_t A) { return (L->flag[A] & 2) != 0; }
+
+/* pairs of level l compressed at this level: both boxes active (their
+ * parents were subdivided and their parents' pair not admissible) and the
+ * pair admissible */
+static int il_pair(const ohodlr* h, const olevel* L, int64_t A, int64_t B)
+{
+    if (!active(L, A) || !active(L, B)) return 0;
+    return in_il(L->coord + A * h->d, L->coord + B * h->d, h->d, h->adm);
+}
+
+/* dense pairs of level l: both active, not admissible (the box itself or an
+ * adjacent box sharing a hyper-surface of dimension > t), and one of them a
+ * leaf, so the pair is not subdivided further */
+static int near_pair(const ohodlr* h, const olevel* L, int64_t A, int64_t B)
+{
+    if (!active(L, A) || !active(L, B)) return 0;
+    if (!is_leaf(L, A) && !is_leaf(L, B)) return 0;
+    return in_near(L->coord + A * h->d, L->coord + B * h->d, h->d, h->adm);
+}
+
 static void build_lists(ohodlr* h, int l)
 {
     olevel* L = &h->lev[l];
-    const int d = h->d;
     const int64_t nb = L->nb;
     L->il_ptr = (int64_t*)calloc((size_t)nb + 1, sizeof(int64_t));
     /* count (brute force over every box pair) */
@@ -204,7 +262,7 @@ static void build_lists(ohodlr* h, int l)
     for (int64_t A = 0; A < nb; ++A) {
         int64_t c = 0;
         for (int64_t B = 0; B < nb; ++B)
-            if (in_il(L->coord + A * d, L->coord + B * d, d, h->adm)) ++c;
+            if (il_pair(h, L, A, B)) ++c;
         L->il_ptr[A + 1] = c;
     }
     for (int64_t A = 0; A < nb; ++A) L->il_ptr[A + 1] += L->il_ptr[A];
@@ -214,7 +272,7 @@ static void build_lists(ohodlr* h, int l)
     for (int64_t A = 0; A < nb; ++A) {
         int64_t c = L->il_ptr[A];
         for (int64_t B = 0; B < nb; ++B)
-            if (in_il(L->coord + A * d, L->coord + B * d, d, h->adm)) L->il_col[c++] = (int32_t)B;
+            if (il_pair(h, L, A, B)) L->il_col[c++] = (int32_t)B;
     }
     L->rank = (int32_t*)malloc(sizeof(int32_t) * (nnz ? nnz : 1));
     L->U = (double**)calloc(nnz ? nnz : 1, sizeof(double*));
@@ -222,27 +280,26 @@ static void build_lists(ohodlr* h, int l)
     for (int64_t e = 0; e < nnz; ++e) L->rank[e] = -1;
 }
 
-static void build_near(ohodlr* h)
+static void build_near(ohodlr* h, int l)
 {
-    olevel* L = &h->lev[h->kappa];
-    const int d = h->d;
+    olevel* L = &h->lev[l];
     const int64_t nb = L->nb;
-    h->near_ptr = (int64_t*)calloc((size_t)nb + 1, sizeof(int64_t));
+    L->near_ptr = (int64_t*)calloc((size_t)nb + 1, sizeof(int64_t));
 #pragma omp parallel for schedule(dynamic, 16)
     for (int64_t A = 0; A < nb; ++A) {
         int64_t c = 0;
         for (int64_t B = 0; B < nb; ++B)
-            if (in_near(L->coord + A * d, L->coord + B * d, d, h->adm)) ++c;
-        h->near_ptr[A + 1] = c;
+            if (near_pair(h, L, A, B)) ++c;
+        L->near_ptr[A + 1] = c;
     }
-    for (int64_t A = 0; A < nb; ++A) h->near_ptr[A + 1] += h->near_ptr[A];
-    int64_t nnz = h->near_ptr[nb];
-    h->near_col = (int32_t*)malloc(sizeof(int32_t) * (nnz ? nnz : 1));
+    for (int64_t A = 0; A < nb; ++A) L->near_ptr[A + 1] += L->near_ptr[A];
+    int64_t nnz = L->near_ptr[nb];
+    L->near_col = (int32_t*)malloc(sizeof(int32_t) * (nnz ? nnz : 1));
 #pragma omp parallel for schedule(dynamic, 16)
     for (int64_t A = 0; A < nb; ++A) {
-        int64_t c = h->near_ptr[A];
+        int64_t c = L->near_ptr[A];
         for (int64_t B = 0; B < nb; ++B)
-            if (in_near(L->coord + A * d, L->coord + B * d, d, h->adm)) h->near_col[c++] = (int32_t)B;
+            if (near_pair(h, L, A, B)) L->near_col[c++] = (int32_t)B;
     }
 }
 
@@ -333,7 +390,7 @@ ohodlr* ohodlr_create_adm(const double* points, int64_t N, int d, int has_domain
 
     /* depth kappa */
     int kappa = 0;
-    if (level_rule == 0) {
+    if (level_rule == 0 || level_rule == 2) {
         while (kappa < L && level_max_count(h, kappa) > leaf) ++kappa;
     } else {
         /* smallest kappa with leaf * 2^(d kappa) >= N, in integers:
@@ -348,8 +405,9 @@ ohodlr* ohodlr_create_adm(const double* points, int64_t N, int d, int has_domain
     }
     h->kappa = kappa;
     for (int l = 0; l <= kappa; ++l) build_level(h, l);
+    build_flags(h);
     for (int l = 1; l <= kappa; ++l) build_lists(h, l);
-    build_near(h);
+    for (int l = 0; l <= kappa; ++l) build_near(h, l);
     *status = ORK_OK;
     return h;
 }
@@ -359,14 +417,14 @@ void ohodlr_destroy(ohodlr* h)
     if (!h) return;
     for (int l = 0; l <= h->kappa; ++l) {
         olevel* L = &h->lev[l];
-        free(L->start); free(L->key); free(L->coord);
+        free(L->start); free(L->key); free(L->coord); free(L->flag);
+        free(L->near_ptr); free(L->near_col);
         if (L->il_ptr) {
             int64_t nnz = L->il_ptr[L->nb];
             for (int64_t e = 0; e < nnz; ++e) { free(L->U[e]); free(L->V[e]); }
             free(L->il_ptr); free(L->il_col); free(L->rank); free(L->U); free(L->V);
         }
     }
-    free(h->near_ptr); free(h->near_col);
     free(h->pts_user); free(h->pts); free(h->q); free(h->key); free(h->perm);
     free(h);
 }
@@ -404,12 +462,26 @@ void ohodlr_il(const ohodlr* h, int level, int64_t* ptr, int32_t* col)
     memcpy(ptr, L->il_ptr, sizeof(int64_t) * (L->nb + 1));
     memcpy(col, L->il_col, sizeof(int32_t) * L->il_ptr[L->nb]);
 }
-int64_t ohodlr_near_nnz(const ohodlr* h) { return h->near_ptr[h->lev[h->kappa].nb]; }
+int64_t ohodlr_near_nnz(const ohodlr* h) { return ohodlr_near_level_nnz(h, h->kappa); }
 void ohodlr_near(const ohodlr* h, int64_t* ptr, int32_t* col)
 {
-    const olevel* L = &h->lev[h->kappa];
-    memcpy(ptr, h->near_ptr, sizeof(int64_t) * (L->nb + 1));
-    memcpy(col, h->near_col, sizeof(int32_t) * h->near_ptr[L->nb]);
+    ohodlr_near_level(h, h->kappa, ptr, col);
+}
+int64_t ohodlr_near_level_nnz(const ohodlr* h, int level)
+{
+    if (level < 0 || level > h->kappa) return -1;
+    return h->lev[level].near_ptr[h->lev[level].nb];
+}
+void ohodlr_near_level(const ohodlr* h, int level, int64_t* ptr, int32_t* col)
+{
+    const olevel* L = &h->lev[level];
+    memcpy(ptr, L->near_ptr, sizeof(int64_t) * (L->nb + 1));
+    memcpy(col, L->near_col, sizeof(int32_t) * L->near_ptr[L->nb]);
+}
+void ohodlr_box_flags(const ohodlr* h, int level, uint8_t* flags)
+{
+    const olevel* L = &h->lev[level];
+    memcpy(flags, L->flag, (size_t)L->nb);
 }
 
 /* ------------------------------------------------------------------------- */
@@ -711,23 +783,27 @@ int ohodlr_matvec(const ohodlr* h, const ork_kernel* k, const double* q, int nrh
                 free(t);
             }
         }
-        /* dense near field at the leaves */
-        const olevel* L = &h->lev[h->kappa];
+        /* dense near-field pairs of every level (only level kappa in a
+         * uniform tree) */
+        for (int l = 0; l <= h->kappa; ++l) {
+            const olevel* L = &h->lev[l];
 #pragma omp parallel for schedule(dynamic, 1)
-        for (int64_t A = 0; A < L->nb; ++A) {
-            if (L->start[A] < row0 || L->start[A + 1] > row1) continue;
-            for (int64_t i = L->start[A]; i < L->start[A + 1]; ++i) {
-                double s = 0.0;
-                for (int64_t e = h->near_ptr[A]; e < h->near_ptr[A + 1]; ++e) {
-                    int64_t B = h->near_col[e];
-                    for (int64_t j = L->start[B]; j < L->start[B + 1]; ++j) {
-                        double kij = h->perm[i] == h->perm[j]
-                                         ? k->diag
-                                         : ohodlr_kernel_eval(k, h->pts + i * d, h->pts + j * d, d);
-                        s += kij * x[j];
+            for (int64_t A = 0; A < L->nb; ++A) {
+                if (L->near_ptr[A] == L->near_ptr[A + 1]) continue;
+                if (L->start[A] < row0 || L->start[A + 1] > row1) continue;
+                for (int64_t i = L->start[A]; i < L->start[A + 1]; ++i) {
+                    double s = 0.0;
+                    for (int64_t e = L->near_ptr[A]; e < L->near_ptr[A + 1]; ++e) {
+                        int64_t B = L->near_col[e];
+                        for (int64_t j = L->start[B]; j < L->start[B + 1]; ++j) {
+                            double kij = h->perm[i] == h->perm[j]
+                                             ? k->diag
+                                             : ohodlr_kernel_eval(k, h->pts + i * d, h->pts + j * d, d);
+                            s += kij * x[j];
+                        }
                     }
+                    y[i] += s;
                 }
-                y[i] += s;
             }
         }
         double* bc = b + (int64_t)c * N;

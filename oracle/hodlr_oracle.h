@@ -55,7 +55,9 @@ void ohodlr_kernel_block(const ork_kernel* k, const double* X, int64_t m,
  * has_domain != 0: the hyper-cube is [lo, lo+side]^d (points outside -> EINVAL);
  * otherwise the bounding cube.  level_rule 0: kappa = smallest level whose
  * fullest box holds at most leaf points; 1: smallest kappa with
- * leaf * 2^(d kappa) >= N. */
+ * leaf * 2^(d kappa) >= N; 2: adaptive tree, depth as rule 0, and a box is
+ * subdivided only while it holds more than leaf points (leaves on several
+ * levels; see ohodlr_box_flags). */
 ohodlr* ohodlr_create(const double* points, int64_t N, int d, int has_domain,
                       const double* lo, double side, int leaf, int level_rule,
                       int* status);
@@ -78,8 +80,15 @@ int64_t ohodlr_nboxes(const ohodlr* h, int level);
 void    ohodlr_boxes(const ohodlr* h, int level, int64_t* start, uint64_t* key, int32_t* coord);
 int64_t ohodlr_il_nnz(const ohodlr* h, int level);
 void    ohodlr_il(const ohodlr* h, int level, int64_t* ptr, int32_t* col);
+/* dense near-field pairs of level kappa (all of them in a uniform tree) */
 int64_t ohodlr_near_nnz(const ohodlr* h);
 void    ohodlr_near(const ohodlr* h, int64_t* ptr, int32_t* col);
+/* dense near-field pairs of one level: rows are the level's boxes, columns
+ * the boxes B with (A, B) dense (both active, not admissible, one a leaf) */
+int64_t ohodlr_near_level_nnz(const ohodlr* h, int level);
+void    ohodlr_near_level(const ohodlr* h, int level, int64_t* ptr, int32_t* col);
+/* per box of a level: bit 0 active (its parent was subdivided), bit 1 leaf */
+void    ohodlr_box_flags(const ohodlr* h, int level, uint8_t* flags);
 
 /* ACA (partial pivoting) on an explicit m x n matrix M (row-major).
  * U must hold m*min(m,n) and V min(m,n)*n doubles; pivots min(m,n) each.

@@ -68,7 +68,13 @@ typedef enum { HODLR_FP64 = 0, HODLR_FP32 = 1, HODLR_BF16 = 2 } hodlr_prec;
 typedef struct {
     /* depth rule (sec. 5.2 / Alg. "HODLRdD Initialization"):
      * 0 = smallest level whose fullest box holds <= leaf_size points;
-     * 1 = smallest kappa with leaf_size * 2^(d kappa) >= N */
+     * 1 = smallest kappa with leaf_size * 2^(d kappa) >= N;
+     * 2 = adaptive 2^d tree (the option sec. 5.2 names beside the balanced
+     *     tree): depth as rule 0, but a box is subdivided only while it holds
+     *     more than leaf_size points.  Leaves then lie on several levels; the
+     *     lists take only boxes whose parent was subdivided (active boxes),
+     *     and a pair that is not admissible with a leaf on either side is a
+     *     dense near-field pair of its level (hodlr_export_near_level). */
     int level_rule;
     /* computational hyper-cube: [domain_lo, domain_lo + domain_side]^d when
      * has_domain != 0 (points outside -> HODLR_EINVAL), else the bounding cube */
@@ -329,8 +335,19 @@ hodlr_status hodlr_export_boxes(hodlr_t h, int level, int64_t* start, uint64_t* 
 hodlr_status hodlr_export_il(hodlr_t h, int level, int64_t* nnz, int64_t* ptr, int32_t* col);
 
 /* Near list of the leaves ({A} and boxes sharing a hyper-surface of
- * dimension 1..d-1 with A), same CSR convention. */
+ * dimension 1..d-1 with A), same CSR convention: the dense pairs of level
+ * kappa (every dense pair of a uniform tree). */
 hodlr_status hodlr_export_near(hodlr_t h, int64_t* nnz, int64_t* ptr, int32_t* col);
+
+/* Dense near-field pairs of level l (0..kappa), same CSR convention over the
+ * level's boxes: (A, B) both active, not admissible, and A or B a leaf.  In
+ * a uniform tree only level kappa has any. */
+hodlr_status hodlr_export_near_level(hodlr_t h, int level, int64_t* nnz, int64_t* ptr,
+                                     int32_t* col);
+
+/* Box flags of level l (0..kappa), host pointer flags[nb]: bit 0 active (the
+ * box's parent was subdivided), bit 1 leaf. */
+hodlr_status hodlr_export_box_flags(hodlr_t h, int level, uint8_t* flags);
 
 /* Factors of level l in the interaction list's CSR order, for every entry
  * (A,B): U (|A| x r, column after column) and V (r x |B|, row after row),

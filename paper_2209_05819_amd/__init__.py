@@ -129,6 +129,8 @@ def lib():
         L.hodlr_export_boxes.argtypes = [_P, C.c_int, _P, _P, _P]
         L.hodlr_export_il.argtypes = [_P, C.c_int, C.POINTER(_i64), _P, _P]
         L.hodlr_export_near.argtypes = [_P, C.POINTER(_i64), _P, _P]
+        L.hodlr_export_near_level.argtypes = [_P, C.c_int, C.POINTER(_i64), _P, _P]
+        L.hodlr_export_box_flags.argtypes = [_P, C.c_int, _P]
         L.hodlr_export_factors.argtypes = [_P, C.c_int, _P, C.POINTER(_i64), C.POINTER(_i64),
                                            _P, _P]
         L.hodlr_import_factors.argtypes = [_P, C.c_int, _P, _P, _P]
@@ -137,6 +139,7 @@ def lib():
         for f in ("hodlr_build", "hodlr_matvec", "hodlr_matvec_events", "hodlr_get_info",
                   "hodlr_export_tree",
                   "hodlr_export_boxes", "hodlr_export_il", "hodlr_export_near",
+                  "hodlr_export_near_level", "hodlr_export_box_flags",
                   "hodlr_export_factors", "hodlr_import_factors", "hodlr_solve",
                   "hodlr_server_create", "hodlr_server_add_set", "hodlr_server_submit",
                   "hodlr_server_wait", "hodlr_server_poll", "hodlr_server_get_stats"):
@@ -301,6 +304,22 @@ def hodlr_export_near(h: int, nb: int):
     col = np.empty(max(nnz.value, 1), dtype=np.int32)
     _check(lib().hodlr_export_near(C.c_void_p(h), C.byref(nnz), _np_ptr(ptr), _np_ptr(col)))
     return ptr, col[:nnz.value]
+
+
+def hodlr_export_near_level(h: int, level: int, nb: int):
+    nnz = C.c_int64()
+    _check(lib().hodlr_export_near_level(C.c_void_p(h), level, C.byref(nnz), None, None))
+    ptr = np.empty(nb + 1, dtype=np.int64)
+    col = np.empty(max(nnz.value, 1), dtype=np.int32)
+    _check(lib().hodlr_export_near_level(C.c_void_p(h), level, C.byref(nnz), _np_ptr(ptr),
+                                         _np_ptr(col)))
+    return ptr, col[:nnz.value]
+
+
+def hodlr_export_box_flags(h: int, level: int, nb: int):
+    f = np.empty(max(nb, 1), dtype=np.uint8)
+    _check(lib().hodlr_export_box_flags(C.c_void_p(h), level, _np_ptr(f)))
+    return f[:nb]
 
 
 def hodlr_export_factors(h: int, level: int, nnz: int):

@@ -100,7 +100,7 @@ hodlr_status hodlr_build(const double* points, int64_t N, int d, const hodlr_ker
     hodlr_opts o;
     hodlr_default_opts(&o);
     if (opts) o = *opts;
-    if (o.level_rule != 0 && o.level_rule != 1) return set_error(HODLR_EINVAL, "bad level_rule");
+    if (o.level_rule < 0 || o.level_rule > 2) return set_error(HODLR_EINVAL, "bad level_rule");
     if (o.storage != HODLR_FP64 && o.storage != HODLR_FP32 && o.storage != HODLR_BF16)
         return set_error(HODLR_EINVAL, "storage must be FP64, FP32 or BF16");
     if (o.has_domain && !(o.domain_side > 0.0 && std::isfinite(o.domain_side)))
@@ -392,7 +392,8 @@ hodlr_status hodlr_get_info(hodlr_t h, hodlr_info* info) {
         info->mfma_expand_factor_elems = h->mexp_felems;
         info->mfma_proj_elems = h->mt_total;
     }
-    info->near_entries = h->near_nnz;
+    info->near_entries = 0;
+    for (int l = 0; l <= h->kappa; ++l) info->near_entries += h->lev[l].near_nnz;
     info->near_pairs = h->near_pairs;
     info->device_bytes = h->device_bytes;
     for (int i = 0; i < 4; ++i) info->build_ms[i] = h->build_ms[i];
@@ -451,6 +452,31 @@ hodlr_status hodlr_export_near(hodlr_t h, int64_t* nnz, int64_t* ptr, int32_t* c
         if (col && h->near_nnz)
             HIP_CHECK(hipMemcpy(col, h->near_col, sizeof(int32_t) * h->near_nnz,
                                 hipMemcpyDeviceToHost));
+    });
+}
+
+hodlr_status hodlr_export_near_level(hodlr_t h, int level, int64_t* nnz, int64_t* ptr,
+                                     int32_t* col) {
+    if (!h) return set_error(HODLR_EINVAL, "null handle");
+    if (level < 0 || level > h->kappa) return set_error(HODLR_EINVAL, "level out of range");
+    return guarded([&] {
+        const auto& Lv = h->lev[level];
+        if (nnz) *nnz = Lv.near_nnz;
+        if (ptr)
+            HIP_CHECK(hipMemcpy(ptr, Lv.near_ptr, sizeof(int64_t) * (Lv.nb + 1),
+                                hipMemcpyDeviceToHost));
+        if (col && Lv.near_nnz)
+            HIP_CHECK(hipMemcpy(col, Lv.near_col, sizeof(int32_t) * Lv.near_nnz,
+                                hipMemcpyDeviceToHost));
+    });
+}
+
+hodlr_status hodlr_export_box_flags(hodlr_t h, int level, uint8_t* flags) {
+    if (!h) return set_error(HODLR_EINVAL, "null handle");
+    if (level < 0 || level > h->kappa) return set_error(HODLR_EINVAL, "level out of range");
+    return guarded([&] {
+        const auto& Lv = h->lev[level];
+        if (flags && Lv.nb) std::copy(Lv.hflags.begin(), Lv.hflags.end(), flags);
     });
 }
 

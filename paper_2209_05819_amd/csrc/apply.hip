@@ -1471,27 +1471,59 @@ void plan_apply(hodlr_t h) {
     }
     h->class_off[kNumClasses] = (int64_t)grp.size();
     // leaves: 64-row chunks, their near-field source ranges and, per level,
-    // the contribution segments of the box containing them
-    const auto& st = h->lev[kappa].hstart;
-    const int64_t nleaf = h->lev[kappa].nb;
-    std::vector<int64_t> nptr(nleaf + 1);
-    std::vector<int32_t> ncol(std::max<int64_t>(h->near_nnz, 1));
-    HIP_CHECK(hipMemcpy(nptr.data(), h->near_ptr, sizeof(int64_t) * (nleaf + 1),
-                        hipMemcpyDeviceToHost));
-    if (h->near_nnz)
-        HIP_CHECK(hipMemcpy(ncol.data(), h->near_col, sizeof(int32_t) * h->near_nnz,
+    // the contribution segments of the box containing them.  A leaf is a
+    // leaf box of any level (in a uniform tree: the boxes of level kappa);
+    // its rows take the dense pairs of every box containing them, from the
+    // root down to the leaf itself.
+    std::vector<std::vector<int64_t>> nptr(kappa + 1);
+    std::vector<std::vector<int32_t>> ncol(kappa + 1);
+    for (int l = 0; l <= kappa; ++l) {
+        const LevelData& Lv = h->lev[l];
+        if (!Lv.near_nnz) continue;
+        nptr[l].resize(Lv.nb + 1);
+        ncol[l].resize(Lv.near_nnz);
+        HIP_CHECK(hipMemcpy(nptr[l].data(), Lv.near_ptr, sizeof(int64_t) * (Lv.nb + 1),
                             hipMemcpyDeviceToHost));
+        HIP_CHECK(hipMemcpy(ncol[l].data(), Lv.near_col, sizeof(int32_t) * Lv.near_nnz,
+                            hipMemcpyDeviceToHost));
+    }
+    struct LeafRef {
+        int32_t a0, a1;
+        int level;
+    };
+    std::vector<LeafRef> leaves;
+    for (int l = 0; l <= kappa; ++l) {
+        const LevelData& Lv = h->lev[l];
+        for (int64_t A = 0; A < Lv.nb; ++A)
+            if (Lv.hflags[A] & 2) leaves.push_back(LeafRef{Lv.hstart[A], Lv.hstart[A + 1], l});
+    }
+    std::sort(leaves.begin(), leaves.end(),
+              [](const LeafRef& x, const LeafRef& y) { return x.a0 < y.a0; });
+    const int64_t nleaf = (int64_t)leaves.size();
     std::vector<NearItem> nr;
+    std::vector<int2> rng;
     h->near_max_ranges = 0;
-    for (int64_t A = 0; A < nleaf; ++A)
-        h->near_max_ranges = std::max<int64_t>(h->near_max_ranges, nptr[A + 1] - nptr[A]);
-    for (int64_t A = 0; A < nleaf; ++A)
-        for (int32_t i = st[A]; i < st[A + 1]; i += 64)
-            nr.push_back(NearItem{(int32_t)A, i, std::min(64, st[A + 1] - i), st[A], nptr[A],
-                                  (int32_t)(nptr[A + 1] - nptr[A]), 0});
-    std::vector<int2> rng(std::max<int64_t>(h->near_nnz, 1));
-    for (int64_t e = 0; e < h->near_nnz; ++e) rng[e] = make_int2(st[ncol[e]], st[ncol[e] + 1]);
-    std::vector<SegRef> seg((size_t)std::max(kappa, 1) * nleaf);
+    {
+        std::vector<int64_t> box(kappa + 1, 0);   // box of each level containing the leaf
+        for (int64_t t = 0; t < nleaf; ++t) {
+            const LeafRef& lf = leaves[t];
+            const int64_t nb0 = (int64_t)rng.size();
+            for (int l = 0; l <= lf.level; ++l) {
+                const auto& sl = h->lev[l].hstart;
+                while (sl[box[l] + 1] <= lf.a0) ++box[l];
+                if (nptr[l].empty()) continue;
+                const int64_t A = box[l];
+                for (int64_t e = nptr[l][A]; e < nptr[l][A + 1]; ++e)
+                    rng.push_back(make_int2(sl[ncol[l][e]], sl[ncol[l][e] + 1]));
+            }
+            const int32_t nn = (int32_t)((int64_t)rng.size() - nb0);
+            h->near_max_ranges = std::max<int64_t>(h->near_max_ranges, nn);
+            for (int32_t i = lf.a0; i < lf.a1; i += 64)
+                nr.push_back(NearItem{(int32_t)t, i, std::min(64, lf.a1 - i), lf.a0, nb0, nn, 0});
+        }
+    }
+    if (rng.empty()) rng.push_back(make_int2(0, 0));
+    std::vector<SegRef> seg((size_t)std::max(kappa, 1) * std::max<int64_t>(nleaf, 1));
     for (int l = 1; l <= kappa; ++l) {
         const auto& sl = h->lev[l].hstart;
         std::vector<int64_t> ptr(h->lev[l].nb + 1);
@@ -1499,11 +1531,14 @@ void plan_apply(hodlr_t h) {
                             hipMemcpyDeviceToHost));
         int64_t A = 0;
         for (int64_t leafb = 0; leafb < nleaf; ++leafb) {
-            while (sl[A + 1] <= st[leafb]) ++A;
+            const int32_t a0 = leaves[leafb].a0;
+            while (sl[A + 1] <= a0) ++A;
             SegRef& r = seg[(size_t)leafb * kappa + (l - 1)];
-            r.base = cbase[l][A] + (st[leafb] - sl[A]);
+            // below the leaf's own level the box holding its first row is
+            // inactive and has no entries
+            r.base = cbase[l][A] + (a0 - sl[A]);
             r.len = sl[A + 1] - sl[A];
-            r.ne = (int32_t)(ptr[A + 1] - ptr[A]);
+            r.ne = l <= leaves[leafb].level ? (int32_t)(ptr[A + 1] - ptr[A]) : 0;
         }
     }
     auto upload = [&](const void* src, size_t bytes, void** dst) {

@@ -206,6 +206,14 @@ struct LevelData {
     int64_t* eref = nullptr;     // device, per IL entry: (stored block << 1) | transposed
     int64_t blk0 = 0, nblk = 0;  // range in the global block table
     std::vector<int32_t> hstart; // host copy of start
+    // bit 0: active (its parent was subdivided); bit 1: leaf.  A uniform tree
+    // has every box active and its leaves on the last level.
+    uint8_t* flags = nullptr;    // device, nb
+    std::vector<uint8_t> hflags; // host copy
+    // dense near-field pairs of this level (rows: the level's boxes)
+    int64_t* near_ptr = nullptr;
+    int32_t* near_col = nullptr;
+    int64_t near_nnz = 0;
     bool has_factors = false;
 };
 

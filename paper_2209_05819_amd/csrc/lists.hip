@@ -10,6 +10,10 @@
 // 1..d-1 with A.  Candidates are enumerated from the parent's 3^d
 // neighbourhood; the children of a box are a contiguous key range, found by
 // binary search in the level's sorted keys.  Rows are sorted afterwards.
+// Adaptive tree (sec. 5.2 names it beside the balanced tree): only active
+// boxes (parent subdivided) take part; a pair that is not admissible is a
+// dense near-field pair of its level when either box is a leaf, so near
+// lists exist on every level that has leaves.
 #include <algorithm>
 
 #include "hodlr_impl.hpp"
@@ -42,10 +46,14 @@ __device__ __forceinline__ int64_t lower_bound(const uint64_t* __restrict__ key,
 
 // count (ptr == nullptr: out[A] = count) or fill (out = columns)
 __global__ void k_il(int level, int d, int adm, int64_t nb, const uint64_t* __restrict__ key,
-                     const int32_t* __restrict__ coord, const int64_t* __restrict__ ptr,
-                     int32_t* __restrict__ out) {
+                     const int32_t* __restrict__ coord, const uint8_t* __restrict__ flags,
+                     const int64_t* __restrict__ ptr, int32_t* __restrict__ out) {
     int64_t A = blockIdx.x * (int64_t)T + threadIdx.x;
     if (A >= nb) return;
+    if (!(flags[A] & 1)) {   // below a leaf: no lists
+        if (!ptr) out[A] = 0;
+        return;
+    }
     int32_t a[kMaxD], P[kMaxD], Q[kMaxD];
     for (int k = 0; k < d; ++k) {
         a[k] = coord[A * d + k];
@@ -74,7 +82,7 @@ __global__ void k_il(int level, int d, int adm, int64_t nb, const uint64_t* __re
         const int64_t lo = lower_bound(key, nb, kq << d);
         const int64_t hi = lower_bound(key, nb, (kq + 1) << d);
         for (int64_t B = lo; B < hi; ++B) {
-            if (B == A) continue;
+            if (B == A || !(flags[B] & 1)) continue;
             int mx = 0, eq = 0;
             for (int k = 0; k < d; ++k) {
                 int dc = abs(coord[B * d + k] - a[k]);
@@ -93,10 +101,15 @@ __global__ void k_il(int level, int d, int adm, int64_t nb, const uint64_t* __re
 }
 
 __global__ void k_near(int level, int d, int adm, int64_t nb, const uint64_t* __restrict__ key,
-                       const int32_t* __restrict__ coord, const int64_t* __restrict__ ptr,
-                       int32_t* __restrict__ out) {
+                       const int32_t* __restrict__ coord, const uint8_t* __restrict__ flags,
+                       const int64_t* __restrict__ ptr, int32_t* __restrict__ out) {
     int64_t A = blockIdx.x * (int64_t)T + threadIdx.x;
     if (A >= nb) return;
+    const int fa = flags[A];
+    if (!(fa & 1)) {
+        if (!ptr) out[A] = 0;
+        return;
+    }
     int32_t a[kMaxD], B[kMaxD];
     for (int k = 0; k < d; ++k) a[k] = coord[A * d + k];
     const int32_t ns = 1 << level;
@@ -119,7 +132,8 @@ __global__ void k_near(int level, int d, int adm, int64_t nb, const uint64_t* __
         if (!ok || nzero <= adm) continue;
         const uint64_t kb = interleave(B, level, d);
         const int64_t pos = lower_bound(key, nb, kb);
-        if (pos < nb && key[pos] == kb) {
+        // both active, and not subdivided further: one of them is a leaf
+        if (pos < nb && key[pos] == kb && (flags[pos] & 1) && ((fa | flags[pos]) & 2)) {
             if (ptr) out[base + cnt] = (int32_t)pos;
             ++cnt;
         }
@@ -207,11 +221,11 @@ void build_csr(hodlr_t h, int level, bool near, int64_t** ptr_out, int32_t** col
     int32_t* off32 = (int32_t*)dalloc(h, sizeof(int32_t) * (nb + 1));
     int64_t* ptr = (int64_t*)dalloc(h, sizeof(int64_t) * (nb + 1));
     if (near)
-        k_near<<<nblk(nb, T), T, 0, s>>>(level, h->d, h->opts.adm_dim, nb, Lv.key, Lv.coord, nullptr,
-                                         cnt);
+        k_near<<<nblk(nb, T), T, 0, s>>>(level, h->d, h->opts.adm_dim, nb, Lv.key, Lv.coord,
+                                         Lv.flags, nullptr, cnt);
     else
-        k_il<<<nblk(nb, T), T, 0, s>>>(level, h->d, h->opts.adm_dim, nb, Lv.key, Lv.coord, nullptr,
-                                       cnt);
+        k_il<<<nblk(nb, T), T, 0, s>>>(level, h->d, h->opts.adm_dim, nb, Lv.key, Lv.coord,
+                                       Lv.flags, nullptr, cnt);
     HIP_CHECK(hipGetLastError());
     // row counts fit in 32 bits; the offsets are widened before they can overflow
     int64_t* cnt64 = (int64_t*)dalloc(h, sizeof(int64_t) * (nb + 1));
@@ -227,10 +241,11 @@ void build_csr(hodlr_t h, int level, bool near, int64_t** ptr_out, int32_t** col
     int32_t* col = (int32_t*)dalloc(h, sizeof(int32_t) * std::max<int64_t>(nnz, 1));
     int32_t* tmp = (int32_t*)dalloc(h, sizeof(int32_t) * std::max<int64_t>(nnz, 1));
     if (near)
-        k_near<<<nblk(nb, T), T, 0, s>>>(level, h->d, h->opts.adm_dim, nb, Lv.key, Lv.coord, ptr,
-                                         tmp);
+        k_near<<<nblk(nb, T), T, 0, s>>>(level, h->d, h->opts.adm_dim, nb, Lv.key, Lv.coord,
+                                         Lv.flags, ptr, tmp);
     else
-        k_il<<<nblk(nb, T), T, 0, s>>>(level, h->d, h->opts.adm_dim, nb, Lv.key, Lv.coord, ptr, tmp);
+        k_il<<<nblk(nb, T), T, 0, s>>>(level, h->d, h->opts.adm_dim, nb, Lv.key, Lv.coord,
+                                       Lv.flags, ptr, tmp);
     HIP_CHECK(hipGetLastError());
     if (nnz > 0) segmented_sort_i32(tmp, col, nnz, nb, ptr, s);
     dfree(h, tmp);
@@ -247,22 +262,30 @@ void build_csr(hodlr_t h, int level, bool near, int64_t** ptr_out, int32_t** col
 void build_lists(hodlr_t h, hipStream_t s) {
     for (int l = 1; l <= h->kappa; ++l)
         build_csr(h, l, false, &h->lev[l].il_ptr, &h->lev[l].il_col, &h->lev[l].nnz, s);
-    build_csr(h, h->kappa, true, &h->near_ptr, &h->near_col, &h->near_nnz, s);
-    // number of point pairs of the near field (reported by hodlr_get_info)
-    const LevelData& Lk = h->lev[h->kappa];
-    std::vector<int64_t> ptr(Lk.nb + 1);
-    std::vector<int32_t> col(std::max<int64_t>(h->near_nnz, 1));
-    HIP_CHECK(hipMemcpyAsync(ptr.data(), h->near_ptr, sizeof(int64_t) * (Lk.nb + 1),
-                             hipMemcpyDeviceToHost, s));
-    HIP_CHECK(hipMemcpyAsync(col.data(), h->near_col, sizeof(int32_t) * h->near_nnz,
-                             hipMemcpyDeviceToHost, s));
-    HIP_CHECK(hipStreamSynchronize(s));
+    // dense pairs: on level kappa only in a uniform tree (the other levels
+    // have no leaves, their rows stay empty), on every level in an adaptive one
     int64_t pairs = 0;
-    for (int64_t A = 0; A < Lk.nb; ++A) {
-        int64_t m = Lk.hstart[A + 1] - Lk.hstart[A];
-        for (int64_t e = ptr[A]; e < ptr[A + 1]; ++e)
-            pairs += m * (Lk.hstart[col[e] + 1] - Lk.hstart[col[e]]);
+    for (int l = 0; l <= h->kappa; ++l) {
+        LevelData& Lk = h->lev[l];
+        build_csr(h, l, true, &Lk.near_ptr, &Lk.near_col, &Lk.near_nnz, s);
+        // number of point pairs of the near field (reported by hodlr_get_info)
+        if (!Lk.near_nnz) continue;
+        std::vector<int64_t> ptr(Lk.nb + 1);
+        std::vector<int32_t> col(Lk.near_nnz);
+        HIP_CHECK(hipMemcpyAsync(ptr.data(), Lk.near_ptr, sizeof(int64_t) * (Lk.nb + 1),
+                                 hipMemcpyDeviceToHost, s));
+        HIP_CHECK(hipMemcpyAsync(col.data(), Lk.near_col, sizeof(int32_t) * Lk.near_nnz,
+                                 hipMemcpyDeviceToHost, s));
+        HIP_CHECK(hipStreamSynchronize(s));
+        for (int64_t A = 0; A < Lk.nb; ++A) {
+            int64_t m = Lk.hstart[A + 1] - Lk.hstart[A];
+            for (int64_t e = ptr[A]; e < ptr[A + 1]; ++e)
+                pairs += m * (Lk.hstart[col[e] + 1] - Lk.hstart[col[e]]);
+        }
     }
+    h->near_ptr = h->lev[h->kappa].near_ptr;
+    h->near_col = h->lev[h->kappa].near_col;
+    h->near_nnz = h->lev[h->kappa].near_nnz;
     h->near_pairs = pairs;
 }
 

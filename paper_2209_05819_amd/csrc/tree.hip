@@ -274,6 +274,37 @@ void build_tree(hodlr_t h, const double* points_host, hipStream_t s) {
         if (l + 1 >= kMaxLevels) fail(HODLR_EUNSUPPORTED, "tree deeper than 31 levels");
     }
     h->kappa = l;
+    // active and leaf boxes (uniform rules: all active, leaves on level kappa;
+    // adaptive rule: a box is active when its parent holds more than `leaf`
+    // points, and an active box is a leaf when it holds at most `leaf` points
+    // or lies on level kappa)
+    for (int lv = 0; lv <= h->kappa; ++lv) {
+        LevelData& Lv = h->lev[lv];
+        Lv.hflags.assign((size_t)Lv.nb, 0);
+        const std::vector<int32_t>* ps = lv > 0 ? &h->lev[lv - 1].hstart : nullptr;
+        int64_t par = 0;
+        for (int64_t A = 0; A < Lv.nb; ++A) {
+            const int32_t cnt = Lv.hstart[A + 1] - Lv.hstart[A];
+            bool act, lf;
+            if (h->opts.level_rule != 2) {
+                act = true;
+                lf = lv == h->kappa;
+            } else {
+                act = true;
+                if (ps) {
+                    while ((*ps)[par + 1] <= Lv.hstart[A]) ++par;
+                    act = (*ps)[par + 1] - (*ps)[par] > h->leaf;
+                }
+                lf = act && (cnt <= h->leaf || lv == h->kappa);
+            }
+            Lv.hflags[A] = (uint8_t)((act ? 1 : 0) | (lf ? 2 : 0));
+        }
+        Lv.flags = (uint8_t*)dalloc(h, std::max<size_t>((size_t)Lv.nb, 1));
+        if (Lv.nb)
+            HIP_CHECK(hipMemcpyAsync(Lv.flags, Lv.hflags.data(), (size_t)Lv.nb,
+                                     hipMemcpyHostToDevice, s));
+    }
+    HIP_CHECK(hipStreamSynchronize(s));
     dfree(h, flag);
     dfree(h, pos);
     dfree(h, lo_side);

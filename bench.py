@@ -161,22 +161,65 @@ def multi_rhs(P, torch, W, steps, warmup, n_override=0):
     }
 
 
+def mixture_trees(P, torch, W, w, pts, q, steps=5):
+    """The 16-RHS BF16 product on the Gaussian-mixture cloud with the
+    closed-form balanced tree and with the adaptive tree: blocks, dense pairs,
+    factor bytes, build and product times, error against the direct sum on
+    256 sampled rows.  Returns (records, the adaptive handle)."""
+    import oracle
+    N, nrhs = w.N, q.shape[1]
+    k = P.make_kernel(w.kernel, h=w.h, diag=w.diag)
+    rows = np.sort(W.rng(211).choice(N, 256, replace=False))
+    bd = oracle.direct(pts, oracle.kernel(w.kernel, h=w.h, diag=w.diag), q, rows=rows)
+    X = torch.tensor(np.ascontiguousarray(q.T), dtype=torch.float32, device="cuda").t()
+    out, keep = {}, None
+    for name, rule in (("closed_form", 1), ("adaptive", 2)):
+        t0 = time.perf_counter()
+        H = P.HODLR(pts, k, w.leaf, w.tol, domain=w.domain, storage=P.BF16, level_rule=rule)
+        torch.cuda.synchronize()
+        build = time.perf_counter() - t0
+        Y = torch.empty((nrhs, N), dtype=torch.float32, device="cuda").t()
+        wall, per, _, _ = time_matvecs(P, torch, H, X, Y, P.FP32, 1, steps)
+        ms = wall / steps * 1e3
+        y = Y.t().contiguous().cpu().numpy().T.astype(np.float64)
+        info = H.info()
+        fe = sum(info.factor_elems[l] for l in range(1, info.kappa + 1))
+        nblk = sum(info.stored_blocks[l] for l in range(1, info.kappa + 1))
+        out[name] = {
+            "kappa": info.kappa, "stored_blocks": int(nblk),
+            "near_pairs": int(info.near_pairs), "factor_bytes": int(2 * fe),
+            "build_s": round(build, 2), "ms_per_product": ms,
+            "stage_ms": [round(float(v), 3) for v in per.mean(axis=0)],
+            "value": N * nrhs / (ms * 1e-3), "unit": "N*nrhs/s",
+            "rel_err": rel_err_rows(y, bd, rows),
+        }
+        print(f"[bench] mixture {name}: {ms:.2f} ms per 16-RHS product, "
+              f"near pairs {info.near_pairs:.3e}, build {build:.1f} s", file=sys.stderr, flush=True)
+        if rule == 2:
+            keep = H
+        else:
+            del H
+    return out, keep
+
+
 def solve_bench(P, torch, W, n_override=0):
     """GMRES with FP64 iterative refinement: (I + K/N) U = F on the 2^20-point
     Gaussian-mixture cloud (exp(-r^2/0.25), diagonal 1 + 1e-3, leaf 64, ACA
     1e-6), 16 N(0,1) right-hand sides; FP64 residuals on FP64 factors, inner
-    GMRES on BF16 factors, to a relative residual of 1e-10."""
+    GMRES on BF16 factors, to a relative residual of 1e-10.  Both
+    representations on the adaptive tree; the product on this cloud is
+    compared between the closed-form and the adaptive tree first."""
     w = W.WORKLOADS["mixture3d_gauss_n1048576"]
     if n_override:
         w = W.scaled(w, n_override)
     pts, q = w.points(), w.rhs()
     N, nrhs = w.N, q.shape[1]
     k = P.make_kernel(w.kernel, h=w.h, diag=w.diag)
+    trees, H16 = mixture_trees(P, torch, W, w, pts, q)
     t0 = time.perf_counter()
-    H64 = P.HODLR(pts, k, w.leaf, w.tol, domain=w.domain)
-    H16 = P.HODLR(pts, k, w.leaf, w.tol, domain=w.domain, storage=P.BF16)
+    H64 = P.HODLR(pts, k, w.leaf, w.tol, domain=w.domain, level_rule=2)
     torch.cuda.synchronize()
-    build = time.perf_counter() - t0
+    build = time.perf_counter() - t0 + trees["adaptive"]["build_s"]
     F = torch.tensor(np.ascontiguousarray(q.T), dtype=torch.float64, device="cuda").t()
     U = torch.zeros((nrhs, N), dtype=torch.float64, device="cuda").t()
     o = P.default_solve_opts()
@@ -192,12 +235,14 @@ def solve_bench(P, torch, W, n_override=0):
     return {
         "workload": w.name, "system": "(I + K/N) U = F", "N": N, "nrhs": nrhs,
         "kernel": "exp(-r^2/0.25), diag 1+1e-3", "leaf": w.leaf, "aca_tol": w.tol,
-        "tol": o.tol, "inner": "GMRES(30) on BF16 factors, f32 arithmetic, to 1e-3",
+        "tree": "adaptive", "tol": o.tol,
+        "inner": "GMRES(30) on BF16 factors, f32 arithmetic, to 1e-3",
         "outer": "FP64 residuals on FP64 factors", "converged": bool(info.converged),
         "rel_residual": info.rel_residual, "outer_iters": info.outer_iters,
         "inner_iters": info.inner_iters, "seconds": secs,
         "value": N * nrhs / secs, "unit": "N*nrhs/s solved", "build_s": round(build, 2),
         "history": [info.history[i] for i in range(min(info.outer_iters + 1, 64))],
+        "product_16rhs_bf16": trees,
     }
 
 

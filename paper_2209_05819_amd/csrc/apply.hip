@@ -1234,10 +1234,16 @@ __global__ __launch_bounds__(256) void k_skel(const BlockDesc* __restrict__ bloc
 // (coordinates, and x rows in the operand layout) and each wave multiplies
 // all 64 targets by 32 of them: 4 x CT 16x16x32 products per wave and tile.
 // The waves' partial sums meet in LDS in wave order; the level sums of the
-// low-rank part are added and the rows written to Y in user order.
+// low-rank part are added and the rows written to Y in user order.  The
+// kernel function (KIND) and the number of coordinates (DC = 3 for d <= 3,
+// 4 for d = 4) are fixed at compile time; padded sources sit at a far
+// sentinel point with x = 0 (finite kernel values times zero) and padded
+// target rows are computed but never written, so the pair loop carries no
+// masks; K rounds to BF16 with the hardware conversion (nearest even).
 constexpr int kNmTile = 128;
+constexpr float kNmFar = 1e18f;   // sentinel coordinate of padded sources
 
-template <typename XT, int CT>
+template <typename XT, int CT, int KIND, int DC>
 __global__ __launch_bounds__(256) void k_near_mfma(
     const NearItem* __restrict__ items, const int2* __restrict__ nrng,
     const double* __restrict__ pts, int64_t N, int d, KParams kp,
@@ -1305,7 +1311,8 @@ __global__ __launch_bounds__(256) void k_near_mfma(
             }
             s_j[sI] = j;
 #pragma unroll
-            for (int c = 0; c < 4; ++c) s_pt[c][sI] = (j >= 0 && c < d) ? (float)pts[c * N + j] : 0.f;
+            for (int c = 0; c < 4; ++c)
+                s_pt[c][sI] = j < 0 ? kNmFar : c < d ? (float)pts[c * N + j] : 0.f;
         }
         __syncthreads();
         for (int f = threadIdx.x; f < kNmTile * NRP; f += 256) {
@@ -1339,21 +1346,19 @@ __global__ __launch_bounds__(256) void k_near_mfma(
         }
 #pragma unroll
         for (int tm = 0; tm < 4; ++tm) {
-            u16x8_t kv;
+            if (16 * tm >= it.cnt) break;   // 16-row target tiles past the chunk's rows
+            bf16x8_t ka;
 #pragma unroll
             for (int e = 0; e < 8; ++e) {
                 float r2 = 0.f;
 #pragma unroll
-                for (int c = 0; c < 4; ++c) {
+                for (int c = 0; c < DC; ++c) {
                     const float dx = xt[tm][c] - sp[c][e];
                     r2 += dx * dx;
                 }
-                float kij = kfun(kp, r2);
-                if (sj[e] == ti[tm]) kij = (float)kp.diag;
-                if (sj[e] < 0 || ti[tm] < 0) kij = 0.f;
-                kv[e] = bf16_from_float(kij);
+                const float kij = sj[e] == ti[tm] ? (float)kp.diag : kfun_k<KIND>(kp, r2);
+                ka[e] = (__bf16)kij;
             }
-            const bf16x8_t ka = __builtin_bit_cast(bf16x8_t, kv);
 #pragma unroll
             for (int ct = 0; ct < CT; ++ct)
                 acc[tm][ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ka, xb[ct], acc[tm][ct], 0, 0, 0);
@@ -1747,11 +1752,28 @@ void run_matvec(hodlr_t h, const XT* X, int64_t ldx, int nrhs, XT* Y, int64_t ld
                 HIP_CHECK(hipGetLastError());
             }
             if (ev && c0 == 0) HIP_CHECK(hipEventRecord(ev[3], s));
-            if (h->near_max_ranges <= kNearTileRanges && h->d <= 4)
-                k_near_mfma<XT, CTn><<<(unsigned)h->n_near_items, 256, 0, s>>>(
-                    h->near_items, h->near_rng, h->pts, N, h->d, h->kp, xr, yl, h->perm, nc, c0, Y,
-                    ldy);
-            else
+            if (h->near_max_ranges <= kNearTileRanges && h->d <= 4) {
+                switch (h->kp.kind * 2 + (h->d == 4 ? 1 : 0)) {
+#define HODLR_NEAR_MFMA(K, DC)                                                                  \
+    case K * 2 + (DC == 4 ? 1 : 0):                                                             \
+        k_near_mfma<XT, CTn, K, DC><<<(unsigned)h->n_near_items, 256, 0, s>>>(                  \
+            h->near_items, h->near_rng, h->pts, N, h->d, h->kp, xr, yl, h->perm, nc, c0, Y, ldy); \
+        break;
+#define HODLR_NEAR_MFMA2(K) HODLR_NEAR_MFMA(K, 3) HODLR_NEAR_MFMA(K, 4)
+                    HODLR_NEAR_MFMA2(HODLR_K_LOG)
+                    HODLR_NEAR_MFMA2(HODLR_K_INV_R)
+                    HODLR_NEAR_MFMA2(HODLR_K_INV_R2)
+                    HODLR_NEAR_MFMA2(HODLR_K_GAUSS)
+                    HODLR_NEAR_MFMA2(HODLR_K_EXP)
+                    HODLR_NEAR_MFMA2(HODLR_K_R)
+                    HODLR_NEAR_MFMA2(HODLR_K_SIN)
+                    HODLR_NEAR_MFMA2(HODLR_K_INV_SQRT1P)
+#undef HODLR_NEAR_MFMA2
+#undef HODLR_NEAR_MFMA
+                    default:
+                        fail(HODLR_EINVAL, "unknown kernel function");
+                }
+            } else
                 k_gather_near<XT, C, NR><<<(unsigned)h->n_near_items, TG, 0, s>>>(
                     h->near_items, h->leaf_seg, h->near_rng, h->kappa, h->pts, N, h->d, h->kp, x,
                     contrib, CT, h->perm, nrhs, c0, Y, ldy, yl);

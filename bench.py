@@ -161,6 +161,78 @@ def multi_rhs(P, torch, W, steps, warmup, n_override=0):
     }
 
 
+def small_bench(P, torch, W, reps=200):
+    """The small workload (4096 points uniform in [-1,1]^2, log r, leaf 64,
+    ACA 1e-8, FP64, one U[-1,1] right-hand side): per-call latency of the
+    product launched eagerly and replayed from a captured HIP graph, and its
+    error against the direct N^2 sum on every row."""
+    import oracle
+    w = W.WORKLOADS["uniform2d_log_n4096"]
+    pts, q = w.points(), w.rhs()[:, 0]
+    N = w.N
+    H = P.HODLR(pts, P.make_kernel(w.kernel, h=w.h, diag=w.diag), w.leaf, w.tol, domain=w.domain,
+                level_rule=1)
+    P.hodlr_reserve_workspace(H.h, 1, P.FP64)
+    X = torch.tensor(q, dtype=torch.float64, device="cuda")
+    Y = torch.empty_like(X)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        for _ in range(3):
+            P.hodlr_matvec(H.h, X, Y)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        P.hodlr_matvec(H.h, X, Y)
+    torch.cuda.synchronize()
+
+    def per_call(fn):
+        ev = _events(torch, reps + 1)
+        ev[0].record()
+        for i in range(reps):
+            fn()
+            ev[i + 1].record()
+        torch.cuda.synchronize()
+        return np.array([ev[i].elapsed_time(ev[i + 1]) for i in range(reps)])
+
+    def wall_per_call(fn):
+        t = np.empty(reps)
+        for i in range(reps):
+            t0 = time.perf_counter()
+            fn()
+            torch.cuda.synchronize()
+            t[i] = (time.perf_counter() - t0) * 1e3
+        return t
+
+    eager = per_call(lambda: P.hodlr_matvec(H.h, X, Y))
+    graph = per_call(g.replay)
+    eager_w = wall_per_call(lambda: P.hodlr_matvec(H.h, X, Y))
+    graph_w = wall_per_call(g.replay)
+    y = Y.cpu().numpy()
+    bd = oracle.direct(pts, oracle.kernel(w.kernel, h=w.h, diag=w.diag), q[:, None])[:, 0]
+    err = float(np.linalg.norm(y - bd) / np.linalg.norm(bd))
+    info = H.info()
+    del g, H
+    return {
+        "workload": w.name, "N": N, "d": w.d, "kernel": "log r, diag 0", "leaf": w.leaf,
+        "aca_tol": w.tol, "kappa": info.kappa, "dtype": "f64",
+        "eager_p50_ms": float(np.percentile(eager, 50)),
+        "eager_p99_ms": float(np.percentile(eager, 99)),
+        "graph_p50_ms": float(np.percentile(graph, 50)),
+        "graph_p99_ms": float(np.percentile(graph, 99)),
+        "gpu_time": "HIP events between back-to-back calls on the stream",
+        "eager_wall_p50_ms": float(np.percentile(eager_w, 50)),
+        "eager_wall_p99_ms": float(np.percentile(eager_w, 99)),
+        "graph_wall_p50_ms": float(np.percentile(graph_w, 50)),
+        "graph_wall_p99_ms": float(np.percentile(graph_w, 99)),
+        "wall_time": "host clock, one call then a synchronisation (launch included)",
+        "value": N / (min(float(np.percentile(eager, 50)), float(np.percentile(graph, 50))) * 1e-3),
+        "unit": "N*nrhs/s (back-to-back, the faster of eager and graph)",
+        "rel_err": err, "rel_err_ref": "direct N^2 sum, every row",
+    }
+
+
 def mixture_trees(P, torch, W, w, pts, q, steps=5):
     """The 16-RHS BF16 product on the Gaussian-mixture cloud with the
     closed-form balanced tree and with the adaptive tree: blocks, dense pairs,
@@ -447,6 +519,8 @@ def main():
                     help="skip the 32-RHS BF16 matrix-core workload")
     ap.add_argument("--multi-rhs-n", type=int, default=0, help="override its N")
     ap.add_argument("--no-solve", action="store_true", help="skip the GMRES-IR solve")
+    ap.add_argument("--no-small", action="store_true",
+                    help="skip the small 2D workload (eager and graph-replayed latency)")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving measurement")
     ap.add_argument("--no-skeleton", action="store_true", help="skip the skeleton form")
     ap.add_argument("--no-adm", action="store_true",
@@ -553,6 +627,14 @@ def main():
     if not args.no_multi_rhs:
         mrhs = multi_rhs(P, torch, W, max(3, args.steps // 4), 1, args.multi_rhs_n)
 
+    small = None
+    if not args.no_small:
+        small = small_bench(P, torch, W)
+        print(f"[bench] small workload: eager {small['eager_p50_ms']:.3f} ms "
+              f"(wall {small['eager_wall_p50_ms']:.3f}), graph {small['graph_p50_ms']:.3f} ms "
+              f"(wall {small['graph_wall_p50_ms']:.3f}), rel err {small['rel_err']:.2e}",
+              file=sys.stderr, flush=True)
+
     solve = None
     if not args.no_solve:
         solve = solve_bench(P, torch, W, args.solve_n)
@@ -623,6 +705,7 @@ def main():
         "skeleton": skel,
         "multi_rhs": mrhs,
         "solve": solve,
+        "small": small,
         "serve": serve,
         "admissibility": adm,
         "cpu_baseline": cpu,

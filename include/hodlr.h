@@ -161,6 +161,17 @@ hodlr_status hodlr_matvec_events(hodlr_t h, const void* X, int64_t ldx, int nrhs
                                  void* Y, int64_t ldy, int compute_prec, void* stream,
                                  void* const* events, int nevents);
 
+/* Reserves the product's device workspace for nrhs columns in compute_prec
+ * (the largest request so far is kept).  hodlr_matvec reserves on demand;
+ * reserving first makes a later hodlr_matvec / hodlr_matvec_events with at
+ * most nrhs columns free of allocations, host synchronisation and memsets:
+ * only kernel launches (and events) on the caller's stream, so the call can
+ * be captured into a HIP graph and replayed (inputs and outputs at the
+ * captured addresses).  A call under stream capture that would have to grow
+ * the workspace returns HODLR_EINVAL instead.  EINVAL for a null handle,
+ * nrhs < 1 or a bad precision. */
+hodlr_status hodlr_reserve_workspace(hodlr_t h, int nrhs, int compute_prec);
+
 /* Options of hodlr_solve. */
 typedef struct {
     double tol;           /* outer stop: max over columns of |F - A U| / |F| (FP64 operator) */

@@ -131,6 +131,7 @@ def lib():
         L.hodlr_export_near.argtypes = [_P, C.POINTER(_i64), _P, _P]
         L.hodlr_export_near_level.argtypes = [_P, C.c_int, C.POINTER(_i64), _P, _P]
         L.hodlr_export_box_flags.argtypes = [_P, C.c_int, _P]
+        L.hodlr_reserve_workspace.argtypes = [_P, C.c_int, C.c_int]
         L.hodlr_export_factors.argtypes = [_P, C.c_int, _P, C.POINTER(_i64), C.POINTER(_i64),
                                            _P, _P]
         L.hodlr_import_factors.argtypes = [_P, C.c_int, _P, _P, _P]
@@ -139,7 +140,7 @@ def lib():
         for f in ("hodlr_build", "hodlr_matvec", "hodlr_matvec_events", "hodlr_get_info",
                   "hodlr_export_tree",
                   "hodlr_export_boxes", "hodlr_export_il", "hodlr_export_near",
-                  "hodlr_export_near_level", "hodlr_export_box_flags",
+                  "hodlr_export_near_level", "hodlr_export_box_flags", "hodlr_reserve_workspace",
                   "hodlr_export_factors", "hodlr_import_factors", "hodlr_solve",
                   "hodlr_server_create", "hodlr_server_add_set", "hodlr_server_submit",
                   "hodlr_server_wait", "hodlr_server_poll", "hodlr_server_get_stats"):
@@ -204,6 +205,12 @@ def hodlr_matvec(h: int, X, Y, compute_prec: int = FP64, stream=None) -> None:
         ldx, ldy = X.stride(1) if nrhs > 1 else N, Y.stride(1) if nrhs > 1 else N
     _check(lib().hodlr_matvec(C.c_void_p(h), C.c_void_p(X.data_ptr()), ldx, nrhs, xp,
                               C.c_void_p(Y.data_ptr()), ldy, compute_prec, _stream_ptr(stream)))
+
+
+def hodlr_reserve_workspace(h: int, nrhs: int, compute_prec: int = FP64) -> None:
+    """Reserve the product workspace so that later products with at most
+    nrhs columns only launch kernels (capturable into a HIP graph)."""
+    _check(lib().hodlr_reserve_workspace(C.c_void_p(h), nrhs, compute_prec))
 
 
 def _mv_args(X, Y):

@@ -185,6 +185,14 @@ hodlr_status matvec_checked(hodlr_t h, const void* X, int64_t ldx, int nrhs, int
 }
 }  // namespace
 
+hodlr_status hodlr_reserve_workspace(hodlr_t h, int nrhs, int compute_prec) {
+    if (!h) return set_error(HODLR_EINVAL, "null handle");
+    if (nrhs < 1) return set_error(HODLR_EINVAL, "nrhs must be >= 1");
+    if (compute_prec != HODLR_FP64 && compute_prec != HODLR_FP32)
+        return set_error(HODLR_EINVAL, "compute_prec must be FP64 or FP32");
+    return guarded([&] { hodlr::reserve_workspace(h, nrhs, compute_prec, nullptr); });
+}
+
 hodlr_status hodlr_matvec(hodlr_t h, const void* X, int64_t ldx, int nrhs, int x_prec, void* Y,
                           int64_t ldy, int compute_prec, void* stream) {
     return matvec_checked(h, X, ldx, nrhs, x_prec, Y, ldy, compute_prec, stream, nullptr, 0);

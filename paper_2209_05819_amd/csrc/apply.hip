@@ -1933,6 +1933,11 @@ void reserve_workspace(hodlr_t h, int nrhs, int compute_prec, hipStream_t s) {
     else
         need = cs * ((size_t)N * nrhs + (size_t)CT * nr + 2 * (size_t)TT * nr) + 4096;
     if (h->ws_bytes < need) {
+        // growing allocates and synchronises: not allowed inside a graph capture
+        hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+        if (s && hipStreamIsCapturing(s, &cap) == hipSuccess && cap != hipStreamCaptureStatusNone)
+            fail(HODLR_EINVAL, "workspace not reserved before stream capture "
+                               "(call hodlr_reserve_workspace first)");
         if (h->ws) {
             HIP_CHECK(hipStreamSynchronize(s));
             dfree(h, h->ws);

@@ -827,27 +827,49 @@ __device__ __forceinline__ void row_dot(gptr_t<S> row, int len,
 
 template <typename S, typename C, int NR>
 __global__ __launch_bounds__(TP) void k_project(const BlockDesc* __restrict__ blocks,
-                                                const WorkItem* __restrict__ items, int sym,
+                                                const ProjSeg* __restrict__ items, int sym,
                                                 const C* __restrict__ x, int64_t N, int nrhs,
-                                                int c0, int64_t TT, C* __restrict__ tb,
-                                                C* __restrict__ sb) {
+                                                int c0, C* __restrict__ part) {
     __shared__ C red[TP / 64][NR];
-    const WorkItem it = items[blockIdx.x];
-    const BlockDesc b = blocks[it.id];
-    const gptr_t<S> Ub = as_global<S>(b.U);
-    const gptr_t<S> Vb = as_global<S>(b.V);
+    const ProjSeg it = items[blockIdx.x];
+    const BlockDesc b = blocks[it.blk];
     const int nc = min(NR, nrhs - c0);
-    const C* __restrict__ xB = x + (int64_t)c0 * N + b.b0;
-    const C* __restrict__ xA = x + (int64_t)c0 * N + b.a0;
-    for (int k = it.lo; k < it.lo + it.cnt; ++k) {
-        C acc[NR];
-        row_dot<S, C, NR>(Vb + (int64_t)k * fstride<S>(b.n), b.n, xB, N, nc, acc);
-        wg_reduce_store<C, NR>(acc, red, nc, tb + b.toff + k, TT);
-        if (sym) {
-            row_dot<S, C, NR>(Ub + (int64_t)k * fstride<S>(b.m), b.m, xA, N, nc, acc);
-            wg_reduce_store<C, NR>(acc, red, nc, sb + b.toff + k, TT);
-        }
+    const int k = it.k;
+    C acc[NR];
+    {   // t_k partial: V[k, j0:j1] x_B[j0:j1]
+        const int ln = (b.n + it.nseg - 1) / it.nseg, j0 = it.seg * ln;
+        const int len = max(0, min(b.n, j0 + ln) - j0);
+        row_dot<S, C, NR>(as_global<S>(b.V) + (int64_t)k * fstride<S>(b.n) + j0, len,
+                          x + (int64_t)c0 * N + b.b0 + j0, N, nc, acc);
+        wg_reduce_store<C, NR>(acc, red, nc,
+                               part + ((it.p * 2 + 0) * kProjSegMax + it.seg) * NR, 1);
     }
+    if (sym) {   // s_k partial: U[i0:i1, k]^T x_A[i0:i1]
+        const int ln = (b.m + it.nseg - 1) / it.nseg, i0 = it.seg * ln;
+        const int len = max(0, min(b.m, i0 + ln) - i0);
+        row_dot<S, C, NR>(as_global<S>(b.U) + (int64_t)k * fstride<S>(b.m) + i0, len,
+                          x + (int64_t)c0 * N + b.a0 + i0, N, nc, acc);
+        wg_reduce_store<C, NR>(acc, red, nc,
+                               part + ((it.p * 2 + 1) * kProjSegMax + it.seg) * NR, 1);
+    }
+}
+
+// t_k (and s_k) of the segmented projections: the partials summed in segment
+// order, one thread per (term, side, column)
+template <typename C, int NR>
+__global__ void k_proj_sum(const ProjSum* __restrict__ sums, int64_t nsum, int sym, int nc,
+                           const C* __restrict__ part, int64_t TT, C* __restrict__ tb,
+                           C* __restrict__ sb) {
+    const int64_t t = blockIdx.x * (int64_t)256 + threadIdx.x;
+    if (t >= nsum * 2 * NR) return;
+    const int c = (int)(t % NR), side = (int)((t / NR) & 1);
+    const int64_t i = t / (2 * NR);
+    if (c >= nc || (side == 1 && !sym)) return;
+    const ProjSum S = sums[i];
+    const C* __restrict__ pp = part + (S.p * 2 + side) * kProjSegMax * NR + c;
+    C v = 0;
+    for (int g = 0; g < S.nseg; ++g) v += pp[(int64_t)g * NR];
+    (side ? sb : tb)[(int64_t)c * TT + S.dst] = v;
 }
 
 // 64-row chunk of one side of a large block: side 0 writes U t into the rows
@@ -1400,7 +1422,9 @@ __global__ __launch_bounds__(256) void k_near_mfma(
 void plan_apply(hodlr_t h) {
     const int kappa = h->kappa;
     std::vector<int32_t> fused;
-    std::vector<WorkItem> proj, ex;
+    std::vector<ProjSeg> proj;
+    std::vector<ProjSum> psum;
+    std::vector<WorkItem> ex;
     // contribution offsets: per level, per box, the box's IL entries in order,
     // |A| values each
     std::vector<std::vector<int64_t>> cbase(kappa + 1);
@@ -1455,9 +1479,14 @@ void plan_apply(hodlr_t h) {
         } else {
             ++h->split_blocks;
             h->split_felems += el;
-            const int per = 1;
-            for (int k = 0; k < bd.rank; k += per)
-                proj.push_back(WorkItem{(int32_t)b, k, std::min(per, bd.rank - k), bd.level});
+            // rows split into segments of at least 4096 so that enough
+            // workgroups stream the few large blocks at once
+            const int nseg = std::max(1, std::min(kProjSegMax, std::max(bd.m, bd.n) / 4096));
+            for (int k = 0; k < bd.rank; ++k) {
+                const int64_t pidx = (int64_t)psum.size();
+                psum.push_back(ProjSum{bd.toff + k, pidx, nseg, 0});
+                for (int g = 0; g < nseg; ++g) proj.push_back(ProjSeg{(int32_t)b, k, g, nseg, pidx});
+            }
             for (int32_t i = 0; i < bd.m; i += 64)
                 ex.push_back(WorkItem{(int32_t)b, i, std::min(64, bd.m - i), 0});
             if (h->opts.symmetric)
@@ -1555,8 +1584,10 @@ void plan_apply(hodlr_t h) {
     std::vector<BlockDesc> cbd(grp.size());
     for (size_t t = 0; t < grp.size(); ++t) cbd[t] = h->hblocks[grp[t]];
     upload(cbd.data(), sizeof(BlockDesc) * cbd.size(), (void**)&h->class_blocks);
-    upload(proj.data(), sizeof(WorkItem) * proj.size(), (void**)&h->proj_items);
+    upload(proj.data(), sizeof(ProjSeg) * proj.size(), (void**)&h->proj_items);
     h->n_proj_items = (int64_t)proj.size();
+    upload(psum.data(), sizeof(ProjSum) * psum.size(), (void**)&h->proj_sums);
+    h->n_proj_sums = (int64_t)psum.size();
     upload(ex.data(), sizeof(WorkItem) * ex.size(), (void**)&h->exp_items);
     h->n_exp_items = (int64_t)ex.size();
     upload(nr.data(), sizeof(NearItem) * nr.size(), (void**)&h->near_items);
@@ -1692,6 +1723,7 @@ void run_matvec(hodlr_t h, const XT* X, int64_t ldx, int nrhs, XT* Y, int64_t ld
     C* contrib = x + N * nrhs;
     C* tb = contrib + CT * NR;
     C* sb = tb + TT * NR;
+    C* pp = sb + TT * NR;   // partials of the segmented projections
     const int sym = h->opts.symmetric ? 1 : 0;
     if (ev) HIP_CHECK(hipEventRecord(ev[0], s));
     k_permute_in<XT, C><<<nblk(N, 256), 256, 0, s>>>(X, ldx, nrhs, N, h->perm, x);
@@ -1852,9 +1884,12 @@ void run_matvec(hodlr_t h, const XT* X, int64_t ldx, int nrhs, XT* Y, int64_t ld
                 k_lr_fused<S, C, NR, RMAX><<<(unsigned)cnt, 64, 0, s>>>(
                     h->class_blocks, sym, x, N, nrhs, c0, CT, contrib);
         }
-        if (h->n_proj_items)
+        if (h->n_proj_items) {
             k_project<S, C, NR><<<(unsigned)h->n_proj_items, TP, 0, s>>>(
-                h->blocks, h->proj_items, sym, x, N, nrhs, c0, TT, tb, sb);
+                h->blocks, h->proj_items, sym, x, N, nrhs, c0, pp);
+            k_proj_sum<C, NR><<<nblk(h->n_proj_sums * 2 * NR, 256), 256, 0, s>>>(
+                h->proj_sums, h->n_proj_sums, sym, std::min(NR, nrhs - c0), pp, TT, tb, sb);
+        }
         HIP_CHECK(hipGetLastError());
         if (ev && c0 == 0) HIP_CHECK(hipEventRecord(ev[2], s));
         if (h->n_exp_items)
@@ -1931,7 +1966,8 @@ void reserve_workspace(hodlr_t h, int nrhs, int compute_prec, hipStream_t s) {
                align256(2 * (size_t)std::max<int64_t>(h->mt_total, 1) * nr) +
                4 * (size_t)std::max<int64_t>(h->mpart_total, 1) * nr + 4096;
     else
-        need = cs * ((size_t)N * nrhs + (size_t)CT * nr + 2 * (size_t)TT * nr) + 4096;
+        need = cs * ((size_t)N * nrhs + (size_t)CT * nr + 2 * (size_t)TT * nr +
+                     2 * (size_t)kProjSegMax * (size_t)h->n_proj_sums * nr) + 4096;
     if (h->ws_bytes < need) {
         // growing allocates and synchronises: not allowed inside a graph capture
         hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;

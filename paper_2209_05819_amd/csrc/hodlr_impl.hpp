@@ -244,6 +244,21 @@ struct MTile {          // rows of a target box A at one level applied by one wo
     int32_t ne, pad;
 };
 
+// Projections of a block too large for one workgroup: term k of block blk,
+// rows segment seg of nseg of both sides; its partial sums go to slot p of
+// the partial buffer, [p][side][seg][column].
+constexpr int kProjSegMax = 16;
+struct ProjSeg {
+    int32_t blk, k, seg, nseg;
+    int64_t p;
+};
+// the sum of a term's nseg partials, in segment order, into t (and s) at
+// offset dst (the block's term offset plus k)
+struct ProjSum {
+    int64_t dst, p;
+    int32_t nseg, pad;
+};
+
 struct WorkItem {   // launch planning record: a block (or box) and a sub-range
     int32_t id;
     int32_t lo;
@@ -283,7 +298,10 @@ struct hodlr_handle_s {
     std::vector<int64_t> class_off;        // class c: [class_off[c], class_off[c+1])
     int64_t cls_felems[8]{}, cls_velems[8]{};  // factor / vector elements per class
     int64_t split_blocks = 0, split_felems = 0;
-    hodlr::WorkItem* proj_items = nullptr; // row ranges of the blocks too large for one wave
+    hodlr::ProjSeg* proj_items = nullptr;  // segmented projections of the blocks too large
+                                           // for one workgroup
+    hodlr::ProjSum* proj_sums = nullptr;   // their per-term sums
+    int64_t n_proj_sums = 0;
     int64_t n_proj_items = 0;
     hodlr::WorkItem* exp_items = nullptr;  // 64-row chunks of those blocks (level = side)
     int64_t n_exp_items = 0;

@@ -295,3 +295,43 @@ def test_error_paths(P):
     with pytest.raises(P.HodlrError) as e:
         _build(P, pts, k, 8, 1e-6, mem_budget_bytes=1000)
     assert e.value.status == 2
+
+
+@pytest.mark.parametrize("sym", [False, True])
+def test_split_blocks_with_oracle_factors(P, orc, sym):
+    """Blocks wider than one workgroup's range (the segmented projection):
+    1D, 40000 points, level-1 boxes of 20000 rows (4 segments of the rows),
+    levels 2 and 3 split as well; oracle factors, within 1e-13 (FP64)."""
+    _say(f"[split] sym={sym}")
+    N = 40000
+    pts = W.uniform_points(N, 1, 91)
+    ko = orc.kernel("inv_r")
+    o = orc.OracleHODLR(pts, 64, 1, domain=(np.full(1, -1.0), 2.0))
+    o.compress(ko, 1e-10)
+    H = _build(P, pts, P.make_kernel("inv_r"), 64, 1e-10, level_rule=1,
+               domain=(np.full(1, -1.0), 2.0), skip_aca=True, symmetric=sym)
+    for l in range(1, o.kappa + 1):
+        if sym:
+            r, U, V = _symmetrize(o, l)
+            o.set_factors(l, r, U, V)
+        r, U, V = o.factors(l)
+        P.hodlr_import_factors(H.h, l, r, U, V)
+    assert H.info().split_blocks > 0
+    q = W.rhs_normal(N, 3, 92)
+    b_or = o.matvec(ko, q)
+    for nr in (1, 3):
+        qq = q[:, 0] if nr == 1 else q
+        bo = b_or[:, 0] if nr == 1 else b_or
+        bg = _gpu_matvec(P, H, qq)
+        assert _rel(bg, bo) <= 1e-13
+    # FP32 arithmetic on the same split structure, smooth kernel (with 1/r the
+    # closest of 40000 random points on a line, ~1e-9 apart, make FP32
+    # coordinates meaningless): within 1e-5 of the FP64 arithmetic
+    G = _build(P, pts, P.make_kernel("gauss", h=0.5, diag=1.001), 64, 1e-10, level_rule=1,
+               domain=(np.full(1, -1.0), 2.0), symmetric=sym)
+    assert G.info().split_blocks > 0
+    for nr in (1, 3):
+        qq = q[:, 0] if nr == 1 else q
+        b64 = _gpu_matvec(P, G, qq)
+        b32 = _gpu_matvec(P, G, qq, x_dtype="f32", compute=P.FP32)
+        assert _rel(b32, b64) <= 1e-5

@@ -520,6 +520,19 @@ constexpr int MSMALL = 192;   // boxes up to this many rows: one wave (12 row ti
 constexpr int MBIGW = 4;      // larger boxes: workgroups of 4 waves x 128 rows
 constexpr int MPAD = 8;       // LDS row padding of a staged chunk (elements)
 
+// Workgroups are dispatched to the 8 XCDs in turn (workgroup i to XCD i mod
+// 8), each XCD with its own L2.  With a grid of 8 ceil(n / 8) workgroups,
+// this maps the workgroups of one XCD to one contiguous range of the n
+// items, so items that read the same data (jobs sorted by the x slice they
+// read) share that XCD's L2.  Returns -1 for the padding past n.
+constexpr int kXcds = 8;
+__device__ __forceinline__ int64_t xcd_item(int64_t n) {
+    const int64_t per = (n + kXcds - 1) / kXcds;
+    const int64_t j = (int64_t)(blockIdx.x % kXcds) * per + blockIdx.x / kXcds;
+    return j < n ? j : -1;
+}
+inline unsigned xcd_grid(int64_t n) { return (unsigned)(kXcds * ((n + kXcds - 1) / kXcds)); }
+
 // orders this wave's LDS accesses (a staged chunk is written and read by
 // different lanes of the same wave)
 __device__ __forceinline__ void wave_lds_fence() { asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory"); }
@@ -550,13 +563,15 @@ __device__ __forceinline__ int64_t tidx(int64_t base, int k, int c, int nrp) {
 }
 
 template <int W, int CT>
-__global__ __launch_bounds__(64 * W) void k_mproj(const MJob* __restrict__ jobs,
+__global__ __launch_bounds__(64 * W) void k_mproj(const MJob* __restrict__ jobs, int64_t njobs,
                                                   const uint16_t* __restrict__ xr,
                                                   uint16_t* __restrict__ tproj,
                                                   float* __restrict__ part) {
     constexpr int NRP = 16 * CT;
     __shared__ f32x4_t red[W > 1 ? W : 1][CT][64];
-    const MJob J = jobs[blockIdx.x];
+    const int64_t jx = xcd_item(njobs);
+    if (jx < 0) return;   // padding of the last XCD's range (whole workgroup)
+    const MJob J = jobs[jx];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int a = lane & 15, q = lane >> 4;
     const int64_t ld = fstride<bf16>(J.len);
@@ -1643,8 +1658,13 @@ void plan_apply(hodlr_t h) {
         std::vector<MJob> mj;
         h->mjob_off.assign(5, 0);
         for (int c = 0; c < 4; ++c) {
-            std::stable_sort(jobs[c].begin(), jobs[c].end(),
-                             [](const auto& a, const auto& b) { return a.first > b.first; });
+            // by the x slice they read (first row, then panel), larger first
+            // among equals: an XCD's contiguous range of jobs reuses x in its L2
+            std::stable_sort(jobs[c].begin(), jobs[c].end(), [](const auto& a, const auto& b) {
+                if (a.second.x0 != b.second.x0) return a.second.x0 < b.second.x0;
+                if (a.second.p0 != b.second.p0) return a.second.p0 < b.second.p0;
+                return a.first > b.first;
+            });
             h->mjob_off[c] = (int64_t)mj.size();
             for (auto& p : jobs[c]) {
                 mj.push_back(p.second);
@@ -1753,12 +1773,12 @@ void run_matvec(hodlr_t h, const XT* X, int64_t ldx, int nrhs, XT* Y, int64_t ld
                 const int64_t n0 = h->mjob_off[w], cnt = h->mjob_off[w + 1] - n0;
                 if (cnt) {
                     const MJob* jb = h->mjobs + n0;
-                    const unsigned g = (unsigned)cnt;
+                    const unsigned g = xcd_grid(cnt);
                     switch (w) {
-                    case 0: k_mproj<1, CTn><<<g, 64, 0, s>>>(jb, xr, tproj, part); break;
-                    case 1: k_mproj<2, CTn><<<g, 128, 0, s>>>(jb, xr, tproj, part); break;
-                    case 2: k_mproj<4, CTn><<<g, 256, 0, s>>>(jb, xr, tproj, part); break;
-                    default: k_mproj<8, CTn><<<g, 512, 0, s>>>(jb, xr, tproj, part); break;
+                    case 0: k_mproj<1, CTn><<<g, 64, 0, s>>>(jb, cnt, xr, tproj, part); break;
+                    case 1: k_mproj<2, CTn><<<g, 128, 0, s>>>(jb, cnt, xr, tproj, part); break;
+                    case 2: k_mproj<4, CTn><<<g, 256, 0, s>>>(jb, cnt, xr, tproj, part); break;
+                    default: k_mproj<8, CTn><<<g, 512, 0, s>>>(jb, cnt, xr, tproj, part); break;
                     }
                     HIP_CHECK(hipGetLastError());
                 }

@@ -534,8 +534,15 @@ __device__ __forceinline__ int64_t xcd_item(int64_t n) {
 inline unsigned xcd_grid(int64_t n) { return (unsigned)(kXcds * ((n + kXcds - 1) / kXcds)); }
 
 // orders this wave's LDS accesses (a staged chunk is written and read by
-// different lanes of the same wave)
-__device__ __forceinline__ void wave_lds_fence() { asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory"); }
+// different lanes of the same wave).  The LDS executes one wave's
+// instructions in issue order, so only the compiler must not move them
+// across: wavefront-scope fences and a wave barrier, which emit no wait (an
+// explicit wait here would also hold back the prefetched global loads).
+__device__ __forceinline__ void wave_lds_fence() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 
 // x in tree order, row-major N x nrp, BF16 (columns c0 .. c0 + nc of X; the
 // remaining columns zero)
@@ -694,43 +701,45 @@ __global__ __launch_bounds__(64 * TW, RT > 8 ? 2 : 4) void k_mexp(
         for (int ct = 0; ct < CT; ++ct) acc[it][ct] = f32x4_t{0.f, 0.f, 0.f, 0.f};
     // (entry, 16-term chunk) pairs in order; the loads of the next pair are
     // issued before the current one is multiplied
-    auto load_words = [&](const MEnt& E, int k0, u32x4 (&w)[NWORD]) {
+    // Buffer loads: a lane with nothing to load (term past the rank, row past
+    // the box, or no next chunk) gets an offset past the resource's range
+    // and reads zero by the hardware range check, so the loads carry no
+    // per-lane branch and no select on their results; the wait before a
+    // multiply then counts only that chunk's loads.  The whole offset is the
+    // per-lane operand (the one the range check covers).
+    auto rsrc = [](uint64_t base) {
+        return __builtin_amdgcn_make_buffer_rsrc((void*)base, (short)0, 0x7fffffff, 0x00020000);
+    };
+    auto load_words = [&](const MEnt& E, int k0, u32x4 (&w)[NWORD], bool valid = true) {
+        const __amdgpu_buffer_rsrc_t rs = rsrc(E.F);
 #pragma unroll
         for (int sI = 0; sI < NWORD; ++sI) {
             const int f = lane + 64 * sI, tt = f / (WR / 8), g = f % (WR / 8);
-            w[sI] = u32x4{0u, 0u, 0u, 0u};
-            if (k0 + tt < E.r && 8 * g < wrows)
-                w[sI] = *as_global<u32x4>(E.F + 2 * ((int64_t)(k0 + tt) * ld + T.rowoff + wrow + 8 * g));
+            const bool ok = valid && k0 + tt < E.r && 8 * g < wrows;
+            const uint32_t off =
+                ok ? (uint32_t)(2 * ((int64_t)(k0 + tt) * ld + T.rowoff + wrow + 8 * g)) : 0x80000000u;
+            w[sI] = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(rs, (int)off, 0, 0));
         }
     };
     // the chunk's projections, 16 terms x NRP contiguous (16-byte word per lane)
-    auto load_t = [&](const MEnt& E, int k0, u32x4& tw) {
-        tw = u32x4{0u, 0u, 0u, 0u};
-        if (8 * lane < 16 * NRP)
-            tw = *reinterpret_cast<const u32x4*>(tproj + (E.t + k0) * NRP + 8 * lane);
+    auto load_t = [&](const MEnt& E, int k0, u32x4& tw, bool valid = true) {
+        const __amdgpu_buffer_rsrc_t rs = rsrc((uint64_t)(tproj + (E.t + k0) * NRP));
+        const bool ok = valid && 8 * lane < 16 * NRP;
+        const uint32_t off = ok ? (uint32_t)(16 * lane) : 0x80000000u;
+        tw = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(rs, (int)off, 0, 0));
     };
-    int e = 0;
-    MEnt E{};
-    while (e < T.ne && (E = ents[T.e0 + e]).r <= 0) ++e;
-    int k0 = 0, par = 0;
-    u32x4 w[NWORD], tw;
-    if (e < T.ne) {
-        load_words(E, k0, w);
-        if (TW == 1 || wv == 0) load_t(E, k0, tw);
-    }
-    while (e < T.ne) {
-        int en = e, kn = k0 + 16;
-        MEnt En = E;
-        if (kn >= E.r) {
-            kn = 0;
-            ++en;
-            while (en < T.ne && (En = ents[T.e0 + en]).r <= 0) ++en;
+    // the (entry, chunk) sequence: the pair after (e, k0) of entry E
+    auto advance = [&](int& ee, int& kk, MEnt& EE) {
+        kk += 16;
+        if (kk >= EE.r) {
+            kk = 0;
+            ++ee;
+            while (ee < T.ne && (EE = ents[T.e0 + ee]).r <= 0) ++ee;
         }
-        u32x4 wn[NWORD], tn;
-        if (en < T.ne) {
-            load_words(En, kn, wn);
-            if (TW == 1 || wv == 0) load_t(En, kn, tn);
-        }
+    };
+    int par = 0;
+    // multiply one staged chunk (projections tw, factor words w)
+    auto process = [&](const u32x4 (&w)[NWORD], const u32x4& tw) {
         // the projections as the A operand: lane (a, q) takes terms
         // k0 + 4 q .. + 3 of right-hand side 16 ct + a
         s16x4_t ta[CT];
@@ -765,14 +774,65 @@ __global__ __launch_bounds__(64 * TW, RT > 8 ? 2 : 4) void k_mexp(
                     acc[it][ct] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ta[ct], up, acc[it][ct], 0, 0, 0);
             }
         }
-        if (en >= T.ne) break;
-#pragma unroll
-        for (int sI = 0; sI < NWORD; ++sI) w[sI] = wn[sI];
-        tw = tn;
-        e = en;
-        k0 = kn;
-        E = En;
         par ^= 1;
+    };
+    int e = 0, k0 = 0;
+    MEnt E{};
+    while (e < T.ne && (E = ents[T.e0 + e]).r <= 0) ++e;
+    if constexpr (TW == 1) {
+        // two register buffers in turn: while one chunk is multiplied the
+        // loads of the next are in flight (no copy between the buffers, which
+        // would wait for those loads)
+        u32x4 wa[NWORD], ta_w, wb[NWORD], tb_w;
+        if (e < T.ne) {
+            load_words(E, k0, wa);
+            load_t(E, k0, ta_w);
+        }
+        // the loads are issued every time (past the last chunk all lanes
+        // read the zero word), so the wait before a multiply can count the
+        // other buffer's loads as still in flight
+        for (;;) {
+            if (e >= T.ne) break;
+            advance(e, k0, E);   // the chunk after the one in wa
+            load_words(E, k0, wb, e < T.ne);
+            load_t(E, k0, tb_w, e < T.ne);
+            __builtin_amdgcn_sched_barrier(0);
+            process(wa, ta_w);
+            __builtin_amdgcn_sched_barrier(0);
+            if (e >= T.ne) break;
+            advance(e, k0, E);   // the chunk after the one in wb
+            load_words(E, k0, wa, e < T.ne);
+            load_t(E, k0, ta_w, e < T.ne);
+            __builtin_amdgcn_sched_barrier(0);
+            process(wb, tb_w);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    } else {
+        // several waves share the projections through LDS: one buffer for
+        // the next chunk (registers are short at four waves per SIMD)
+        u32x4 w[NWORD], tw;
+        if (e < T.ne) {
+            load_words(E, k0, w);
+            if (wv == 0) load_t(E, k0, tw);
+        }
+        while (e < T.ne) {
+            int en = e, kn = k0;
+            MEnt En = E;
+            advance(en, kn, En);
+            u32x4 wn[NWORD], tn;
+            if (en < T.ne) {
+                load_words(En, kn, wn);
+                if (wv == 0) load_t(En, kn, tn);
+            }
+            process(w, tw);
+            if (en >= T.ne) break;
+#pragma unroll
+            for (int sI = 0; sI < NWORD; ++sI) w[sI] = wn[sI];
+            tw = tn;
+            e = en;
+            k0 = kn;
+            E = En;
+        }
     }
     // lane (a, q) holds C[row 16 it + a][rhs 16 ct + 4 q + e]
 #pragma unroll

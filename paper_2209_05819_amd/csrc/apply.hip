@@ -716,8 +716,11 @@ __global__ __launch_bounds__(64 * TW, RT > 8 ? 2 : 4) void k_mexp(
         for (int sI = 0; sI < NWORD; ++sI) {
             const int f = lane + 64 * sI, tt = f / (WR / 8), g = f % (WR / 8);
             const bool ok = valid && k0 + tt < E.r && 8 * g < wrows;
-            const uint32_t off =
-                ok ? (uint32_t)(2 * ((int64_t)(k0 + tt) * ld + T.rowoff + wrow + 8 * g)) : 0x80000000u;
+            // below 2^31 for any term up to r + 16 of a factor; moved past the
+            // range by adding 2^31 (arithmetic, not a select the compiler
+            // could turn into branches)
+            const uint32_t off = (uint32_t)(2 * ((int64_t)(k0 + tt) * ld + T.rowoff + wrow + 8 * g)) +
+                                 ((uint32_t)!ok << 31);
             w[sI] = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(rs, (int)off, 0, 0));
         }
     };
@@ -725,7 +728,7 @@ __global__ __launch_bounds__(64 * TW, RT > 8 ? 2 : 4) void k_mexp(
     auto load_t = [&](const MEnt& E, int k0, u32x4& tw, bool valid = true) {
         const __amdgpu_buffer_rsrc_t rs = rsrc((uint64_t)(tproj + (E.t + k0) * NRP));
         const bool ok = valid && 8 * lane < 16 * NRP;
-        const uint32_t off = ok ? (uint32_t)(16 * lane) : 0x80000000u;
+        const uint32_t off = (uint32_t)(16 * lane) + ((uint32_t)!ok << 31);
         tw = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(rs, (int)off, 0, 0));
     };
     // the (entry, chunk) sequence: the pair after (e, k0) of entry E

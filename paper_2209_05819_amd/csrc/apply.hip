@@ -782,59 +782,32 @@ __global__ __launch_bounds__(64 * TW, RT > 8 ? 2 : 4) void k_mexp(
     int e = 0, k0 = 0;
     MEnt E{};
     while (e < T.ne && (E = ents[T.e0 + e]).r <= 0) ++e;
-    if constexpr (TW == 1) {
+    {
         // two register buffers in turn: while one chunk is multiplied the
         // loads of the next are in flight (no copy between the buffers, which
-        // would wait for those loads)
+        // would wait for those loads).  The loads are issued every time (past
+        // the last chunk all lanes read zero), so the wait before a multiply
+        // can count the other buffer's loads as still in flight.  With
+        // several waves only wave 0 loads the projections.
+        const bool ldt = TW == 1 || wv == 0;
         u32x4 wa[NWORD], ta_w, wb[NWORD], tb_w;
-        if (e < T.ne) {
-            load_words(E, k0, wa);
-            load_t(E, k0, ta_w);
-        }
-        // the loads are issued every time (past the last chunk all lanes
-        // read the zero word), so the wait before a multiply can count the
-        // other buffer's loads as still in flight
+        load_words(E, k0, wa, e < T.ne);
+        load_t(E, k0, ta_w, e < T.ne && ldt);
         for (;;) {
             if (e >= T.ne) break;
             advance(e, k0, E);   // the chunk after the one in wa
             load_words(E, k0, wb, e < T.ne);
-            load_t(E, k0, tb_w, e < T.ne);
+            load_t(E, k0, tb_w, e < T.ne && ldt);
             __builtin_amdgcn_sched_barrier(0);
             process(wa, ta_w);
             __builtin_amdgcn_sched_barrier(0);
             if (e >= T.ne) break;
             advance(e, k0, E);   // the chunk after the one in wb
             load_words(E, k0, wa, e < T.ne);
-            load_t(E, k0, ta_w, e < T.ne);
+            load_t(E, k0, ta_w, e < T.ne && ldt);
             __builtin_amdgcn_sched_barrier(0);
             process(wb, tb_w);
             __builtin_amdgcn_sched_barrier(0);
-        }
-    } else {
-        // several waves share the projections through LDS: one buffer for
-        // the next chunk (registers are short at four waves per SIMD)
-        u32x4 w[NWORD], tw;
-        if (e < T.ne) {
-            load_words(E, k0, w);
-            if (wv == 0) load_t(E, k0, tw);
-        }
-        while (e < T.ne) {
-            int en = e, kn = k0;
-            MEnt En = E;
-            advance(en, kn, En);
-            u32x4 wn[NWORD], tn;
-            if (en < T.ne) {
-                load_words(En, kn, wn);
-                if (wv == 0) load_t(En, kn, tn);
-            }
-            process(w, tw);
-            if (en >= T.ne) break;
-#pragma unroll
-            for (int sI = 0; sI < NWORD; ++sI) w[sI] = wn[sI];
-            tw = tn;
-            e = en;
-            k0 = kn;
-            E = En;
         }
     }
     // lane (a, q) holds C[row 16 it + a][rhs 16 ct + 4 q + e]

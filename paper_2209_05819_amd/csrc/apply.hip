@@ -584,8 +584,16 @@ __global__ __launch_bounds__(64 * W) void k_mproj(const MJob* __restrict__ jobs,
     const int64_t ld = fstride<bf16>(J.len);
     const int col0 = J.p0 + wv * MR;
     const int cend = J.p0 + J.plen;
+    // Buffer loads throughout: a lane with nothing to read (column past the
+    // panel, term past the rank, no next chunk) gets an offset moved past
+    // the range by adding 2^31 and reads zero, so no load sits behind a
+    // per-lane branch and the waits count loads exactly.
+    auto rsrc = [](uint64_t base) {
+        return __builtin_amdgcn_make_buffer_rsrc((void*)base, (short)0, 0x7fffffff, 0x00020000);
+    };
     // x operand (K = factor column, N = right-hand side): lane holds columns
     // col0 + 32 kt + 8 q + e (e < 8) of right-hand side 16 ct + a
+    const __amdgpu_buffer_rsrc_t xrs = rsrc((uint64_t)(xr + (int64_t)J.x0 * NRP));
     bf16x8_t xs[2][CT];
 #pragma unroll
     for (int kt = 0; kt < 2; ++kt)
@@ -595,26 +603,25 @@ __global__ __launch_bounds__(64 * W) void k_mproj(const MJob* __restrict__ jobs,
 #pragma unroll
             for (int e = 0; e < 8; ++e) {
                 const int j = col0 + 32 * kt + 8 * q + e;
-                u[e] = j < cend ? xr[(int64_t)(J.x0 + j) * NRP + 16 * ct + a] : (uint16_t)0;
+                const uint32_t off = (uint32_t)(2 * (j * NRP + 16 * ct + a)) + ((uint32_t)(j >= cend) << 31);
+                u[e] = (uint16_t)__builtin_amdgcn_raw_buffer_load_b16(xrs, (int)off, 0, 0);
             }
             xs[kt][ct] = __builtin_bit_cast(bf16x8_t, u);
         }
     // factor words of a 16-term chunk: lane holds term k0 + a, columns
-    // col0 + 32 kt + 8 q .. + 7; the next chunk's are loaded in advance
+    // col0 + 32 kt + 8 q .. + 7
+    const __amdgpu_buffer_rsrc_t frs = rsrc(J.F);
     auto load_chunk = [&](int k0, u32x4 (&w)[2]) {
         const int k = k0 + a;
 #pragma unroll
         for (int kt = 0; kt < 2; ++kt) {
             const int c8 = col0 + 32 * kt + 8 * q;
-            w[kt] = u32x4{0u, 0u, 0u, 0u};
-            if (k < J.r && c8 < cend) w[kt] = *as_global<u32x4>(J.F + 2 * ((int64_t)k * ld + c8));
+            const bool ok = k < J.r && c8 < cend;
+            const uint32_t off = (uint32_t)(2 * ((int64_t)k * ld + c8)) + ((uint32_t)!ok << 31);
+            w[kt] = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(frs, (int)off, 0, 0));
         }
     };
-    u32x4 wc[2];
-    load_chunk(0, wc);
-    for (int k0 = 0; k0 < J.r; k0 += 16) {
-        u32x4 wn[2];
-        load_chunk(k0 + 16, wn);
+    auto process = [&](int k0, const u32x4 (&wc)[2]) {
         f32x4_t t[CT];
 #pragma unroll
         for (int ct = 0; ct < CT; ++ct) t[ct] = f32x4_t{0.f, 0.f, 0.f, 0.f};
@@ -625,8 +632,6 @@ __global__ __launch_bounds__(64 * W) void k_mproj(const MJob* __restrict__ jobs,
             for (int ct = 0; ct < CT; ++ct)
                 t[ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fv, xs[kt][ct], t[ct], 0, 0, 0);
         }
-        wc[0] = wn[0];
-        wc[1] = wn[1];
         if (W > 1) {
 #pragma unroll
             for (int ct = 0; ct < CT; ++ct) red[wv][ct][lane] = t[ct];
@@ -657,6 +662,24 @@ __global__ __launch_bounds__(64 * W) void k_mproj(const MJob* __restrict__ jobs,
                 }
             }
         }
+    };
+    // two register buffers in turn: the next chunk's loads are in flight
+    // while the current one is multiplied (no copy between the buffers)
+    u32x4 wa[2], wb[2];
+    load_chunk(0, wa);
+    for (int k0 = 0;;) {
+        load_chunk(k0 + 16, wb);
+        __builtin_amdgcn_sched_barrier(0);
+        process(k0, wa);
+        __builtin_amdgcn_sched_barrier(0);
+        k0 += 16;
+        if (k0 >= J.r) break;
+        load_chunk(k0 + 16, wa);
+        __builtin_amdgcn_sched_barrier(0);
+        process(k0, wb);
+        __builtin_amdgcn_sched_barrier(0);
+        k0 += 16;
+        if (k0 >= J.r) break;
     }
 }
 

@@ -140,8 +140,12 @@ hodlr_status hodlr_build(const double* points, int64_t N, int d, const hodlr_ker
  *            512 rows and columns are applied on BF16 matrix cores (x and the
  *            projections V x rounded to BF16, FP32 accumulation), 16 or 32
  *            right-hand sides per pass.
- *   Asynchronous on stream; owns a workspace inside the handle, so calls on
- *   one handle must not overlap in time (serialize them on one stream).
+ *   Asynchronous on stream.  The near field runs on a second stream owned by
+ *   the handle (default priority), beside the low-rank stages: it starts
+ *   after the work queued on `stream` before the call, and `stream` waits
+ *   for it before the final stage.  Owns a workspace inside the handle, so
+ *   calls on one handle must not overlap in time (serialize them on one
+ *   stream).
  * Errors: EINVAL (nrhs < 1, ld < N, bad prec, BF16 storage with FP64
  * compute, skeleton form with FP32 compute, factors missing), EDEVICE. */
 hodlr_status hodlr_matvec(hodlr_t h, const void* X, int64_t ldx, int nrhs, int x_prec,
@@ -151,8 +155,11 @@ hodlr_status hodlr_matvec(hodlr_t h, const void* X, int64_t ldx, int nrhs, int x
  * void*) on the stream, for timing.  nevents == 5: before the product and
  * after each of its four stages (permutation into tree order; projections
  * and one-pass applications of the stored blocks; expansions of the blocks
- * split over several workgroups; gather of the contributions plus the near
- * field evaluated on the fly plus permutation back).  nevents == 11: the
+ * split over several workgroups; gather of the contributions and the
+ * near-field sums plus permutation back; the near field itself runs on the
+ * handle's second stream beside the second and third stages, and with BF16
+ * matrix cores beside the second, the projections).  Stage times are those
+ * of the caller's stream.  nevents == 11: the
  * same five, then events[5 + c] recorded after the launch of block-size
  * class c = 0..5 inside the second stage (classes of hodlr_info
  * class_blocks).  Same results and errors as hodlr_matvec (EINVAL if events
@@ -165,9 +172,10 @@ hodlr_status hodlr_matvec_events(hodlr_t h, const void* X, int64_t ldx, int nrhs
  * (the largest request so far is kept).  hodlr_matvec reserves on demand;
  * reserving first makes a later hodlr_matvec / hodlr_matvec_events with at
  * most nrhs columns free of allocations, host synchronisation and memsets:
- * only kernel launches (and events) on the caller's stream, so the call can
- * be captured into a HIP graph and replayed (inputs and outputs at the
- * captured addresses).  A call under stream capture that would have to grow
+ * only kernel launches and events on the caller's stream and on the
+ * handle's second stream (created here, forked from and joined back into the
+ * caller's stream within each call), so the call can be captured into a HIP
+ * graph and replayed (inputs and outputs at the captured addresses).  A call under stream capture that would have to grow
  * the workspace returns HODLR_EINVAL instead.  EINVAL for a null handle,
  * nrhs < 1 or a bad precision. */
 hodlr_status hodlr_reserve_workspace(hodlr_t h, int nrhs, int compute_prec);

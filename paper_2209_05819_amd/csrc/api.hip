@@ -38,6 +38,11 @@ double ms_since(std::chrono::steady_clock::time_point t0) {
 void free_all(hodlr_t h) {
     for (auto& kv : h->allocs) (void)hipFree(kv.first);
     h->allocs.clear();
+    if (h->ev_fork) (void)hipEventDestroy(h->ev_fork);
+    if (h->ev_join) (void)hipEventDestroy(h->ev_join);
+    if (h->aux) (void)hipStreamDestroy(h->aux);
+    h->ev_fork = h->ev_join = nullptr;
+    h->aux = nullptr;
 }
 }  // namespace
 

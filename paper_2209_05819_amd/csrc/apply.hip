@@ -192,6 +192,17 @@ __global__ void k_permute_in(const XT* __restrict__ X, int64_t ldx, int nrhs, in
     for (int c = 0; c < nrhs; ++c) x[c * N + p] = (C)X[c * ldx + u];
 }
 
+// Y[:, c0 + c] = the level sums yl[c] (tree order) in user order, c < nc.
+template <typename XT>
+__global__ void k_permute_out(const float* __restrict__ yl, int64_t N, int nc, int c0,
+                              const int32_t* __restrict__ perm, XT* __restrict__ Y,
+                              int64_t ldy) {
+    const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (p >= N) return;
+    const int64_t u = perm[p];
+    for (int c = 0; c < nc; ++c) Y[(int64_t)(c0 + c) * ldy + u] = (XT)yl[(int64_t)c * N + p];
+}
+
 // One wave applies one stored block with NR right-hand sides: the
 // projections of up to RMAX terms (multi-row reductions in batches of K),
 // then their expansion re-reading the factors (cache hits); repeated over
@@ -995,20 +1006,26 @@ __global__ __launch_bounds__(TE) void k_expand_split(const BlockDesc* __restrict
 // sources and the contribution segments; partial sums meet in a fixed order.
 // The leaf's source ranges and per-level segments are precomputed, so its
 // loads do not depend on each other.
+// MODE kNearFused: both, written to Y.  MODE kNearOnly: the near field alone,
+// written to yn (tree order, column c at yn[c N + i]); it has no input from
+// the low-rank stages and runs beside them.  MODE kGatherOnly: yn plus the
+// contributions, written to Y.
 constexpr int TG = 256;
 constexpr int kNearTile = 256;         // sources per LDS tile
 constexpr int kNearTileRanges = 1024;  // near boxes a tiled leaf may have
+constexpr int kNearFused = 0, kNearOnly = 1, kGatherOnly = 2;
 
-template <typename XT, typename C, int NR, int KIND = -1>
+template <typename XT, typename C, int NR, int KIND = -1, int MODE = kNearFused>
 __global__ __launch_bounds__(TG) void k_gather_near(
     const NearItem* __restrict__ items, const SegRef* __restrict__ lseg,
     const int2* __restrict__ nrng, int kappa, const double* __restrict__ pts, int64_t N, int d,
     KParams kp, const C* __restrict__ x, const C* __restrict__ contrib, int64_t CT,
     const int32_t* __restrict__ perm, int nrhs, int c0, XT* __restrict__ Y, int64_t ldy,
-    const C* __restrict__ ylev) {
+    const C* __restrict__ ylev, C* __restrict__ yn) {
     __shared__ C red[TG / 64][NR][64];
     const NearItem it = items[blockIdx.x];
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    // the wave index as a scalar: loop bounds built from it stay wave-uniform
+    const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     int mp = 1;
     while (mp < it.cnt) mp <<= 1;
     const int S = 64 / mp;
@@ -1022,9 +1039,14 @@ __global__ __launch_bounds__(TG) void k_gather_near(
 #pragma unroll
     for (int c = 0; c < NR; ++c) acc[c] = 0;
     double xi[kMaxD];
-    if (active)
+    if (MODE != kGatherOnly && active)
         for (int a = 0; a < d; ++a) xi[a] = pts[a * N + i];
-    if (d <= 4 && it.nn <= kNearTileRanges) {
+    if constexpr (MODE == kGatherOnly) {
+        if (active && sg == 0)
+#pragma unroll
+            for (int c = 0; c < NR; ++c)
+                if (c < nc) acc[c] = yn[(int64_t)c * N + i];
+    } else if (d <= 4 && it.nn <= kNearTileRanges) {
         // sources staged through LDS in tiles: coalesced cooperative loads,
         // then every lane reads them as broadcasts
         __shared__ int s_pre[kNearTileRanges + 1], s_rs[kNearTileRanges];
@@ -1072,11 +1094,16 @@ __global__ __launch_bounds__(TG) void k_gather_near(
                 const int64_t rs = s_rs[e];
                 if (i >= rs && i < rs + (s_pre[e + 1] - s_pre[e])) qself = s_pre[e] + (int)(i - rs);
             }
+        // A lane takes sources sg, sg + SG, ... of the tile.  The wave walks
+        // the tile with one trip count for all of its lanes (they differ
+        // only by their slice within the wave), so the loop has no per-lane
+        // exit and the diagonal is a select; the last, partly filled step
+        // reads a valid record and drops its term.
+        const int sl = lane / mp;
         auto tile = [&](int t0, int tn, auto packed) {
             constexpr bool P = decltype(packed)::value;
             const int qs = qself - t0;
-#pragma unroll 4
-            for (int q = sg; q < tn; q += SG) {
+            auto term = [&](int q, bool ok) {
                 const C4 pq = s_pt[q];
                 C r2 = 0;
 #pragma unroll
@@ -1084,13 +1111,25 @@ __global__ __launch_bounds__(TG) void k_gather_near(
                     const C dx = xc[a] - pq.v[a];
                     r2 += dx * dx;
                 }
-                const C kij = q == qs ? (C)kp.diag : kfun_k<KIND>(kp, r2);
+                C kij = kfun_k<KIND>(kp, r2);
+                kij = q == qs ? (C)kp.diag : kij;
+                kij = ok ? kij : (C)0;
                 if constexpr (P) {
                     acc[0] += kij * pq.v[3];
                 } else {
 #pragma unroll
                     for (int c = 0; c < NR; ++c) acc[c] += kij * s_x[c][q];
                 }
+            };
+            int q0 = wv * S;
+            for (; q0 + 3 * SG + S <= tn; q0 += 4 * SG) {   // four records read at once
+#pragma unroll
+                for (int u = 0; u < 4; ++u) term(q0 + u * SG + sl, true);
+            }
+            for (; q0 + S <= tn; q0 += SG) term(q0 + sl, true);
+            if (q0 < tn) {
+                const bool ok = q0 + sl < tn;
+                term(ok ? q0 + sl : tn - 1, ok);
             }
         };
         for (int t0 = 0; t0 < total; t0 += kNearTile) {
@@ -1118,12 +1157,12 @@ __global__ __launch_bounds__(TG) void k_gather_near(
                 s_pt[q] = pq;
             }
             __syncthreads();
-            if (active) {
-                if (packx)
-                    tile(t0, tn, std::true_type{});
-                else
-                    tile(t0, tn, std::false_type{});
-            }
+            // every lane runs the tile (idle rows have zero coordinates and
+            // their sums are dropped), so the wave stays converged
+            if (packx)
+                tile(t0, tn, std::true_type{});
+            else
+                tile(t0, tn, std::false_type{});
             __syncthreads();
         }
     } else if (active) {
@@ -1147,22 +1186,24 @@ __global__ __launch_bounds__(TG) void k_gather_near(
             }
         }
     }
-    if (active && ylev) {
-        // the low-rank part is already summed per row (columns c0 .. c0+nc)
-        if (sg == 0)
-#pragma unroll
-            for (int c = 0; c < NR; ++c)
-                if (c < nc) acc[c] += ylev[(int64_t)c * N + i];
-    } else if (active) {
-        const int64_t off = i - it.leaf0;
-        for (int l = 0; l < kappa; ++l) {
-            const SegRef sr = lseg[(int64_t)it.leaf * kappa + l];
-            const C* __restrict__ seg = contrib + sr.base + off;
-#pragma unroll 4
-            for (int64_t e = sg; e < sr.ne; e += SG)
+    if constexpr (MODE != kNearOnly) {
+        if (active && ylev) {
+            // the low-rank part is already summed per row (columns c0 .. c0+nc)
+            if (sg == 0)
 #pragma unroll
                 for (int c = 0; c < NR; ++c)
-                    if (c < nc) acc[c] += seg[(int64_t)c * CT + e * sr.len];
+                    if (c < nc) acc[c] += ylev[(int64_t)c * N + i];
+        } else if (active) {
+            const int64_t off = i - it.leaf0;
+            for (int l = 0; l < kappa; ++l) {
+                const SegRef sr = lseg[(int64_t)it.leaf * kappa + l];
+                const C* __restrict__ seg = contrib + sr.base + off;
+#pragma unroll 4
+                for (int64_t e = sg; e < sr.ne; e += SG)
+#pragma unroll
+                    for (int c = 0; c < NR; ++c)
+                        if (c < nc) acc[c] += seg[(int64_t)c * CT + e * sr.len];
+            }
         }
     }
     for (int o = mp; o < 64; o <<= 1)
@@ -1172,11 +1213,13 @@ __global__ __launch_bounds__(TG) void k_gather_near(
     for (int c = 0; c < NR; ++c) red[wv][c][lane] = acc[c];
     __syncthreads();
     if (wv == 0 && active && lane < mp) {
-        const int64_t u = perm[i];
         for (int c = 0; c < nc; ++c) {
             C v = red[0][c][lane];
             for (int w = 1; w < TG / 64; ++w) v += red[w][c][lane];
-            Y[(int64_t)(c0 + c) * ldy + u] = (XT)v;
+            if constexpr (MODE == kNearOnly)
+                yn[(int64_t)c * N + i] = v;
+            else
+                Y[(int64_t)(c0 + c) * ldy + perm[i]] = (XT)v;
         }
     }
 }
@@ -1329,9 +1372,10 @@ __global__ __launch_bounds__(256) void k_skel(const BlockDesc* __restrict__ bloc
 // chunk of a leaf; the sources are staged through LDS 128 at a time
 // (coordinates, and x rows in the operand layout) and each wave multiplies
 // all 64 targets by 32 of them: 4 x CT 16x16x32 products per wave and tile.
-// The waves' partial sums meet in LDS in wave order; the level sums of the
-// low-rank part are added and the rows written to Y in user order.  The
-// kernel function (KIND) and the number of coordinates (DC = 3 for d <= 3,
+// The waves' partial sums meet in LDS in wave order and are written as the
+// rows' starting values of the level sums yl (tree order), which pass 2 then
+// adds to: the kernel needs nothing from the low-rank passes and runs beside
+// pass 1.  The kernel function (KIND) and the number of coordinates (DC = 3 for d <= 3,
 // 4 for d = 4) are fixed at compile time; padded sources sit at a far
 // sentinel point with x = 0 (finite kernel values times zero) and padded
 // target rows are computed but never written, so the pair loop carries no
@@ -1339,12 +1383,11 @@ __global__ __launch_bounds__(256) void k_skel(const BlockDesc* __restrict__ bloc
 constexpr int kNmTile = 128;
 constexpr float kNmFar = 1e18f;   // sentinel coordinate of padded sources
 
-template <typename XT, int CT, int KIND, int DC>
+template <int CT, int KIND, int DC>
 __global__ __launch_bounds__(256) void k_near_mfma(
     const NearItem* __restrict__ items, const int2* __restrict__ nrng,
     const double* __restrict__ pts, int64_t N, int d, KParams kp,
-    const uint16_t* __restrict__ xr, const float* __restrict__ ylev,
-    const int32_t* __restrict__ perm, int nc, int c0, XT* __restrict__ Y, int64_t ldy) {
+    const uint16_t* __restrict__ xr, int nc, float* __restrict__ yl) {
     constexpr int NRP = 16 * CT;
     __shared__ int s_pre[kNearTileRanges + 1], s_rs[kNearTileRanges];
     __shared__ __attribute__((aligned(16))) int s_j[kNmTile];
@@ -1481,7 +1524,7 @@ __global__ __launch_bounds__(256) void k_near_mfma(
                 const int o = 16 * tm + 4 * q + e;
                 if (o < it.cnt && c < nc) {
                     const int64_t i = it.lo + o;
-                    Y[(int64_t)(c0 + c) * ldy + perm[i]] = (XT)(v[e] + ylev[(int64_t)c * N + i]);
+                    yl[(int64_t)c * N + i] = v[e];
                 }
             }
         }
@@ -1803,7 +1846,18 @@ void run_matvec(hodlr_t h, const XT* X, int64_t ldx, int nrhs, XT* Y, int64_t ld
     C* tb = contrib + CT * NR;
     C* sb = tb + TT * NR;
     C* pp = sb + TT * NR;   // partials of the segmented projections
+    C* yn = pp + 2 * kProjSegMax * h->n_proj_sums * NR;   // near-field sums
     const int sym = h->opts.symmetric ? 1 : 0;
+    // the second stream starts after everything issued so far on s, and s
+    // waits for all of its work at the join
+    auto fork = [&] {
+        HIP_CHECK(hipEventRecord(h->ev_fork, s));
+        HIP_CHECK(hipStreamWaitEvent(h->aux, h->ev_fork, 0));
+    };
+    auto join = [&] {
+        HIP_CHECK(hipEventRecord(h->ev_join, h->aux));
+        HIP_CHECK(hipStreamWaitEvent(s, h->ev_join, 0));
+    };
     if (ev) HIP_CHECK(hipEventRecord(ev[0], s));
     k_permute_in<XT, C><<<nblk(N, 256), 256, 0, s>>>(X, ldx, nrhs, N, h->perm, x);
     HIP_CHECK(hipGetLastError());
@@ -1825,8 +1879,38 @@ void run_matvec(hodlr_t h, const XT* X, int64_t ldx, int nrhs, XT* Y, int64_t ld
             p += align256(2 * (size_t)std::max<int64_t>(h->mt_total, 1) * NR);
             float* part = reinterpret_cast<float*>(p);
             k_rows_bf16<XT><<<nblk(N * NR, 256), 256, 0, s>>>(X, ldx, c0, nc, N, h->perm, NR, xr);
-            k_fill_zero<float><<<nblk(N * NR, 256), 256, 0, s>>>(yl, N * NR);
             HIP_CHECK(hipGetLastError());
+            // the near field on matrix cores writes the starting values of the
+            // level sums on the second stream while pass 1 runs
+            const bool nm = h->near_max_ranges <= kNearTileRanges && h->d <= 4;
+            if (nm) {
+                fork();
+                switch (h->kp.kind * 2 + (h->d == 4 ? 1 : 0)) {
+#define HODLR_NEAR_MFMA(K, DC)                                                                  \
+    case K * 2 + (DC == 4 ? 1 : 0):                                                             \
+        k_near_mfma<CTn, K, DC><<<(unsigned)h->n_near_items, 256, 0, h->aux>>>(                 \
+            h->near_items, h->near_rng, h->pts, N, h->d, h->kp, xr, nc, yl);                     \
+        break;
+#define HODLR_NEAR_MFMA2(K) HODLR_NEAR_MFMA(K, 3) HODLR_NEAR_MFMA(K, 4)
+                    HODLR_NEAR_MFMA2(HODLR_K_LOG)
+                    HODLR_NEAR_MFMA2(HODLR_K_INV_R)
+                    HODLR_NEAR_MFMA2(HODLR_K_INV_R2)
+                    HODLR_NEAR_MFMA2(HODLR_K_GAUSS)
+                    HODLR_NEAR_MFMA2(HODLR_K_EXP)
+                    HODLR_NEAR_MFMA2(HODLR_K_R)
+                    HODLR_NEAR_MFMA2(HODLR_K_SIN)
+                    HODLR_NEAR_MFMA2(HODLR_K_INV_SQRT1P)
+#undef HODLR_NEAR_MFMA2
+#undef HODLR_NEAR_MFMA
+                    default:
+                        join();
+                        fail(HODLR_EINVAL, "unknown kernel function");
+                }
+                HIP_CHECK(hipGetLastError());
+            } else {
+                k_fill_zero<float><<<nblk(N * NR, 256), 256, 0, s>>>(yl, N * NR);
+                HIP_CHECK(hipGetLastError());
+            }
             // pass 1: projections, by workgroup width
             for (int w = 0; w < 4; ++w) {
                 const int64_t n0 = h->mjob_off[w], cnt = h->mjob_off[w + 1] - n0;
@@ -1849,6 +1933,7 @@ void run_matvec(hodlr_t h, const XT* X, int64_t ldx, int nrhs, XT* Y, int64_t ld
             if (ev && nev > 5 && c0 == 0)
                 for (int c = 4; c < kNumClasses; ++c) HIP_CHECK(hipEventRecord(ev[5 + c], s));
             if (ev && c0 == 0) HIP_CHECK(hipEventRecord(ev[2], s));
+            if (nm) join();
             // pass 2: expansions, one level at a time (tiles of a level own
             // disjoint rows of the level sum)
             for (int l = 1; l <= h->kappa; ++l) {
@@ -1863,34 +1948,43 @@ void run_matvec(hodlr_t h, const XT* X, int64_t ldx, int nrhs, XT* Y, int64_t ld
                 HIP_CHECK(hipGetLastError());
             }
             if (ev && c0 == 0) HIP_CHECK(hipEventRecord(ev[3], s));
-            if (h->near_max_ranges <= kNearTileRanges && h->d <= 4) {
-                switch (h->kp.kind * 2 + (h->d == 4 ? 1 : 0)) {
-#define HODLR_NEAR_MFMA(K, DC)                                                                  \
-    case K * 2 + (DC == 4 ? 1 : 0):                                                             \
-        k_near_mfma<XT, CTn, K, DC><<<(unsigned)h->n_near_items, 256, 0, s>>>(                  \
-            h->near_items, h->near_rng, h->pts, N, h->d, h->kp, xr, yl, h->perm, nc, c0, Y, ldy); \
-        break;
-#define HODLR_NEAR_MFMA2(K) HODLR_NEAR_MFMA(K, 3) HODLR_NEAR_MFMA(K, 4)
-                    HODLR_NEAR_MFMA2(HODLR_K_LOG)
-                    HODLR_NEAR_MFMA2(HODLR_K_INV_R)
-                    HODLR_NEAR_MFMA2(HODLR_K_INV_R2)
-                    HODLR_NEAR_MFMA2(HODLR_K_GAUSS)
-                    HODLR_NEAR_MFMA2(HODLR_K_EXP)
-                    HODLR_NEAR_MFMA2(HODLR_K_R)
-                    HODLR_NEAR_MFMA2(HODLR_K_SIN)
-                    HODLR_NEAR_MFMA2(HODLR_K_INV_SQRT1P)
-#undef HODLR_NEAR_MFMA2
-#undef HODLR_NEAR_MFMA
-                    default:
-                        fail(HODLR_EINVAL, "unknown kernel function");
-                }
-            } else
+            if (nm)
+                k_permute_out<XT><<<nblk(N, 256), 256, 0, s>>>(yl, N, nc, c0, h->perm, Y, ldy);
+            else
                 k_gather_near<XT, C, NR><<<(unsigned)h->n_near_items, TG, 0, s>>>(
                     h->near_items, h->leaf_seg, h->near_rng, h->kappa, h->pts, N, h->d, h->kp, x,
-                    contrib, CT, h->perm, nrhs, c0, Y, ldy, yl);
+                    contrib, CT, h->perm, nrhs, c0, Y, ldy, yl, nullptr);
             HIP_CHECK(hipGetLastError());
             continue;
         } else {
+        // the near field on the second stream, beside the low-rank stages
+        fork();
+        if constexpr (NR == 1) {
+            // one right-hand side: the kernel function fixed at compile time
+            switch (h->kp.kind) {
+#define HODLR_NEAR(K)                                                                           \
+    case K:                                                                                     \
+        k_gather_near<XT, C, NR, K, kNearOnly><<<(unsigned)h->n_near_items, TG, 0, h->aux>>>(   \
+            h->near_items, h->leaf_seg, h->near_rng, h->kappa, h->pts, N, h->d, h->kp, x,       \
+            contrib, CT, h->perm, nrhs, c0, Y, ldy, nullptr, yn);                               \
+        break;
+                HODLR_NEAR(HODLR_K_LOG)
+                HODLR_NEAR(HODLR_K_INV_R)
+                HODLR_NEAR(HODLR_K_INV_R2)
+                HODLR_NEAR(HODLR_K_GAUSS)
+                HODLR_NEAR(HODLR_K_EXP)
+                HODLR_NEAR(HODLR_K_R)
+                HODLR_NEAR(HODLR_K_SIN)
+                default:
+                HODLR_NEAR(HODLR_K_INV_SQRT1P)
+#undef HODLR_NEAR
+            }
+        } else {
+            k_gather_near<XT, C, NR, -1, kNearOnly><<<(unsigned)h->n_near_items, TG, 0, h->aux>>>(
+                h->near_items, h->leaf_seg, h->near_rng, h->kappa, h->pts, N, h->d, h->kp, x,
+                contrib, CT, h->perm, nrhs, c0, Y, ldy, nullptr, yn);
+        }
+        HIP_CHECK(hipGetLastError());
         if constexpr (NR == 1 && !std::is_same<S, bf16>::value) {
             if (h->opts.skeleton) {
                 // skeleton form: every stored block, the kernel evaluated on the fly
@@ -1978,31 +2072,11 @@ void run_matvec(hodlr_t h, const XT* X, int64_t ldx, int nrhs, XT* Y, int64_t ld
         if (ev && c0 == 0) HIP_CHECK(hipEventRecord(ev[3], s));
         }
     gather:
-        if constexpr (NR == 1) {
-            // one right-hand side: the kernel function fixed at compile time
-            switch (h->kp.kind) {
-#define HODLR_GATHER(K)                                                                         \
-    case K:                                                                                     \
-        k_gather_near<XT, C, NR, K><<<(unsigned)h->n_near_items, TG, 0, s>>>(                   \
-            h->near_items, h->leaf_seg, h->near_rng, h->kappa, h->pts, N, h->d, h->kp, x,       \
-            contrib, CT, h->perm, nrhs, c0, Y, ldy, nullptr);                                   \
-        break;
-                HODLR_GATHER(HODLR_K_LOG)
-                HODLR_GATHER(HODLR_K_INV_R)
-                HODLR_GATHER(HODLR_K_INV_R2)
-                HODLR_GATHER(HODLR_K_GAUSS)
-                HODLR_GATHER(HODLR_K_EXP)
-                HODLR_GATHER(HODLR_K_R)
-                HODLR_GATHER(HODLR_K_SIN)
-                default:
-                HODLR_GATHER(HODLR_K_INV_SQRT1P)
-#undef HODLR_GATHER
-            }
-        } else {
-            k_gather_near<XT, C, NR><<<(unsigned)h->n_near_items, TG, 0, s>>>(
-                h->near_items, h->leaf_seg, h->near_rng, h->kappa, h->pts, N, h->d, h->kp, x,
-                contrib, CT, h->perm, nrhs, c0, Y, ldy, nullptr);
-        }
+        // near-field sums plus the contributions of every level, to Y
+        join();
+        k_gather_near<XT, C, NR, -1, kGatherOnly><<<(unsigned)h->n_near_items, TG, 0, s>>>(
+            h->near_items, h->leaf_seg, h->near_rng, h->kappa, h->pts, N, h->d, h->kp, x, contrib,
+            CT, h->perm, nrhs, c0, Y, ldy, nullptr, yn);
         HIP_CHECK(hipGetLastError());
     }
     if (ev) HIP_CHECK(hipEventRecord(ev[4], s));
@@ -2044,15 +2118,28 @@ void reserve_workspace(hodlr_t h, int nrhs, int compute_prec, hipStream_t s) {
         need = align256(cs * (size_t)N * nrhs) + align256(2 * (size_t)N * nr) + align256(4 * (size_t)N * nr) +
                align256(2 * (size_t)std::max<int64_t>(h->mt_total, 1) * nr) +
                4 * (size_t)std::max<int64_t>(h->mpart_total, 1) * nr + 4096;
-    else
+    else   // x, contributions, projections, partials, near-field sums
         need = cs * ((size_t)N * nrhs + (size_t)CT * nr + 2 * (size_t)TT * nr +
-                     2 * (size_t)kProjSegMax * (size_t)h->n_proj_sums * nr) + 4096;
-    if (h->ws_bytes < need) {
-        // growing allocates and synchronises: not allowed inside a graph capture
+                     2 * (size_t)kProjSegMax * (size_t)h->n_proj_sums * nr + (size_t)N * nr) +
+               4096;
+    // growing allocates and synchronises, and creating the second stream is
+    // no stream operation: neither is allowed inside a graph capture
+    auto capturing = [&] {
         hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
-        if (s && hipStreamIsCapturing(s, &cap) == hipSuccess && cap != hipStreamCaptureStatusNone)
+        return s && hipStreamIsCapturing(s, &cap) == hipSuccess &&
+               cap != hipStreamCaptureStatusNone;
+    };
+    if (h->ws_bytes < need || !h->aux) {
+        if (capturing())
             fail(HODLR_EINVAL, "workspace not reserved before stream capture "
                                "(call hodlr_reserve_workspace first)");
+    }
+    if (!h->aux) {
+        HIP_CHECK(hipStreamCreateWithFlags(&h->aux, hipStreamNonBlocking));
+        HIP_CHECK(hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming));
+        HIP_CHECK(hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming));
+    }
+    if (h->ws_bytes < need) {
         if (h->ws) {
             HIP_CHECK(hipStreamSynchronize(s));
             dfree(h, h->ws);

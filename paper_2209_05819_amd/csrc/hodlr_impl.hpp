@@ -69,12 +69,15 @@ __device__ __forceinline__ double kfun(const KParams& k, double r2) {
     return k.scale * f;
 }
 
+// FP32: 1/r and 1/r^2 by the hardware reciprocal (square root), 1 ulp, without
+// a rescaled path for r^2 below the smallest normal FP32 number (where 1/r
+// exceeds 1.8e19 and the product has no accuracy left in FP32 anyway).
 __device__ __forceinline__ float kfun(const KParams& k, float r2) {
     float f;
     switch (k.kind) {
     case HODLR_K_LOG: f = 0.5f * __logf(r2); break;
-    case HODLR_K_INV_R: f = rsqrtf(r2); break;
-    case HODLR_K_INV_R2: f = 1.0f / r2; break;
+    case HODLR_K_INV_R: f = __builtin_amdgcn_rsqf(r2); break;
+    case HODLR_K_INV_R2: f = __builtin_amdgcn_rcpf(r2); break;
     case HODLR_K_GAUSS: f = __expf(-r2 * (float)k.inv_h2); break;
     case HODLR_K_EXP: f = __expf(-sqrtf(r2) * (float)k.inv_h); break;
     case HODLR_K_R: f = sqrtf(r2); break;
@@ -330,6 +333,11 @@ struct hodlr_handle_s {
     // matvec workspace
     void* ws = nullptr;
     size_t ws_bytes = 0;
+    // second stream of the product (default priority): the near field, which
+    // is bound by arithmetic, runs on it while the low-rank stages stream the
+    // factors from HBM on the caller's stream; fork and join by events
+    hipStream_t aux = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     size_t device_bytes = 0;
     double build_ms[4]{};
     std::unordered_map<void*, size_t> allocs;

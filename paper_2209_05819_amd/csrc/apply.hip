@@ -1017,210 +1017,215 @@ constexpr int kNearFused = 0, kNearOnly = 1, kGatherOnly = 2;
 
 template <typename XT, typename C, int NR, int KIND = -1, int MODE = kNearFused>
 __global__ __launch_bounds__(TG) void k_gather_near(
-    const NearItem* __restrict__ items, const SegRef* __restrict__ lseg,
+    const NearItem* __restrict__ items, int64_t nitems, const SegRef* __restrict__ lseg,
     const int2* __restrict__ nrng, int kappa, const double* __restrict__ pts, int64_t N, int d,
     KParams kp, const C* __restrict__ x, const C* __restrict__ contrib, int64_t CT,
     const int32_t* __restrict__ perm, int nrhs, int c0, XT* __restrict__ Y, int64_t ldy,
     const C* __restrict__ ylev, C* __restrict__ yn) {
     __shared__ C red[TG / 64][NR][64];
-    const NearItem it = items[blockIdx.x];
-    // the wave index as a scalar: loop bounds built from it stay wave-uniform
-    const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    int mp = 1;
-    while (mp < it.cnt) mp <<= 1;
-    const int S = 64 / mp;
-    const int t = lane % mp;
-    const int sg = wv * S + lane / mp;     // slice of this lane
-    const int SG = (TG / 64) * S;          // slices in the workgroup
-    const bool active = t < it.cnt;
-    const int64_t i = it.lo + t;
-    const int nc = min(NR, nrhs - c0);
-    C acc[NR];
-#pragma unroll
-    for (int c = 0; c < NR; ++c) acc[c] = 0;
-    double xi[kMaxD];
-    if (MODE != kGatherOnly && active)
-        for (int a = 0; a < d; ++a) xi[a] = pts[a * N + i];
-    if constexpr (MODE == kGatherOnly) {
-        if (active && sg == 0)
-#pragma unroll
-            for (int c = 0; c < NR; ++c)
-                if (c < nc) acc[c] = yn[(int64_t)c * N + i];
-    } else if (d <= 4 && it.nn <= kNearTileRanges) {
-        // sources staged through LDS in tiles: coalesced cooperative loads,
-        // then every lane reads them as broadcasts
-        __shared__ int s_pre[kNearTileRanges + 1], s_rs[kNearTileRanges];
-        struct alignas(4 * sizeof(C)) C4 {
-            C v[4];
-        };
-        // one record per source: its coordinates, and for d <= 3 with one
-        // right-hand side its x value in the fourth slot (one LDS read)
-        __shared__ C4 s_pt[kNearTile];
-        __shared__ C s_x[NR][kNearTile];
-        const bool packx = NR == 1 && d <= 3;
-        // coordinates in the compute type: FP64 as they are; FP32 relative to
-        // the leaf's first point, so that differences of nearby points keep
-        // their relative accuracy (zero beyond d)
-        double ref[4];
-        C xc[4];
-#pragma unroll
-        for (int a = 0; a < 4; ++a) {
-            ref[a] = (sizeof(C) == 4 && a < d) ? pts[a * N + it.leaf0] : 0.0;
-            xc[a] = (active && a < d) ? (C)(xi[a] - ref[a]) : (C)0;
-        }
-        for (int e = threadIdx.x; e < it.nn; e += TG) {
-            const int2 rg = nrng[it.nb0 + e];
-            s_rs[e] = rg.x;
-            s_pre[e] = rg.y - rg.x;
-        }
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            int a = 0;
-            for (int e = 0; e < it.nn; ++e) {
-                const int len = s_pre[e];
-                s_pre[e] = a;
-                a += len;
-            }
-            s_pre[it.nn] = a;
-        }
-        __syncthreads();
-        const int total = s_pre[it.nn];
-        // the row's own point as a position in the concatenated sources (its
-        // leaf is one of the near ranges): the diagonal entry is found by
-        // position, without a per-source index
-        int qself = -1;
-        if (active)
-            for (int e = 0; e < it.nn; ++e) {
-                const int64_t rs = s_rs[e];
-                if (i >= rs && i < rs + (s_pre[e + 1] - s_pre[e])) qself = s_pre[e] + (int)(i - rs);
-            }
-        // A lane takes sources sg, sg + SG, ... of the tile.  The wave walks
-        // the tile with one trip count for all of its lanes (they differ
-        // only by their slice within the wave), so the loop has no per-lane
-        // exit and the diagonal is a select; the last, partly filled step
-        // reads a valid record and drops its term.
-        const int sl = lane / mp;
-        auto tile = [&](int t0, int tn, auto packed) {
-            constexpr bool P = decltype(packed)::value;
-            const int qs = qself - t0;
-            auto term = [&](int q, bool ok) {
-                const C4 pq = s_pt[q];
-                C r2 = 0;
-#pragma unroll
-                for (int a = 0; a < (P ? 3 : 4); ++a) {
-                    const C dx = xc[a] - pq.v[a];
-                    r2 += dx * dx;
-                }
-                C kij = kfun_k<KIND>(kp, r2);
-                kij = q == qs ? (C)kp.diag : kij;
-                kij = ok ? kij : (C)0;
-                if constexpr (P) {
-                    acc[0] += kij * pq.v[3];
-                } else {
-#pragma unroll
-                    for (int c = 0; c < NR; ++c) acc[c] += kij * s_x[c][q];
-                }
+    // a grid smaller than the item count loops over the items: a capped grid
+    // keeps the kernel to a share of every CU while it runs beside others
+    for (int64_t bi = blockIdx.x; bi < nitems; bi += gridDim.x) {
+        const NearItem it = items[bi];
+        // the wave index as a scalar: loop bounds built from it stay wave-uniform
+        const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+        int mp = 1;
+        while (mp < it.cnt) mp <<= 1;
+        const int S = 64 / mp;
+        const int t = lane % mp;
+        const int sg = wv * S + lane / mp;     // slice of this lane
+        const int SG = (TG / 64) * S;          // slices in the workgroup
+        const bool active = t < it.cnt;
+        const int64_t i = it.lo + t;
+        const int nc = min(NR, nrhs - c0);
+        C acc[NR];
+    #pragma unroll
+        for (int c = 0; c < NR; ++c) acc[c] = 0;
+        double xi[kMaxD];
+        if (MODE != kGatherOnly && active)
+            for (int a = 0; a < d; ++a) xi[a] = pts[a * N + i];
+        if constexpr (MODE == kGatherOnly) {
+            if (active && sg == 0)
+    #pragma unroll
+                for (int c = 0; c < NR; ++c)
+                    if (c < nc) acc[c] = yn[(int64_t)c * N + i];
+        } else if (d <= 4 && it.nn <= kNearTileRanges) {
+            // sources staged through LDS in tiles: coalesced cooperative loads,
+            // then every lane reads them as broadcasts
+            __shared__ int s_pre[kNearTileRanges + 1], s_rs[kNearTileRanges];
+            struct alignas(4 * sizeof(C)) C4 {
+                C v[4];
             };
-            int q0 = wv * S;
-            for (; q0 + 3 * SG + S <= tn; q0 += 4 * SG) {   // four records read at once
-#pragma unroll
-                for (int u = 0; u < 4; ++u) term(q0 + u * SG + sl, true);
+            // one record per source: its coordinates, and for d <= 3 with one
+            // right-hand side its x value in the fourth slot (one LDS read)
+            __shared__ C4 s_pt[kNearTile];
+            __shared__ C s_x[NR][kNearTile];
+            const bool packx = NR == 1 && d <= 3;
+            // coordinates in the compute type: FP64 as they are; FP32 relative to
+            // the leaf's first point, so that differences of nearby points keep
+            // their relative accuracy (zero beyond d)
+            double ref[4];
+            C xc[4];
+    #pragma unroll
+            for (int a = 0; a < 4; ++a) {
+                ref[a] = (sizeof(C) == 4 && a < d) ? pts[a * N + it.leaf0] : 0.0;
+                xc[a] = (active && a < d) ? (C)(xi[a] - ref[a]) : (C)0;
             }
-            for (; q0 + S <= tn; q0 += SG) term(q0 + sl, true);
-            if (q0 < tn) {
-                const bool ok = q0 + sl < tn;
-                term(ok ? q0 + sl : tn - 1, ok);
-            }
-        };
-        for (int t0 = 0; t0 < total; t0 += kNearTile) {
-            const int tn = min(kNearTile, total - t0);
-            for (int q = threadIdx.x; q < tn; q += TG) {
-                const int sidx = t0 + q;
-                int lo = 0, hi = it.nn - 1;   // last range starting at or before sidx
-                while (lo < hi) {
-                    const int mid = (lo + hi + 1) >> 1;
-                    if (s_pre[mid] <= sidx)
-                        lo = mid;
-                    else
-                        hi = mid - 1;
-                }
-                const int j = s_rs[lo] + (sidx - s_pre[lo]);
-                C4 pq;
-#pragma unroll
-                for (int a = 0; a < 4; ++a) pq.v[a] = a < d ? (C)(pts[a * N + j] - ref[a]) : (C)0;
-                if (packx) {
-                    pq.v[3] = x[(int64_t)c0 * N + j];
-                } else {
-#pragma unroll
-                    for (int c = 0; c < NR; ++c) s_x[c][q] = c < nc ? x[(int64_t)(c0 + c) * N + j] : (C)0;
-                }
-                s_pt[q] = pq;
+            for (int e = threadIdx.x; e < it.nn; e += TG) {
+                const int2 rg = nrng[it.nb0 + e];
+                s_rs[e] = rg.x;
+                s_pre[e] = rg.y - rg.x;
             }
             __syncthreads();
-            // every lane runs the tile (idle rows have zero coordinates and
-            // their sums are dropped), so the wave stays converged
-            if (packx)
-                tile(t0, tn, std::true_type{});
-            else
-                tile(t0, tn, std::false_type{});
+            if (threadIdx.x == 0) {
+                int a = 0;
+                for (int e = 0; e < it.nn; ++e) {
+                    const int len = s_pre[e];
+                    s_pre[e] = a;
+                    a += len;
+                }
+                s_pre[it.nn] = a;
+            }
             __syncthreads();
-        }
-    } else if (active) {
-        for (int e = 0; e < it.nn; ++e) {
-            const int2 rg = nrng[it.nb0 + e];
-            for (int64_t j = rg.x + sg; j < rg.y; j += SG) {
-                C kij;
-                if (j == i) {
-                    kij = (C)kp.diag;
-                } else {
+            const int total = s_pre[it.nn];
+            // the row's own point as a position in the concatenated sources (its
+            // leaf is one of the near ranges): the diagonal entry is found by
+            // position, without a per-source index
+            int qself = -1;
+            if (active)
+                for (int e = 0; e < it.nn; ++e) {
+                    const int64_t rs = s_rs[e];
+                    if (i >= rs && i < rs + (s_pre[e + 1] - s_pre[e])) qself = s_pre[e] + (int)(i - rs);
+                }
+            // A lane takes sources sg, sg + SG, ... of the tile.  The wave walks
+            // the tile with one trip count for all of its lanes (they differ
+            // only by their slice within the wave), so the loop has no per-lane
+            // exit and the diagonal is a select; the last, partly filled step
+            // reads a valid record and drops its term.
+            const int sl = lane / mp;
+            auto tile = [&](int t0, int tn, auto packed) {
+                constexpr bool P = decltype(packed)::value;
+                const int qs = qself - t0;
+                auto term = [&](int q, bool ok) {
+                    const C4 pq = s_pt[q];
                     C r2 = 0;
-                    for (int a = 0; a < d; ++a) {
-                        const C dx = (C)(xi[a] - pts[a * N + j]);
+    #pragma unroll
+                    for (int a = 0; a < (P ? 3 : 4); ++a) {
+                        const C dx = xc[a] - pq.v[a];
                         r2 += dx * dx;
                     }
-                    kij = kfun_k<KIND>(kp, r2);
+                    C kij = kfun_k<KIND>(kp, r2);
+                    kij = q == qs ? (C)kp.diag : kij;
+                    kij = ok ? kij : (C)0;
+                    if constexpr (P) {
+                        acc[0] += kij * pq.v[3];
+                    } else {
+    #pragma unroll
+                        for (int c = 0; c < NR; ++c) acc[c] += kij * s_x[c][q];
+                    }
+                };
+                int q0 = wv * S;
+                for (; q0 + 3 * SG + S <= tn; q0 += 4 * SG) {   // four records read at once
+    #pragma unroll
+                    for (int u = 0; u < 4; ++u) term(q0 + u * SG + sl, true);
                 }
-#pragma unroll
-                for (int c = 0; c < NR; ++c)
-                    if (c < nc) acc[c] += kij * x[(int64_t)(c0 + c) * N + j];
+                for (; q0 + S <= tn; q0 += SG) term(q0 + sl, true);
+                if (q0 < tn) {
+                    const bool ok = q0 + sl < tn;
+                    term(ok ? q0 + sl : tn - 1, ok);
+                }
+            };
+            for (int t0 = 0; t0 < total; t0 += kNearTile) {
+                const int tn = min(kNearTile, total - t0);
+                for (int q = threadIdx.x; q < tn; q += TG) {
+                    const int sidx = t0 + q;
+                    int lo = 0, hi = it.nn - 1;   // last range starting at or before sidx
+                    while (lo < hi) {
+                        const int mid = (lo + hi + 1) >> 1;
+                        if (s_pre[mid] <= sidx)
+                            lo = mid;
+                        else
+                            hi = mid - 1;
+                    }
+                    const int j = s_rs[lo] + (sidx - s_pre[lo]);
+                    C4 pq;
+    #pragma unroll
+                    for (int a = 0; a < 4; ++a) pq.v[a] = a < d ? (C)(pts[a * N + j] - ref[a]) : (C)0;
+                    if (packx) {
+                        pq.v[3] = x[(int64_t)c0 * N + j];
+                    } else {
+    #pragma unroll
+                        for (int c = 0; c < NR; ++c) s_x[c][q] = c < nc ? x[(int64_t)(c0 + c) * N + j] : (C)0;
+                    }
+                    s_pt[q] = pq;
+                }
+                __syncthreads();
+                // every lane runs the tile (idle rows have zero coordinates and
+                // their sums are dropped), so the wave stays converged
+                if (packx)
+                    tile(t0, tn, std::true_type{});
+                else
+                    tile(t0, tn, std::false_type{});
+                __syncthreads();
             }
-        }
-    }
-    if constexpr (MODE != kNearOnly) {
-        if (active && ylev) {
-            // the low-rank part is already summed per row (columns c0 .. c0+nc)
-            if (sg == 0)
-#pragma unroll
-                for (int c = 0; c < NR; ++c)
-                    if (c < nc) acc[c] += ylev[(int64_t)c * N + i];
         } else if (active) {
-            const int64_t off = i - it.leaf0;
-            for (int l = 0; l < kappa; ++l) {
-                const SegRef sr = lseg[(int64_t)it.leaf * kappa + l];
-                const C* __restrict__ seg = contrib + sr.base + off;
-#pragma unroll 4
-                for (int64_t e = sg; e < sr.ne; e += SG)
-#pragma unroll
+            for (int e = 0; e < it.nn; ++e) {
+                const int2 rg = nrng[it.nb0 + e];
+                for (int64_t j = rg.x + sg; j < rg.y; j += SG) {
+                    C kij;
+                    if (j == i) {
+                        kij = (C)kp.diag;
+                    } else {
+                        C r2 = 0;
+                        for (int a = 0; a < d; ++a) {
+                            const C dx = (C)(xi[a] - pts[a * N + j]);
+                            r2 += dx * dx;
+                        }
+                        kij = kfun_k<KIND>(kp, r2);
+                    }
+    #pragma unroll
                     for (int c = 0; c < NR; ++c)
-                        if (c < nc) acc[c] += seg[(int64_t)c * CT + e * sr.len];
+                        if (c < nc) acc[c] += kij * x[(int64_t)(c0 + c) * N + j];
+                }
             }
         }
-    }
-    for (int o = mp; o < 64; o <<= 1)
-#pragma unroll
-        for (int c = 0; c < NR; ++c) acc[c] += __shfl_xor(acc[c], o, 64);
-#pragma unroll
-    for (int c = 0; c < NR; ++c) red[wv][c][lane] = acc[c];
-    __syncthreads();
-    if (wv == 0 && active && lane < mp) {
-        for (int c = 0; c < nc; ++c) {
-            C v = red[0][c][lane];
-            for (int w = 1; w < TG / 64; ++w) v += red[w][c][lane];
-            if constexpr (MODE == kNearOnly)
-                yn[(int64_t)c * N + i] = v;
-            else
-                Y[(int64_t)(c0 + c) * ldy + perm[i]] = (XT)v;
+        if constexpr (MODE != kNearOnly) {
+            if (active && ylev) {
+                // the low-rank part is already summed per row (columns c0 .. c0+nc)
+                if (sg == 0)
+    #pragma unroll
+                    for (int c = 0; c < NR; ++c)
+                        if (c < nc) acc[c] += ylev[(int64_t)c * N + i];
+            } else if (active) {
+                const int64_t off = i - it.leaf0;
+                for (int l = 0; l < kappa; ++l) {
+                    const SegRef sr = lseg[(int64_t)it.leaf * kappa + l];
+                    const C* __restrict__ seg = contrib + sr.base + off;
+    #pragma unroll 4
+                    for (int64_t e = sg; e < sr.ne; e += SG)
+    #pragma unroll
+                        for (int c = 0; c < NR; ++c)
+                            if (c < nc) acc[c] += seg[(int64_t)c * CT + e * sr.len];
+                }
+            }
         }
+        for (int o = mp; o < 64; o <<= 1)
+    #pragma unroll
+            for (int c = 0; c < NR; ++c) acc[c] += __shfl_xor(acc[c], o, 64);
+    #pragma unroll
+        for (int c = 0; c < NR; ++c) red[wv][c][lane] = acc[c];
+        __syncthreads();
+        if (wv == 0 && active && lane < mp) {
+            for (int c = 0; c < nc; ++c) {
+                C v = red[0][c][lane];
+                for (int w = 1; w < TG / 64; ++w) v += red[w][c][lane];
+                if constexpr (MODE == kNearOnly)
+                    yn[(int64_t)c * N + i] = v;
+                else
+                    Y[(int64_t)(c0 + c) * ldy + perm[i]] = (XT)v;
+            }
+        }
+        __syncthreads();   // LDS is reused by the next item
     }
 }
 
@@ -1385,7 +1390,7 @@ constexpr float kNmFar = 1e18f;   // sentinel coordinate of padded sources
 
 template <int CT, int KIND, int DC>
 __global__ __launch_bounds__(256) void k_near_mfma(
-    const NearItem* __restrict__ items, const int2* __restrict__ nrng,
+    const NearItem* __restrict__ items, int64_t nitems, const int2* __restrict__ nrng,
     const double* __restrict__ pts, int64_t N, int d, KParams kp,
     const uint16_t* __restrict__ xr, int nc, float* __restrict__ yl) {
     constexpr int NRP = 16 * CT;
@@ -1394,140 +1399,145 @@ __global__ __launch_bounds__(256) void k_near_mfma(
     __shared__ __attribute__((aligned(16))) float s_pt[4][kNmTile];
     __shared__ __attribute__((aligned(16))) uint16_t s_x[kNmTile / 8][NRP][8];
     __shared__ f32x4_t red[4][4][CT][64];
-    const NearItem it = items[blockIdx.x];
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int a = lane & 15, q = lane >> 4;
-    // target coordinates (d <= 4, zero padded): target tile tm, row
-    // it.lo + 16 tm + a
-    float xt[4][4];
-    int ti[4];
-#pragma unroll
-    for (int tm = 0; tm < 4; ++tm) {
-        const int o = 16 * tm + a;
-        ti[tm] = o < it.cnt ? it.lo + o : -1;
-#pragma unroll
-        for (int c = 0; c < 4; ++c)
-            xt[tm][c] = (ti[tm] >= 0 && c < d) ? (float)pts[c * N + ti[tm]] : 0.f;
-    }
-    for (int e = threadIdx.x; e < it.nn; e += 256) {
-        const int2 rg = nrng[it.nb0 + e];
-        s_rs[e] = rg.x;
-        s_pre[e] = rg.y - rg.x;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        int acc = 0;
-        for (int e = 0; e < it.nn; ++e) {
-            const int len = s_pre[e];
-            s_pre[e] = acc;
-            acc += len;
-        }
-        s_pre[it.nn] = acc;
-    }
-    __syncthreads();
-    const int total = s_pre[it.nn];
-    f32x4_t acc[4][CT];
-#pragma unroll
-    for (int tm = 0; tm < 4; ++tm)
-#pragma unroll
-        for (int ct = 0; ct < CT; ++ct) acc[tm][ct] = f32x4_t{0.f, 0.f, 0.f, 0.f};
-    for (int t0 = 0; t0 < total; t0 += kNmTile) {
-        const int tn = min(kNmTile, total - t0);
-        // stage the tile: source index, coordinates, x rows (zero past tn)
-        for (int sI = threadIdx.x; sI < kNmTile; sI += 256) {
-            int j = -1;
-            if (sI < tn) {
-                const int sidx = t0 + sI;
-                int lo = 0, hi = it.nn - 1;
-                while (lo < hi) {
-                    const int mid = (lo + hi + 1) >> 1;
-                    if (s_pre[mid] <= sidx)
-                        lo = mid;
-                    else
-                        hi = mid - 1;
-                }
-                j = s_rs[lo] + (sidx - s_pre[lo]);
-            }
-            s_j[sI] = j;
-#pragma unroll
-            for (int c = 0; c < 4; ++c)
-                s_pt[c][sI] = j < 0 ? kNmFar : c < d ? (float)pts[c * N + j] : 0.f;
-        }
-        __syncthreads();
-        for (int f = threadIdx.x; f < kNmTile * NRP; f += 256) {
-            const int sI = f / NRP, c = f - sI * NRP;
-            const int j = s_j[sI];
-            s_x[sI >> 3][c][sI & 7] = j >= 0 ? xr[(int64_t)j * NRP + c] : (uint16_t)0;
-        }
-        __syncthreads();
-        // this wave: sources 32 wv + 8 q + e of the tile
-        bf16x8_t xb[CT];
-#pragma unroll
-        for (int ct = 0; ct < CT; ++ct)
-            xb[ct] = __builtin_bit_cast(bf16x8_t,
-                                        *reinterpret_cast<const u16x8_t*>(&s_x[4 * wv + q][16 * ct + a][0]));
-        // this lane's 8 sources: indices and coordinates, read once per tile
-        const int sb0 = 32 * wv + 8 * q;
-        int sj[8];
-        float sp[4][8];
-        {
-            const int4 j0 = *reinterpret_cast<const int4*>(&s_j[sb0]);
-            const int4 j1 = *reinterpret_cast<const int4*>(&s_j[sb0 + 4]);
-            sj[0] = j0.x; sj[1] = j0.y; sj[2] = j0.z; sj[3] = j0.w;
-            sj[4] = j1.x; sj[5] = j1.y; sj[6] = j1.z; sj[7] = j1.w;
-#pragma unroll
-            for (int c = 0; c < 4; ++c) {
-                const float4 p0 = *reinterpret_cast<const float4*>(&s_pt[c][sb0]);
-                const float4 p1 = *reinterpret_cast<const float4*>(&s_pt[c][sb0 + 4]);
-                sp[c][0] = p0.x; sp[c][1] = p0.y; sp[c][2] = p0.z; sp[c][3] = p0.w;
-                sp[c][4] = p1.x; sp[c][5] = p1.y; sp[c][6] = p1.z; sp[c][7] = p1.w;
-            }
-        }
-#pragma unroll
+    // a grid smaller than the item count loops over the items: a capped grid
+    // keeps the kernel to a share of every CU while it runs beside others
+    for (int64_t bi = blockIdx.x; bi < nitems; bi += gridDim.x) {
+        const NearItem it = items[bi];
+        const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+        const int a = lane & 15, q = lane >> 4;
+        // target coordinates (d <= 4, zero padded): target tile tm, row
+        // it.lo + 16 tm + a
+        float xt[4][4];
+        int ti[4];
+    #pragma unroll
         for (int tm = 0; tm < 4; ++tm) {
-            if (16 * tm >= it.cnt) break;   // 16-row target tiles past the chunk's rows
-            bf16x8_t ka;
-#pragma unroll
-            for (int e = 0; e < 8; ++e) {
-                float r2 = 0.f;
-#pragma unroll
-                for (int c = 0; c < DC; ++c) {
-                    const float dx = xt[tm][c] - sp[c][e];
-                    r2 += dx * dx;
-                }
-                const float kij = sj[e] == ti[tm] ? (float)kp.diag : kfun_k<KIND>(kp, r2);
-                ka[e] = (__bf16)kij;
-            }
-#pragma unroll
-            for (int ct = 0; ct < CT; ++ct)
-                acc[tm][ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ka, xb[ct], acc[tm][ct], 0, 0, 0);
+            const int o = 16 * tm + a;
+            ti[tm] = o < it.cnt ? it.lo + o : -1;
+    #pragma unroll
+            for (int c = 0; c < 4; ++c)
+                xt[tm][c] = (ti[tm] >= 0 && c < d) ? (float)pts[c * N + ti[tm]] : 0.f;
+        }
+        for (int e = threadIdx.x; e < it.nn; e += 256) {
+            const int2 rg = nrng[it.nb0 + e];
+            s_rs[e] = rg.x;
+            s_pre[e] = rg.y - rg.x;
         }
         __syncthreads();
-    }
-#pragma unroll
-    for (int tm = 0; tm < 4; ++tm)
-#pragma unroll
-        for (int ct = 0; ct < CT; ++ct) red[wv][tm][ct][lane] = acc[tm][ct];
-    __syncthreads();
-    // wave tm writes target tile tm: lane (a, q) holds rows 16 tm + 4 q + e,
-    // right-hand side 16 ct + a
-    {
-        const int tm = wv;
-#pragma unroll
-        for (int ct = 0; ct < CT; ++ct) {
-            f32x4_t v = red[0][tm][ct][lane];
-#pragma unroll
-            for (int w2 = 1; w2 < 4; ++w2) v += red[w2][tm][ct][lane];
-            const int c = 16 * ct + a;
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const int o = 16 * tm + 4 * q + e;
-                if (o < it.cnt && c < nc) {
-                    const int64_t i = it.lo + o;
-                    yl[(int64_t)c * N + i] = v[e];
+        if (threadIdx.x == 0) {
+            int acc = 0;
+            for (int e = 0; e < it.nn; ++e) {
+                const int len = s_pre[e];
+                s_pre[e] = acc;
+                acc += len;
+            }
+            s_pre[it.nn] = acc;
+        }
+        __syncthreads();
+        const int total = s_pre[it.nn];
+        f32x4_t acc[4][CT];
+    #pragma unroll
+        for (int tm = 0; tm < 4; ++tm)
+    #pragma unroll
+            for (int ct = 0; ct < CT; ++ct) acc[tm][ct] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+        for (int t0 = 0; t0 < total; t0 += kNmTile) {
+            const int tn = min(kNmTile, total - t0);
+            // stage the tile: source index, coordinates, x rows (zero past tn)
+            for (int sI = threadIdx.x; sI < kNmTile; sI += 256) {
+                int j = -1;
+                if (sI < tn) {
+                    const int sidx = t0 + sI;
+                    int lo = 0, hi = it.nn - 1;
+                    while (lo < hi) {
+                        const int mid = (lo + hi + 1) >> 1;
+                        if (s_pre[mid] <= sidx)
+                            lo = mid;
+                        else
+                            hi = mid - 1;
+                    }
+                    j = s_rs[lo] + (sidx - s_pre[lo]);
+                }
+                s_j[sI] = j;
+    #pragma unroll
+                for (int c = 0; c < 4; ++c)
+                    s_pt[c][sI] = j < 0 ? kNmFar : c < d ? (float)pts[c * N + j] : 0.f;
+            }
+            __syncthreads();
+            for (int f = threadIdx.x; f < kNmTile * NRP; f += 256) {
+                const int sI = f / NRP, c = f - sI * NRP;
+                const int j = s_j[sI];
+                s_x[sI >> 3][c][sI & 7] = j >= 0 ? xr[(int64_t)j * NRP + c] : (uint16_t)0;
+            }
+            __syncthreads();
+            // this wave: sources 32 wv + 8 q + e of the tile
+            bf16x8_t xb[CT];
+    #pragma unroll
+            for (int ct = 0; ct < CT; ++ct)
+                xb[ct] = __builtin_bit_cast(bf16x8_t,
+                                            *reinterpret_cast<const u16x8_t*>(&s_x[4 * wv + q][16 * ct + a][0]));
+            // this lane's 8 sources: indices and coordinates, read once per tile
+            const int sb0 = 32 * wv + 8 * q;
+            int sj[8];
+            float sp[4][8];
+            {
+                const int4 j0 = *reinterpret_cast<const int4*>(&s_j[sb0]);
+                const int4 j1 = *reinterpret_cast<const int4*>(&s_j[sb0 + 4]);
+                sj[0] = j0.x; sj[1] = j0.y; sj[2] = j0.z; sj[3] = j0.w;
+                sj[4] = j1.x; sj[5] = j1.y; sj[6] = j1.z; sj[7] = j1.w;
+    #pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    const float4 p0 = *reinterpret_cast<const float4*>(&s_pt[c][sb0]);
+                    const float4 p1 = *reinterpret_cast<const float4*>(&s_pt[c][sb0 + 4]);
+                    sp[c][0] = p0.x; sp[c][1] = p0.y; sp[c][2] = p0.z; sp[c][3] = p0.w;
+                    sp[c][4] = p1.x; sp[c][5] = p1.y; sp[c][6] = p1.z; sp[c][7] = p1.w;
+                }
+            }
+    #pragma unroll
+            for (int tm = 0; tm < 4; ++tm) {
+                if (16 * tm >= it.cnt) break;   // 16-row target tiles past the chunk's rows
+                bf16x8_t ka;
+    #pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    float r2 = 0.f;
+    #pragma unroll
+                    for (int c = 0; c < DC; ++c) {
+                        const float dx = xt[tm][c] - sp[c][e];
+                        r2 += dx * dx;
+                    }
+                    const float kij = sj[e] == ti[tm] ? (float)kp.diag : kfun_k<KIND>(kp, r2);
+                    ka[e] = (__bf16)kij;
+                }
+    #pragma unroll
+                for (int ct = 0; ct < CT; ++ct)
+                    acc[tm][ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ka, xb[ct], acc[tm][ct], 0, 0, 0);
+            }
+            __syncthreads();
+        }
+    #pragma unroll
+        for (int tm = 0; tm < 4; ++tm)
+    #pragma unroll
+            for (int ct = 0; ct < CT; ++ct) red[wv][tm][ct][lane] = acc[tm][ct];
+        __syncthreads();
+        // wave tm writes target tile tm: lane (a, q) holds rows 16 tm + 4 q + e,
+        // right-hand side 16 ct + a
+        {
+            const int tm = wv;
+    #pragma unroll
+            for (int ct = 0; ct < CT; ++ct) {
+                f32x4_t v = red[0][tm][ct][lane];
+    #pragma unroll
+                for (int w2 = 1; w2 < 4; ++w2) v += red[w2][tm][ct][lane];
+                const int c = 16 * ct + a;
+    #pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int o = 16 * tm + 4 * q + e;
+                    if (o < it.cnt && c < nc) {
+                        const int64_t i = it.lo + o;
+                        yl[(int64_t)c * N + i] = v[e];
+                    }
                 }
             }
         }
+        __syncthreads();   // LDS is reused by the next item
     }
 }
 
@@ -1835,6 +1845,14 @@ namespace {
 
 inline size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
+// grid of a near-field kernel that runs beside the low-rank stages: at most
+// cap workgroups (0: one per item), each looping over items
+constexpr int64_t kNearGridCap = 256;     // on-the-fly near field (FP64 / FP32): one per CU
+constexpr int64_t kNearMfmaGridCap = 0;   // near field on matrix cores
+inline unsigned near_grid(int64_t n, int64_t cap) {
+    return (unsigned)(cap > 0 ? std::min(n, cap) : n);
+}
+
 template <typename XT, typename S, typename C, int NR>
 void run_matvec(hodlr_t h, const XT* X, int64_t ldx, int nrhs, XT* Y, int64_t ldy, char* ws,
                 hipEvent_t const* ev, int nev, hipStream_t s) {
@@ -1888,8 +1906,8 @@ void run_matvec(hodlr_t h, const XT* X, int64_t ldx, int nrhs, XT* Y, int64_t ld
                 switch (h->kp.kind * 2 + (h->d == 4 ? 1 : 0)) {
 #define HODLR_NEAR_MFMA(K, DC)                                                                  \
     case K * 2 + (DC == 4 ? 1 : 0):                                                             \
-        k_near_mfma<CTn, K, DC><<<(unsigned)h->n_near_items, 256, 0, h->aux>>>(                 \
-            h->near_items, h->near_rng, h->pts, N, h->d, h->kp, xr, nc, yl);                     \
+        k_near_mfma<CTn, K, DC><<<near_grid(h->n_near_items, kNearMfmaGridCap), 256, 0, h->aux>>>( \
+            h->near_items, h->n_near_items, h->near_rng, h->pts, N, h->d, h->kp, xr, nc, yl);    \
         break;
 #define HODLR_NEAR_MFMA2(K) HODLR_NEAR_MFMA(K, 3) HODLR_NEAR_MFMA(K, 4)
                     HODLR_NEAR_MFMA2(HODLR_K_LOG)
@@ -1952,8 +1970,8 @@ void run_matvec(hodlr_t h, const XT* X, int64_t ldx, int nrhs, XT* Y, int64_t ld
                 k_permute_out<XT><<<nblk(N, 256), 256, 0, s>>>(yl, N, nc, c0, h->perm, Y, ldy);
             else
                 k_gather_near<XT, C, NR><<<(unsigned)h->n_near_items, TG, 0, s>>>(
-                    h->near_items, h->leaf_seg, h->near_rng, h->kappa, h->pts, N, h->d, h->kp, x,
-                    contrib, CT, h->perm, nrhs, c0, Y, ldy, yl, nullptr);
+                    h->near_items, h->n_near_items, h->leaf_seg, h->near_rng, h->kappa, h->pts, N,
+                    h->d, h->kp, x, contrib, CT, h->perm, nrhs, c0, Y, ldy, yl, nullptr);
             HIP_CHECK(hipGetLastError());
             continue;
         } else {
@@ -1964,9 +1982,9 @@ void run_matvec(hodlr_t h, const XT* X, int64_t ldx, int nrhs, XT* Y, int64_t ld
             switch (h->kp.kind) {
 #define HODLR_NEAR(K)                                                                           \
     case K:                                                                                     \
-        k_gather_near<XT, C, NR, K, kNearOnly><<<(unsigned)h->n_near_items, TG, 0, h->aux>>>(   \
-            h->near_items, h->leaf_seg, h->near_rng, h->kappa, h->pts, N, h->d, h->kp, x,       \
-            contrib, CT, h->perm, nrhs, c0, Y, ldy, nullptr, yn);                               \
+        k_gather_near<XT, C, NR, K, kNearOnly><<<near_grid(h->n_near_items, kNearGridCap), TG, 0, h->aux>>>( \
+            h->near_items, h->n_near_items, h->leaf_seg, h->near_rng, h->kappa, h->pts, N, h->d, \
+            h->kp, x, contrib, CT, h->perm, nrhs, c0, Y, ldy, nullptr, yn);                     \
         break;
                 HODLR_NEAR(HODLR_K_LOG)
                 HODLR_NEAR(HODLR_K_INV_R)
@@ -1980,9 +1998,9 @@ void run_matvec(hodlr_t h, const XT* X, int64_t ldx, int nrhs, XT* Y, int64_t ld
 #undef HODLR_NEAR
             }
         } else {
-            k_gather_near<XT, C, NR, -1, kNearOnly><<<(unsigned)h->n_near_items, TG, 0, h->aux>>>(
-                h->near_items, h->leaf_seg, h->near_rng, h->kappa, h->pts, N, h->d, h->kp, x,
-                contrib, CT, h->perm, nrhs, c0, Y, ldy, nullptr, yn);
+            k_gather_near<XT, C, NR, -1, kNearOnly><<<near_grid(h->n_near_items, kNearGridCap), TG, 0, h->aux>>>(
+                h->near_items, h->n_near_items, h->leaf_seg, h->near_rng, h->kappa, h->pts, N,
+                h->d, h->kp, x, contrib, CT, h->perm, nrhs, c0, Y, ldy, nullptr, yn);
         }
         HIP_CHECK(hipGetLastError());
         if constexpr (NR == 1 && !std::is_same<S, bf16>::value) {
@@ -2075,8 +2093,8 @@ void run_matvec(hodlr_t h, const XT* X, int64_t ldx, int nrhs, XT* Y, int64_t ld
         // near-field sums plus the contributions of every level, to Y
         join();
         k_gather_near<XT, C, NR, -1, kGatherOnly><<<(unsigned)h->n_near_items, TG, 0, s>>>(
-            h->near_items, h->leaf_seg, h->near_rng, h->kappa, h->pts, N, h->d, h->kp, x, contrib,
-            CT, h->perm, nrhs, c0, Y, ldy, nullptr, yn);
+            h->near_items, h->n_near_items, h->leaf_seg, h->near_rng, h->kappa, h->pts, N, h->d,
+            h->kp, x, contrib, CT, h->perm, nrhs, c0, Y, ldy, nullptr, yn);
         HIP_CHECK(hipGetLastError());
     }
     if (ev) HIP_CHECK(hipEventRecord(ev[4], s));

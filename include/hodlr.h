@@ -158,8 +158,8 @@ hodlr_status hodlr_matvec(hodlr_t h, const void* X, int64_t ldx, int nrhs, int x
  * split over several workgroups; gather of the contributions and the
  * near-field sums plus permutation back; the near field itself runs on the
  * handle's second stream beside the second and third stages, and with BF16
- * matrix cores beside the second, the projections).  Stage times are those
- * of the caller's stream.  nevents == 11: the
+ * matrix cores beside both passes, joined before the permutation back).
+ * Stage times are those of the caller's stream.  nevents == 11: the
  * same five, then events[5 + c] recorded after the launch of block-size
  * class c = 0..5 inside the second stage (classes of hodlr_info
  * class_blocks).  Same results and errors as hodlr_matvec (EINVAL if events

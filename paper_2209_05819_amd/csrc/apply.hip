@@ -192,15 +192,17 @@ __global__ void k_permute_in(const XT* __restrict__ X, int64_t ldx, int nrhs, in
     for (int c = 0; c < nrhs; ++c) x[c * N + p] = (C)X[c * ldx + u];
 }
 
-// Y[:, c0 + c] = the level sums yl[c] (tree order) in user order, c < nc.
+// Y[:, c0 + c] = the level sums yl[c] plus the near sums yn[c] (both in tree
+// order), in user order, c < nc.
 template <typename XT>
-__global__ void k_permute_out(const float* __restrict__ yl, int64_t N, int nc, int c0,
-                              const int32_t* __restrict__ perm, XT* __restrict__ Y,
-                              int64_t ldy) {
+__global__ void k_permute_out(const float* __restrict__ yl, const float* __restrict__ yn,
+                              int64_t N, int nc, int c0, const int32_t* __restrict__ perm,
+                              XT* __restrict__ Y, int64_t ldy) {
     const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (p >= N) return;
     const int64_t u = perm[p];
-    for (int c = 0; c < nc; ++c) Y[(int64_t)(c0 + c) * ldy + u] = (XT)yl[(int64_t)c * N + p];
+    for (int c = 0; c < nc; ++c)
+        Y[(int64_t)(c0 + c) * ldy + u] = (XT)(yl[(int64_t)c * N + p] + yn[(int64_t)c * N + p]);
 }
 
 // One wave applies one stored block with NR right-hand sides: the
@@ -1377,10 +1379,9 @@ __global__ __launch_bounds__(256) void k_skel(const BlockDesc* __restrict__ bloc
 // chunk of a leaf; the sources are staged through LDS 128 at a time
 // (coordinates, and x rows in the operand layout) and each wave multiplies
 // all 64 targets by 32 of them: 4 x CT 16x16x32 products per wave and tile.
-// The waves' partial sums meet in LDS in wave order and are written as the
-// rows' starting values of the level sums yl (tree order), which pass 2 then
-// adds to: the kernel needs nothing from the low-rank passes and runs beside
-// pass 1.  The kernel function (KIND) and the number of coordinates (DC = 3 for d <= 3,
+// The waves' partial sums meet in LDS in wave order and are written to the
+// near sums yn (tree order): the kernel needs nothing from the low-rank
+// passes and runs beside them.  The kernel function (KIND) and the number of coordinates (DC = 3 for d <= 3,
 // 4 for d = 4) are fixed at compile time; padded sources sit at a far
 // sentinel point with x = 0 (finite kernel values times zero) and padded
 // target rows are computed but never written, so the pair loop carries no
@@ -1392,7 +1393,7 @@ template <int CT, int KIND, int DC>
 __global__ __launch_bounds__(256) void k_near_mfma(
     const NearItem* __restrict__ items, int64_t nitems, const int2* __restrict__ nrng,
     const double* __restrict__ pts, int64_t N, int d, KParams kp,
-    const uint16_t* __restrict__ xr, int nc, float* __restrict__ yl) {
+    const uint16_t* __restrict__ xr, int nc, float* __restrict__ yn) {
     constexpr int NRP = 16 * CT;
     __shared__ int s_pre[kNearTileRanges + 1], s_rs[kNearTileRanges];
     __shared__ __attribute__((aligned(16))) int s_j[kNmTile];
@@ -1532,7 +1533,7 @@ __global__ __launch_bounds__(256) void k_near_mfma(
                     const int o = 16 * tm + 4 * q + e;
                     if (o < it.cnt && c < nc) {
                         const int64_t i = it.lo + o;
-                        yl[(int64_t)c * N + i] = v[e];
+                        yn[(int64_t)c * N + i] = v[e];
                     }
                 }
             }
@@ -1845,13 +1846,11 @@ namespace {
 
 inline size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
-// grid of a near-field kernel that runs beside the low-rank stages: at most
-// cap workgroups (0: one per item), each looping over items
-constexpr int64_t kNearGridCap = 256;     // on-the-fly near field (FP64 / FP32): one per CU
-constexpr int64_t kNearMfmaGridCap = 0;   // near field on matrix cores
-inline unsigned near_grid(int64_t n, int64_t cap) {
-    return (unsigned)(cap > 0 ? std::min(n, cap) : n);
-}
+// grid of a near-field kernel that runs beside the low-rank stages: one
+// workgroup per CU, each looping over items, so that the kernel holds a small
+// share of every CU while the factor streams run
+constexpr int64_t kNearGridCap = 256;
+inline unsigned near_grid(int64_t n) { return (unsigned)std::min(n, kNearGridCap); }
 
 template <typename XT, typename S, typename C, int NR>
 void run_matvec(hodlr_t h, const XT* X, int64_t ldx, int nrhs, XT* Y, int64_t ldy, char* ws,
@@ -1896,18 +1895,20 @@ void run_matvec(hodlr_t h, const XT* X, int64_t ldx, int nrhs, XT* Y, int64_t ld
             uint16_t* tproj = reinterpret_cast<uint16_t*>(p);
             p += align256(2 * (size_t)std::max<int64_t>(h->mt_total, 1) * NR);
             float* part = reinterpret_cast<float*>(p);
+            p += align256(4 * (size_t)std::max<int64_t>(h->mpart_total, 1) * NR);
+            float* ynm = reinterpret_cast<float*>(p);   // near sums
             k_rows_bf16<XT><<<nblk(N * NR, 256), 256, 0, s>>>(X, ldx, c0, nc, N, h->perm, NR, xr);
             HIP_CHECK(hipGetLastError());
-            // the near field on matrix cores writes the starting values of the
-            // level sums on the second stream while pass 1 runs
+            // the near field on matrix cores, on the second stream beside both
+            // passes, into its own sums
             const bool nm = h->near_max_ranges <= kNearTileRanges && h->d <= 4;
             if (nm) {
                 fork();
                 switch (h->kp.kind * 2 + (h->d == 4 ? 1 : 0)) {
 #define HODLR_NEAR_MFMA(K, DC)                                                                  \
     case K * 2 + (DC == 4 ? 1 : 0):                                                             \
-        k_near_mfma<CTn, K, DC><<<near_grid(h->n_near_items, kNearMfmaGridCap), 256, 0, h->aux>>>( \
-            h->near_items, h->n_near_items, h->near_rng, h->pts, N, h->d, h->kp, xr, nc, yl);    \
+        k_near_mfma<CTn, K, DC><<<near_grid(h->n_near_items), 256, 0, h->aux>>>( \
+            h->near_items, h->n_near_items, h->near_rng, h->pts, N, h->d, h->kp, xr, nc, ynm);   \
         break;
 #define HODLR_NEAR_MFMA2(K) HODLR_NEAR_MFMA(K, 3) HODLR_NEAR_MFMA(K, 4)
                     HODLR_NEAR_MFMA2(HODLR_K_LOG)
@@ -1925,10 +1926,9 @@ void run_matvec(hodlr_t h, const XT* X, int64_t ldx, int nrhs, XT* Y, int64_t ld
                         fail(HODLR_EINVAL, "unknown kernel function");
                 }
                 HIP_CHECK(hipGetLastError());
-            } else {
-                k_fill_zero<float><<<nblk(N * NR, 256), 256, 0, s>>>(yl, N * NR);
-                HIP_CHECK(hipGetLastError());
             }
+            k_fill_zero<float><<<nblk(N * NR, 256), 256, 0, s>>>(yl, N * NR);
+            HIP_CHECK(hipGetLastError());
             // pass 1: projections, by workgroup width
             for (int w = 0; w < 4; ++w) {
                 const int64_t n0 = h->mjob_off[w], cnt = h->mjob_off[w + 1] - n0;
@@ -1951,7 +1951,6 @@ void run_matvec(hodlr_t h, const XT* X, int64_t ldx, int nrhs, XT* Y, int64_t ld
             if (ev && nev > 5 && c0 == 0)
                 for (int c = 4; c < kNumClasses; ++c) HIP_CHECK(hipEventRecord(ev[5 + c], s));
             if (ev && c0 == 0) HIP_CHECK(hipEventRecord(ev[2], s));
-            if (nm) join();
             // pass 2: expansions, one level at a time (tiles of a level own
             // disjoint rows of the level sum)
             for (int l = 1; l <= h->kappa; ++l) {
@@ -1966,9 +1965,11 @@ void run_matvec(hodlr_t h, const XT* X, int64_t ldx, int nrhs, XT* Y, int64_t ld
                 HIP_CHECK(hipGetLastError());
             }
             if (ev && c0 == 0) HIP_CHECK(hipEventRecord(ev[3], s));
-            if (nm)
-                k_permute_out<XT><<<nblk(N, 256), 256, 0, s>>>(yl, N, nc, c0, h->perm, Y, ldy);
-            else
+            if (nm) {
+                join();
+                k_permute_out<XT><<<nblk(N, 256), 256, 0, s>>>(yl, ynm, N, nc, c0, h->perm, Y,
+                                                               ldy);
+            } else
                 k_gather_near<XT, C, NR><<<(unsigned)h->n_near_items, TG, 0, s>>>(
                     h->near_items, h->n_near_items, h->leaf_seg, h->near_rng, h->kappa, h->pts, N,
                     h->d, h->kp, x, contrib, CT, h->perm, nrhs, c0, Y, ldy, yl, nullptr);
@@ -1982,7 +1983,7 @@ void run_matvec(hodlr_t h, const XT* X, int64_t ldx, int nrhs, XT* Y, int64_t ld
             switch (h->kp.kind) {
 #define HODLR_NEAR(K)                                                                           \
     case K:                                                                                     \
-        k_gather_near<XT, C, NR, K, kNearOnly><<<near_grid(h->n_near_items, kNearGridCap), TG, 0, h->aux>>>( \
+        k_gather_near<XT, C, NR, K, kNearOnly><<<near_grid(h->n_near_items), TG, 0, h->aux>>>( \
             h->near_items, h->n_near_items, h->leaf_seg, h->near_rng, h->kappa, h->pts, N, h->d, \
             h->kp, x, contrib, CT, h->perm, nrhs, c0, Y, ldy, nullptr, yn);                     \
         break;
@@ -1998,7 +1999,7 @@ void run_matvec(hodlr_t h, const XT* X, int64_t ldx, int nrhs, XT* Y, int64_t ld
 #undef HODLR_NEAR
             }
         } else {
-            k_gather_near<XT, C, NR, -1, kNearOnly><<<near_grid(h->n_near_items, kNearGridCap), TG, 0, h->aux>>>(
+            k_gather_near<XT, C, NR, -1, kNearOnly><<<near_grid(h->n_near_items), TG, 0, h->aux>>>(
                 h->near_items, h->n_near_items, h->leaf_seg, h->near_rng, h->kappa, h->pts, N,
                 h->d, h->kp, x, contrib, CT, h->perm, nrhs, c0, Y, ldy, nullptr, yn);
         }
@@ -2132,10 +2133,12 @@ void reserve_workspace(hodlr_t h, int nrhs, int compute_prec, hipStream_t s) {
     const int nr = (nrhs == 1 || h->opts.skeleton) ? 1
                    : b16 ? (nrhs <= 16 ? 16 : 32) : (nrhs <= 4 ? 4 : 8);
     size_t need;
-    if (b16 && nr >= 16)   // x, x rows, level sums, projections, panel partials
-        need = align256(cs * (size_t)N * nrhs) + align256(2 * (size_t)N * nr) + align256(4 * (size_t)N * nr) +
+    if (b16 && nr >= 16)   // x, x rows, level sums, projections, panel partials, near sums
+        need = align256(cs * (size_t)N * nrhs) + align256(2 * (size_t)N * nr) +
+               align256(4 * (size_t)N * nr) +
                align256(2 * (size_t)std::max<int64_t>(h->mt_total, 1) * nr) +
-               4 * (size_t)std::max<int64_t>(h->mpart_total, 1) * nr + 4096;
+               align256(4 * (size_t)std::max<int64_t>(h->mpart_total, 1) * nr) +
+               align256(4 * (size_t)N * nr) + 4096;
     else   // x, contributions, projections, partials, near-field sums
         need = cs * ((size_t)N * nrhs + (size_t)CT * nr + 2 * (size_t)TT * nr +
                      2 * (size_t)kProjSegMax * (size_t)h->n_proj_sums * nr + (size_t)N * nr) +

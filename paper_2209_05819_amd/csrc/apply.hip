@@ -1846,11 +1846,21 @@ namespace {
 
 inline size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
-// grid of a near-field kernel that runs beside the low-rank stages: one
-// workgroup per CU, each looping over items, so that the kernel holds a small
-// share of every CU while the factor streams run
+// Grid of the on-the-fly near kernel beside the low-rank stages.  When the
+// near field is light next to the factor bytes the stages stream (at most
+// kNearCapPairsPerByte dense pairs per column and byte), one workgroup per CU
+// looping over the items: the kernel then ends well inside the streams while
+// holding only a small share of every CU.  Otherwise one workgroup per item,
+// so that a near-heavy product (crowded leaves) gets the whole chip.
 constexpr int64_t kNearGridCap = 256;
-inline unsigned near_grid(int64_t n) { return (unsigned)std::min(n, kNearGridCap); }
+constexpr double kNearCapPairsPerByte = 0.05;
+inline unsigned near_grid(hodlr_t h, int nc, size_t factor_elem_bytes) {
+    int64_t fe = h->split_felems;
+    for (int c = 0; c < kNumClasses; ++c) fe += h->cls_felems[c];
+    const double light = kNearCapPairsPerByte * (double)fe * (double)factor_elem_bytes;
+    const int64_t n = h->n_near_items;
+    return (unsigned)((double)h->near_pairs * nc <= light ? std::min(n, kNearGridCap) : n);
+}
 
 template <typename XT, typename S, typename C, int NR>
 void run_matvec(hodlr_t h, const XT* X, int64_t ldx, int nrhs, XT* Y, int64_t ldy, char* ws,
@@ -1907,7 +1917,7 @@ void run_matvec(hodlr_t h, const XT* X, int64_t ldx, int nrhs, XT* Y, int64_t ld
                 switch (h->kp.kind * 2 + (h->d == 4 ? 1 : 0)) {
 #define HODLR_NEAR_MFMA(K, DC)                                                                  \
     case K * 2 + (DC == 4 ? 1 : 0):                                                             \
-        k_near_mfma<CTn, K, DC><<<near_grid(h->n_near_items), 256, 0, h->aux>>>( \
+        k_near_mfma<CTn, K, DC><<<(unsigned)h->n_near_items, 256, 0, h->aux>>>(         \
             h->near_items, h->n_near_items, h->near_rng, h->pts, N, h->d, h->kp, xr, nc, ynm);   \
         break;
 #define HODLR_NEAR_MFMA2(K) HODLR_NEAR_MFMA(K, 3) HODLR_NEAR_MFMA(K, 4)
@@ -1978,12 +1988,13 @@ void run_matvec(hodlr_t h, const XT* X, int64_t ldx, int nrhs, XT* Y, int64_t ld
         } else {
         // the near field on the second stream, beside the low-rank stages
         fork();
+        const unsigned gnear = near_grid(h, std::min(NR, nrhs - c0), sizeof(S));
         if constexpr (NR == 1) {
             // one right-hand side: the kernel function fixed at compile time
             switch (h->kp.kind) {
 #define HODLR_NEAR(K)                                                                           \
     case K:                                                                                     \
-        k_gather_near<XT, C, NR, K, kNearOnly><<<near_grid(h->n_near_items), TG, 0, h->aux>>>( \
+        k_gather_near<XT, C, NR, K, kNearOnly><<<gnear, TG, 0, h->aux>>>(                      \
             h->near_items, h->n_near_items, h->leaf_seg, h->near_rng, h->kappa, h->pts, N, h->d, \
             h->kp, x, contrib, CT, h->perm, nrhs, c0, Y, ldy, nullptr, yn);                     \
         break;
@@ -1999,7 +2010,7 @@ void run_matvec(hodlr_t h, const XT* X, int64_t ldx, int nrhs, XT* Y, int64_t ld
 #undef HODLR_NEAR
             }
         } else {
-            k_gather_near<XT, C, NR, -1, kNearOnly><<<near_grid(h->n_near_items), TG, 0, h->aux>>>(
+            k_gather_near<XT, C, NR, -1, kNearOnly><<<gnear, TG, 0, h->aux>>>(
                 h->near_items, h->n_near_items, h->leaf_seg, h->near_rng, h->kappa, h->pts, N,
                 h->d, h->kp, x, contrib, CT, h->perm, nrhs, c0, Y, ldy, nullptr, yn);
         }

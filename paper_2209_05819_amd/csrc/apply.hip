@@ -1041,14 +1041,14 @@ __global__ __launch_bounds__(TG) void k_gather_near(
         const int64_t i = it.lo + t;
         const int nc = min(NR, nrhs - c0);
         C acc[NR];
-    #pragma unroll
+#pragma unroll
         for (int c = 0; c < NR; ++c) acc[c] = 0;
         double xi[kMaxD];
         if (MODE != kGatherOnly && active)
             for (int a = 0; a < d; ++a) xi[a] = pts[a * N + i];
         if constexpr (MODE == kGatherOnly) {
             if (active && sg == 0)
-    #pragma unroll
+#pragma unroll
                 for (int c = 0; c < NR; ++c)
                     if (c < nc) acc[c] = yn[(int64_t)c * N + i];
         } else if (d <= 4 && it.nn <= kNearTileRanges) {
@@ -1068,7 +1068,7 @@ __global__ __launch_bounds__(TG) void k_gather_near(
             // their relative accuracy (zero beyond d)
             double ref[4];
             C xc[4];
-    #pragma unroll
+#pragma unroll
             for (int a = 0; a < 4; ++a) {
                 ref[a] = (sizeof(C) == 4 && a < d) ? pts[a * N + it.leaf0] : 0.0;
                 xc[a] = (active && a < d) ? (C)(xi[a] - ref[a]) : (C)0;
@@ -1111,7 +1111,7 @@ __global__ __launch_bounds__(TG) void k_gather_near(
                 auto term = [&](int q, bool ok) {
                     const C4 pq = s_pt[q];
                     C r2 = 0;
-    #pragma unroll
+#pragma unroll
                     for (int a = 0; a < (P ? 3 : 4); ++a) {
                         const C dx = xc[a] - pq.v[a];
                         r2 += dx * dx;
@@ -1122,13 +1122,13 @@ __global__ __launch_bounds__(TG) void k_gather_near(
                     if constexpr (P) {
                         acc[0] += kij * pq.v[3];
                     } else {
-    #pragma unroll
+#pragma unroll
                         for (int c = 0; c < NR; ++c) acc[c] += kij * s_x[c][q];
                     }
                 };
                 int q0 = wv * S;
                 for (; q0 + 3 * SG + S <= tn; q0 += 4 * SG) {   // four records read at once
-    #pragma unroll
+#pragma unroll
                     for (int u = 0; u < 4; ++u) term(q0 + u * SG + sl, true);
                 }
                 for (; q0 + S <= tn; q0 += SG) term(q0 + sl, true);
@@ -1151,12 +1151,12 @@ __global__ __launch_bounds__(TG) void k_gather_near(
                     }
                     const int j = s_rs[lo] + (sidx - s_pre[lo]);
                     C4 pq;
-    #pragma unroll
+#pragma unroll
                     for (int a = 0; a < 4; ++a) pq.v[a] = a < d ? (C)(pts[a * N + j] - ref[a]) : (C)0;
                     if (packx) {
                         pq.v[3] = x[(int64_t)c0 * N + j];
                     } else {
-    #pragma unroll
+#pragma unroll
                         for (int c = 0; c < NR; ++c) s_x[c][q] = c < nc ? x[(int64_t)(c0 + c) * N + j] : (C)0;
                     }
                     s_pt[q] = pq;
@@ -1185,7 +1185,7 @@ __global__ __launch_bounds__(TG) void k_gather_near(
                         }
                         kij = kfun_k<KIND>(kp, r2);
                     }
-    #pragma unroll
+#pragma unroll
                     for (int c = 0; c < NR; ++c)
                         if (c < nc) acc[c] += kij * x[(int64_t)(c0 + c) * N + j];
                 }
@@ -1195,7 +1195,7 @@ __global__ __launch_bounds__(TG) void k_gather_near(
             if (active && ylev) {
                 // the low-rank part is already summed per row (columns c0 .. c0+nc)
                 if (sg == 0)
-    #pragma unroll
+#pragma unroll
                     for (int c = 0; c < NR; ++c)
                         if (c < nc) acc[c] += ylev[(int64_t)c * N + i];
             } else if (active) {
@@ -1203,18 +1203,18 @@ __global__ __launch_bounds__(TG) void k_gather_near(
                 for (int l = 0; l < kappa; ++l) {
                     const SegRef sr = lseg[(int64_t)it.leaf * kappa + l];
                     const C* __restrict__ seg = contrib + sr.base + off;
-    #pragma unroll 4
+#pragma unroll 4
                     for (int64_t e = sg; e < sr.ne; e += SG)
-    #pragma unroll
+#pragma unroll
                         for (int c = 0; c < NR; ++c)
                             if (c < nc) acc[c] += seg[(int64_t)c * CT + e * sr.len];
                 }
             }
         }
         for (int o = mp; o < 64; o <<= 1)
-    #pragma unroll
+#pragma unroll
             for (int c = 0; c < NR; ++c) acc[c] += __shfl_xor(acc[c], o, 64);
-    #pragma unroll
+#pragma unroll
         for (int c = 0; c < NR; ++c) red[wv][c][lane] = acc[c];
         __syncthreads();
         if (wv == 0 && active && lane < mp) {
@@ -1410,11 +1410,11 @@ __global__ __launch_bounds__(256) void k_near_mfma(
         // it.lo + 16 tm + a
         float xt[4][4];
         int ti[4];
-    #pragma unroll
+#pragma unroll
         for (int tm = 0; tm < 4; ++tm) {
             const int o = 16 * tm + a;
             ti[tm] = o < it.cnt ? it.lo + o : -1;
-    #pragma unroll
+#pragma unroll
             for (int c = 0; c < 4; ++c)
                 xt[tm][c] = (ti[tm] >= 0 && c < d) ? (float)pts[c * N + ti[tm]] : 0.f;
         }
@@ -1436,9 +1436,9 @@ __global__ __launch_bounds__(256) void k_near_mfma(
         __syncthreads();
         const int total = s_pre[it.nn];
         f32x4_t acc[4][CT];
-    #pragma unroll
+#pragma unroll
         for (int tm = 0; tm < 4; ++tm)
-    #pragma unroll
+#pragma unroll
             for (int ct = 0; ct < CT; ++ct) acc[tm][ct] = f32x4_t{0.f, 0.f, 0.f, 0.f};
         for (int t0 = 0; t0 < total; t0 += kNmTile) {
             const int tn = min(kNmTile, total - t0);
@@ -1458,7 +1458,7 @@ __global__ __launch_bounds__(256) void k_near_mfma(
                     j = s_rs[lo] + (sidx - s_pre[lo]);
                 }
                 s_j[sI] = j;
-    #pragma unroll
+#pragma unroll
                 for (int c = 0; c < 4; ++c)
                     s_pt[c][sI] = j < 0 ? kNmFar : c < d ? (float)pts[c * N + j] : 0.f;
             }
@@ -1471,7 +1471,7 @@ __global__ __launch_bounds__(256) void k_near_mfma(
             __syncthreads();
             // this wave: sources 32 wv + 8 q + e of the tile
             bf16x8_t xb[CT];
-    #pragma unroll
+#pragma unroll
             for (int ct = 0; ct < CT; ++ct)
                 xb[ct] = __builtin_bit_cast(bf16x8_t,
                                             *reinterpret_cast<const u16x8_t*>(&s_x[4 * wv + q][16 * ct + a][0]));
@@ -1484,7 +1484,7 @@ __global__ __launch_bounds__(256) void k_near_mfma(
                 const int4 j1 = *reinterpret_cast<const int4*>(&s_j[sb0 + 4]);
                 sj[0] = j0.x; sj[1] = j0.y; sj[2] = j0.z; sj[3] = j0.w;
                 sj[4] = j1.x; sj[5] = j1.y; sj[6] = j1.z; sj[7] = j1.w;
-    #pragma unroll
+#pragma unroll
                 for (int c = 0; c < 4; ++c) {
                     const float4 p0 = *reinterpret_cast<const float4*>(&s_pt[c][sb0]);
                     const float4 p1 = *reinterpret_cast<const float4*>(&s_pt[c][sb0 + 4]);
@@ -1492,14 +1492,14 @@ __global__ __launch_bounds__(256) void k_near_mfma(
                     sp[c][4] = p1.x; sp[c][5] = p1.y; sp[c][6] = p1.z; sp[c][7] = p1.w;
                 }
             }
-    #pragma unroll
+#pragma unroll
             for (int tm = 0; tm < 4; ++tm) {
                 if (16 * tm >= it.cnt) break;   // 16-row target tiles past the chunk's rows
                 bf16x8_t ka;
-    #pragma unroll
+#pragma unroll
                 for (int e = 0; e < 8; ++e) {
                     float r2 = 0.f;
-    #pragma unroll
+#pragma unroll
                     for (int c = 0; c < DC; ++c) {
                         const float dx = xt[tm][c] - sp[c][e];
                         r2 += dx * dx;
@@ -1507,28 +1507,28 @@ __global__ __launch_bounds__(256) void k_near_mfma(
                     const float kij = sj[e] == ti[tm] ? (float)kp.diag : kfun_k<KIND>(kp, r2);
                     ka[e] = (__bf16)kij;
                 }
-    #pragma unroll
+#pragma unroll
                 for (int ct = 0; ct < CT; ++ct)
                     acc[tm][ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ka, xb[ct], acc[tm][ct], 0, 0, 0);
             }
             __syncthreads();
         }
-    #pragma unroll
+#pragma unroll
         for (int tm = 0; tm < 4; ++tm)
-    #pragma unroll
+#pragma unroll
             for (int ct = 0; ct < CT; ++ct) red[wv][tm][ct][lane] = acc[tm][ct];
         __syncthreads();
         // wave tm writes target tile tm: lane (a, q) holds rows 16 tm + 4 q + e,
         // right-hand side 16 ct + a
         {
             const int tm = wv;
-    #pragma unroll
+#pragma unroll
             for (int ct = 0; ct < CT; ++ct) {
                 f32x4_t v = red[0][tm][ct][lane];
-    #pragma unroll
+#pragma unroll
                 for (int w2 = 1; w2 < 4; ++w2) v += red[w2][tm][ct][lane];
                 const int c = 16 * ct + a;
-    #pragma unroll
+#pragma unroll
                 for (int e = 0; e < 4; ++e) {
                     const int o = 16 * tm + 4 * q + e;
                     if (o < it.cnt && c < nc) {

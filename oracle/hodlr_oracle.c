@@ -485,13 +485,22 @@ void ohodlr_box_flags(const ohodlr* h, int level, uint8_t* flags)
 }
 
 /* ------------------------------------------------------------------------- */
-/* ACA with partial pivoting (Bebendorf; Tyrtyshnikov), eq. keq1.              */
-/* The approximation is the sum of rank-one terms u_k v_k^T where v_k is the   */
-/* residual of the pivot row scaled by its largest entry and u_k the residual  */
-/* of the pivot column.  A candidate term with |u||v| <= tol * |S|_F, S the    */
-/* approximation including it, ends the iteration and is not kept; the         */
-/* iteration also ends when the rank reaches its cap or every row was tried.   */
-/* ------------------------------------------------------------------------- */
+/* ACA with partial pivoting (Bebendorf; Tyrtyshnikov), eq. keq1.
+ * The approximation is the sum of rank-one terms u_k v_k^T where v_k is the
+ * residual of the pivot row scaled by its largest entry and u_k the residual
+ * of the pivot column.  A candidate term is "small" when |u||v| <= tol |S|_F,
+ * S the approximation including it.  At a small term the stop is confirmed
+ * on samples of the residual of the approximation without it: 16 evenly
+ * spaced rows and 16 evenly spaced columns (all of them in a smaller block;
+ * the c-th confirmation of a block shifts them by 997c and 991c modulo the
+ * spacing), each sum of squares scaled to an estimate of |K - S|_F^2.  The
+ * iteration ends, dropping the small term, when both estimates are at most
+ * (tol/2)^2 |S|_F^2 (half the tolerance: a residual gathered near a shared
+ * hyper-surface can hide from the samples).  Otherwise the term is kept and
+ * the next pivot row is the untried row holding the largest sampled residual
+ * entry.  The iteration also ends when the rank reaches its cap or every row
+ * was tried.
+ * ------------------------------------------------------------------------- */
 typedef double (*entry_fn)(const void* ctx, int64_t i, int64_t j);
 
 typedef struct {
@@ -519,6 +528,59 @@ static int grow(aca_out* o, int64_t m, int64_t n, int64_t need)
     return 1;
 }
 
+/* residual entry K(i,j) - sum_{p<k} U[p][i] V[p][j] */
+static double resid(entry_fn E, const void* ctx, const aca_out* o, int64_t m, int64_t n,
+                    int64_t k, int64_t i, int64_t j)
+{
+    double s = E(ctx, i, j);
+    for (int64_t p = 0; p < k; ++p) s -= o->U[p * m + i] * o->V[p * n + j];
+    return s;
+}
+
+enum { ACA_SAMPLES = 16 };
+
+/* Sampled confirmation of a stop (check number c of this block).  Returns 1
+ * when both scaled estimates of |K - S|_F^2 are at most (tol/2)^2 S2; otherwise
+ * 0 and *next = the untried row of the largest sampled residual entry (-1 if
+ * every sampled entry of an untried row is zero). */
+static int aca_confirm(entry_fn E, const void* ctx, const aca_out* o, int64_t m, int64_t n,
+                       int64_t k, double tol, double S2, int64_t c, const char* used,
+                       int64_t* next)
+{
+    int64_t sr = m < ACA_SAMPLES ? m : ACA_SAMPLES, str = m / sr;
+    int64_t sc = n < ACA_SAMPLES ? n : ACA_SAMPLES, stc = n / sc;
+    int64_t offr = (c * 997) % str, offc = (c * 991) % stc;
+    double er = 0.0, ec = 0.0, best = 0.0;
+    int64_t bi = -1;
+    for (int64_t t = 0; t < sr; ++t) {
+        int64_t i = t * str + offr;
+        for (int64_t j = 0; j < n; ++j) {
+            double v = resid(E, ctx, o, m, n, k, i, j);
+            er += v * v;
+            if (!used[i] && (fabs(v) > best || (fabs(v) == best && bi >= 0 && i < bi))) {
+                best = fabs(v);
+                bi = i;
+            }
+        }
+    }
+    for (int64_t t = 0; t < sc; ++t) {
+        int64_t j = t * stc + offc;
+        for (int64_t i = 0; i < m; ++i) {
+            double v = resid(E, ctx, o, m, n, k, i, j);
+            ec += v * v;
+            if (!used[i] && (fabs(v) > best || (fabs(v) == best && bi >= 0 && i < bi))) {
+                best = fabs(v);
+                bi = i;
+            }
+        }
+    }
+    er *= (double)m / (double)sr;
+    ec *= (double)n / (double)sc;
+    *next = bi;
+    const double lim = 0.25 * tol * tol * S2;
+    return er <= lim && ec <= lim;
+}
+
 static int aca_core(entry_fn E, const void* ctx, int64_t m, int64_t n, double tol,
                     int64_t kmax, aca_out* o)
 {
@@ -526,16 +588,12 @@ static int aca_core(entry_fn E, const void* ctx, int64_t m, int64_t n, double to
     double S2 = 0.0;
     char* used = (char*)calloc((size_t)m, 1);
     double* r = (double*)malloc(sizeof(double) * n);
-    double* u = (double*)malloc(sizeof(double) * m);
     int64_t nused = 0;
     int64_t istar = 0;
+    int64_t nchecks = 0;    /* sampled confirmations done */
     while (k < kmax) {
         /* residual of the pivot row */
-        for (int64_t j = 0; j < n; ++j) {
-            double s = E(ctx, istar, j);
-            for (int64_t p = 0; p < k; ++p) s -= o->U[p * m + istar] * o->V[p * n + j];
-            r[j] = s;
-        }
+        for (int64_t j = 0; j < n; ++j) r[j] = resid(E, ctx, o, m, n, k, istar, j);
         int64_t jstar = 0;
         for (int64_t j = 1; j < n; ++j)
             if (fabs(r[j]) > fabs(r[jstar])) jstar = j;
@@ -547,15 +605,12 @@ static int aca_core(entry_fn E, const void* ctx, int64_t m, int64_t n, double to
             istar = i;
             continue;
         }
-        if (!grow(o, m, n, k + 1)) { free(used); free(r); free(u); return -1; }
+        if (!grow(o, m, n, k + 1)) { free(used); free(r); return -1; }
         double piv = r[jstar];
         double* v = o->V + k * n;
+        double* u = o->U + k * m;
         for (int64_t j = 0; j < n; ++j) v[j] = r[j] / piv;
-        for (int64_t i = 0; i < m; ++i) {
-            double s = E(ctx, i, jstar);
-            for (int64_t p = 0; p < k; ++p) s -= o->U[p * m + i] * o->V[p * n + jstar];
-            u[i] = s;
-        }
+        for (int64_t i = 0; i < m; ++i) u[i] = resid(E, ctx, o, m, n, k, i, jstar);
         double nu2 = 0.0, nv2 = 0.0;
         for (int64_t i = 0; i < m; ++i) nu2 += u[i] * u[i];
         for (int64_t j = 0; j < n; ++j) nv2 += v[j] * v[j];
@@ -567,22 +622,25 @@ static int aca_core(entry_fn E, const void* ctx, int64_t m, int64_t n, double to
             cross += du * dv;
         }
         double S2new = S2 + 2.0 * cross + nu2 * nv2;
-        /* the new term is negligible against the approximation it would
-         * join: stop without adding it */
-        if (k > 0 && sqrt(nu2 * nv2) <= tol * sqrt(S2new)) break;
+        int64_t next = -1;
+        /* a small candidate term: stop without it if the samples of the
+         * residual confirm the tolerance, else keep it and go on */
+        if (k > 0 && sqrt(nu2 * nv2) <= tol * sqrt(S2new) &&
+            aca_confirm(E, ctx, o, m, n, k, tol, S2, nchecks++, used, &next))
+            break;
         S2 = S2new;
-        memcpy(o->U + k * m, u, sizeof(double) * m);
         o->piv_r[k] = istar;
         o->piv_c[k] = jstar;
         ++k;
         if (nused == m) break;
-        /* next pivot row: largest |u_i| among rows not tried yet */
-        int64_t best = -1;
-        for (int64_t i = 0; i < m; ++i)
-            if (!used[i] && (best < 0 || fabs(u[i]) > fabs(u[best]))) best = i;
-        istar = best;
+        if (next < 0) {
+            /* next pivot row: largest |u_i| among rows not tried yet */
+            for (int64_t i = 0; i < m; ++i)
+                if (!used[i] && (next < 0 || fabs(u[i]) > fabs(u[next]))) next = i;
+        }
+        istar = next;
     }
-    free(used); free(r); free(u);
+    free(used); free(r);
     return (int)k;
 }
 

@@ -134,7 +134,7 @@ def test_adaptive_matvec_within_tolerance(orc, kern, tol):
     b = o.matvec(ko, q)
     bd = orc.direct(P, ko, q)
     err = np.linalg.norm(b - bd) / np.linalg.norm(bd)
-    assert err <= 5 * tol
+    assert err <= tol
 
 
 def test_adaptive_fewer_near_pairs_than_balanced_depth(orc):

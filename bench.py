@@ -469,10 +469,22 @@ def rel_err_rows(y, ref, rows):
     return float(np.linalg.norm(y[rows] - ref) / np.linalg.norm(ref))
 
 
-def cpu_baseline(w, pts, q, level_rule, sample_rows_budget_s=30.0):
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(w, pts, q, level_rule, budget_s=30.0, reps=5):
     """The oracle timed on the host: its matvec over the target rows of one
     level-1 box (all levels' blocks of those rows), after compressing exactly
-    the blocks those rows need."""
+    the blocks those rows need; median of up to `reps` runs within a budget,
+    on all host threads and on one."""
     import oracle
     oracle.build(force=False)
     k = oracle.kernel(w.kernel, diag=w.diag)
@@ -482,26 +494,65 @@ def cpu_baseline(w, pts, q, level_rule, sample_rows_budget_s=30.0):
     r0, r1 = int(start[0]), int(start[1])
     o.compress(k, w.tol, rows=(r0, r1))
     t_setup = time.perf_counter() - t0
-    times = []
-    b = None
-    for _ in range(3):
-        t1 = time.perf_counter()
-        b = o.matvec(k, q, rows=(r0, r1))
-        times.append(time.perf_counter() - t1)
-        if sum(times) > sample_rows_budget_s:
-            break
-    tm = float(np.median(times))
+    all_threads = oracle.num_threads()
+
+    def timed(threads):
+        oracle.set_threads(threads)
+        times, b = [], None
+        for _ in range(reps):
+            t1 = time.perf_counter()
+            b = o.matvec(k, q, rows=(r0, r1))
+            times.append(time.perf_counter() - t1)
+            if sum(times) > budget_s:
+                break
+        return float(np.median(times)), len(times), b
+
+    tm, nrep, b = timed(all_threads)
+    t1c, nrep1, _ = timed(1)
+    oracle.set_threads(all_threads)
     rows = o.perm()[r0:r1]
     return {
         "value": (r1 - r0) * 1 / tm,
         "unit": "N*nrhs/s",
-        "cores": oracle.num_threads(),
+        "cores": all_threads,
         "kind": "oracle",
+        "cpu_model": _cpu_model(),
         "sample": f"oracle matvec (FP64, every ordered block) over the {r1 - r0} target rows of "
-                  f"level-1 box 0 (all levels' blocks of those rows), median of {len(times)}; "
-                  f"setup (tree, lists, ACA of those blocks) {t_setup:.1f} s not timed",
+                  f"level-1 box 0 (all levels' blocks of those rows), median of {nrep} on "
+                  f"{all_threads} threads and of {nrep1} on 1 thread; the oracle's OpenMP loop "
+                  f"runs over the target boxes of each level; setup (tree, lists, ACA of those "
+                  f"blocks) {t_setup:.1f} s not timed",
         "seconds_per_matvec": tm,
+        "value_1_core": (r1 - r0) / t1c,
+        "seconds_per_matvec_1_core": t1c,
+        "parallel_speedup": t1c / tm,
     }, rows, b[rows]
+
+
+def depth_rule_bench(P, torch, w, pts, q, bd, rows, steps, warmup):
+    """The main workload with the max-count depth rule (the smallest level
+    whose fullest box holds at most leaf points) beside the closed form:
+    depth, blocks, dense pairs, bytes, build and FP64 product time, error."""
+    t0 = time.perf_counter()
+    H = P.HODLR(pts, P.make_kernel(w.kernel, h=w.h, diag=w.diag), w.leaf, w.tol,
+                domain=w.domain, level_rule=0)
+    torch.cuda.synchronize()
+    build = time.perf_counter() - t0
+    info = H.info()
+    X = torch.tensor(q, dtype=torch.float64, device="cuda")
+    Y = torch.empty_like(X)
+    wall, per, _, lat = time_matvecs(P, torch, H, X, Y, P.FP64, warmup, steps)
+    y = Y.cpu().numpy()
+    del H
+    return {
+        "rule": "max-count", "kappa": info.kappa,
+        "stored_blocks": int(sum(info.stored_blocks[l] for l in range(1, info.kappa + 1))),
+        "near_pairs": int(info.near_pairs), "factor_bytes": int(factor_bytes(info, 8)),
+        "build_s": round(build, 2), "ms_per_step": wall / steps * 1e3,
+        "value": w.N / (wall / steps), "unit": "N*nrhs/s", "dtype": "f64",
+        "stage_ms": [round(float(v), 4) for v in per.mean(axis=0)],
+        "rel_err": rel_err_rows(y, bd, rows),
+    }
 
 
 def main():

@@ -36,7 +36,7 @@ typedef enum {
     HODLR_ENOMEM = 2,       /* device allocation failed or exceeded mem_budget_bytes */
     HODLR_EDEVICE = 3,      /* a HIP call failed */
     HODLR_EDUPLICATE = 4,   /* two distinct points coincide under a singular kernel */
-    HODLR_ENONFINITE = 5,   /* NaN or Inf in the points */
+    HODLR_ENONFINITE = 5,   /* NaN or Inf in the points, or in a solve's F, guess or residual */
     HODLR_EUNSUPPORTED = 6  /* valid request this build does not handle */
 } hodlr_status;
 
@@ -117,7 +117,8 @@ void hodlr_default_opts(hodlr_opts* opts);
  * and the near lists of the leaves (sec. 5.3, table of notations and the
  * HODLRdD admissibility definition), and the ACA factors of every admissible
  * block (eq. keq1) to relative tolerance tol.
- *   points    host pointer, N x d row-major FP64, user order; copied.
+ *   points    host or device pointer (the copy infers which), N x d
+ *             row-major FP64, user order; copied before the call returns.
  *   N >= 1, 1 <= d <= 8, leaf_size >= 1, 0 <= tol < 1, -1 <= opts->adm_dim <= d-1.
  *   kernel    host pointer; h > 0 for GAUSS and EXP.
  *   opts      host pointer or NULL for the defaults.
@@ -180,6 +181,17 @@ hodlr_status hodlr_matvec_events(hodlr_t h, const void* X, int64_t ldx, int nrhs
  * nrhs < 1 or a bad precision. */
 hodlr_status hodlr_reserve_workspace(hodlr_t h, int nrhs, int compute_prec);
 
+/* Largest byte offset the matrix-core product (BF16 factors, several
+ * right-hand sides; the blocks of Alg. "HODLRdD matrix-vector Product")
+ * forms within one factor of rank `rank` and length `len` or within the x
+ * rows it reads.  Those offsets address buffer resources of a 2^31-byte
+ * range, and a build whose BF16 factors exceed it fails with
+ * HODLR_EUNSUPPORTED; this call exposes the same check.  Host computation
+ * only (no device needed).  Returns OK and *extent, EUNSUPPORTED (with
+ * *extent set) when *extent >= 2^31, EINVAL for negative sizes, nrhs
+ * outside 1..32 or a null extent. */
+hodlr_status hodlr_mfma_extent(int64_t rank, int64_t len, int nrhs, int64_t* extent);
+
 /* Options of hodlr_solve. */
 typedef struct {
     double tol;           /* outer stop: max over columns of |F - A U| / |F| (FP64 operator) */
@@ -212,12 +224,16 @@ void hodlr_default_solve_opts(hodlr_solve_opts* opts);
  *            factors and is applied in FP64 arithmetic.
  *   F, U     device pointers, N x nrhs column-major FP64 in user order,
  *            leading dimensions ldf, ldu >= N; U receives the solution.
+ *            U is read only when opts->use_initial_guess is 1 (any
+ *            contents otherwise).
  *   opts     host pointer or NULL for the defaults; info host pointer (may be NULL).
  *   Allocates a workspace of about (restart + 4) N nrhs doubles for the
  *   call; synchronous on stream.  Calls must not overlap other calls on hi or lo.
  * Errors: EINVAL (arguments, mismatched handles, hi with BF16 factors, factors
- * missing), ENOMEM, EDEVICE.  Not converging is not an error: check
- * info->converged. */
+ * missing), ENONFINITE (NaN or Inf in F, in the initial guess, or in a
+ * residual), ENOMEM, EDEVICE.  Not converging is not an error: check
+ * info->converged.  A column of F that is zero is measured by its absolute
+ * residual. */
 hodlr_status hodlr_solve(hodlr_t hi, hodlr_t lo, double alpha, double beta, const double* F,
                          int64_t ldf, int nrhs, double* U, int64_t ldu,
                          const hodlr_solve_opts* opts, hodlr_solve_info* info, void* stream);
@@ -244,6 +260,9 @@ typedef struct {
     double* Y;                /* device, same shape: the product, or the solution */
     double alpha, beta;       /* solve: (alpha I + beta K~) Y = X */
     double tol;               /* solve: relative residual to reach */
+    void* stream;             /* hipStream_t on which X was produced (NULL: the null
+                               * stream): the request reads X only after the work
+                               * queued there before hodlr_server_submit */
 } hodlr_request;
 
 typedef struct {
@@ -276,8 +295,12 @@ hodlr_status hodlr_server_add_set(hodlr_server_t srv, const double* points, int6
  * products of one set are applied together as one product of their columns.
  * Solves run GMRES with iterative refinement on the set itself (FP64
  * residuals; inner GMRES(30) in FP32 arithmetic, to tol).  X and Y must stay
- * valid until the request completes.  Errors: EINVAL (unknown set, nrhs out
- * of range, solve on BF16 factors, set larger than max_points). */
+ * valid until the request completes.  Ordering: an event is recorded on
+ * req->stream at submission and the request's stream slot waits on it
+ * before reading X, so X may still be in production there; Y is complete
+ * when hodlr_server_wait or a successful hodlr_server_poll returns.
+ * Errors: EINVAL (unknown set, nrhs out of range, solve on BF16 factors, set
+ * larger than max_points), EDEVICE (the event could not be recorded). */
 hodlr_status hodlr_server_submit(hodlr_server_t srv, const hodlr_request* req, int64_t* id);
 
 /* Block until request id completes; returns its status (a solve that misses

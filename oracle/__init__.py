@@ -97,6 +97,8 @@ def lib():
         L.ohodlr_kernel_eval.restype = C.c_double
         L.ohodlr_kernel_block.argtypes = [C.POINTER(_Kernel), _P, _i64, _P, _i64, C.c_int, _P]
         L.ohodlr_num_threads.restype = C.c_int
+        L.ohodlr_set_threads.argtypes = [C.c_int]
+        L.ohodlr_set_threads.restype = None
         _lib = L
     return _lib
 
@@ -112,6 +114,11 @@ def _ptr(a: np.ndarray):
 
 def num_threads() -> int:
     return lib().ohodlr_num_threads()
+
+
+def set_threads(n: int) -> None:
+    """Threads of the oracle's later parallel loops."""
+    lib().ohodlr_set_threads(int(n))
 
 
 def kernel_block(k: _Kernel, X: np.ndarray, Y: np.ndarray) -> np.ndarray:

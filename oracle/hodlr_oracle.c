@@ -66,6 +66,16 @@ int ohodlr_num_threads(void)
 #endif
 }
 
+/* threads of later parallel loops (timing on a given number of cores) */
+void ohodlr_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 /* ------------------------------------------------------------------------- */
 /* Tree (sec. 5.2) and interaction lists (sec. 5.3, table of notations)        */
 /* ------------------------------------------------------------------------- */

@@ -122,6 +122,7 @@ void ohodlr_direct(const double* points, int64_t N, int d, const ork_kernel* k,
                    double* b);
 
 int ohodlr_num_threads(void);
+void ohodlr_set_threads(int n);
 
 #ifdef __cplusplus
 }

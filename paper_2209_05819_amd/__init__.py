@@ -77,7 +77,7 @@ class ServerOpts(C.Structure):
 class Request(C.Structure):
     _fields_ = [("kind", C.c_int), ("set", C.c_int), ("nrhs", C.c_int), ("X", C.c_void_p),
                 ("Y", C.c_void_p), ("alpha", C.c_double), ("beta", C.c_double),
-                ("tol", C.c_double)]
+                ("tol", C.c_double), ("stream", C.c_void_p)]
 
 
 class ServerStats(C.Structure):
@@ -132,6 +132,7 @@ def lib():
         L.hodlr_export_near_level.argtypes = [_P, C.c_int, C.POINTER(_i64), _P, _P]
         L.hodlr_export_box_flags.argtypes = [_P, C.c_int, _P]
         L.hodlr_reserve_workspace.argtypes = [_P, C.c_int, C.c_int]
+        L.hodlr_mfma_extent.argtypes = [_i64, _i64, C.c_int, C.POINTER(_i64)]
         L.hodlr_export_factors.argtypes = [_P, C.c_int, _P, C.POINTER(_i64), C.POINTER(_i64),
                                            _P, _P]
         L.hodlr_import_factors.argtypes = [_P, C.c_int, _P, _P, _P]
@@ -141,6 +142,7 @@ def lib():
                   "hodlr_export_tree",
                   "hodlr_export_boxes", "hodlr_export_il", "hodlr_export_near",
                   "hodlr_export_near_level", "hodlr_export_box_flags", "hodlr_reserve_workspace",
+                  "hodlr_mfma_extent",
                   "hodlr_export_factors", "hodlr_import_factors", "hodlr_solve",
                   "hodlr_server_create", "hodlr_server_add_set", "hodlr_server_submit",
                   "hodlr_server_wait", "hodlr_server_poll", "hodlr_server_get_stats"):
@@ -176,15 +178,36 @@ def _stream_ptr(stream):
     return C.c_void_p(int(stream))
 
 
-def hodlr_build(points: np.ndarray, kernel: Kernel, leaf_size: int, tol: float,
+def hodlr_build(points, kernel: Kernel, leaf_size: int, tol: float,
                 opts: Opts | None = None, stream=None) -> int:
-    P = np.ascontiguousarray(points, dtype=np.float64)
-    N, d = P.shape
+    """points: N x d float64, a host array or a contiguous device tensor."""
+    if _is_device_tensor(points):
+        import torch
+        if points.dtype != torch.float64 or points.dim() != 2 or not points.is_contiguous():
+            raise TypeError("device points must be a contiguous N x d float64 tensor")
+        N, d = points.shape
+        ptr = C.c_void_p(points.data_ptr())
+    else:
+        points = np.ascontiguousarray(points, dtype=np.float64)
+        N, d = points.shape
+        ptr = _np_ptr(points)
     out = C.c_void_p()
-    _check(lib().hodlr_build(_np_ptr(P), N, d, C.byref(kernel), int(leaf_size), float(tol),
+    _check(lib().hodlr_build(ptr, N, d, C.byref(kernel), int(leaf_size), float(tol),
                              C.byref(opts) if opts is not None else None, _stream_ptr(stream),
                              C.byref(out)))
     return out.value
+
+
+def hodlr_mfma_extent(rank: int, length: int, nrhs: int) -> tuple[int, int]:
+    """(status, largest byte offset) of the matrix-core product for one BF16
+    factor; host computation, no device needed."""
+    ext = _i64()
+    st = lib().hodlr_mfma_extent(int(rank), int(length), int(nrhs), C.byref(ext))
+    return st, ext.value
+
+
+def _is_device_tensor(x) -> bool:
+    return type(x).__module__.startswith("torch") and getattr(x, "is_cuda", False)
 
 
 def hodlr_matvec(h: int, X, Y, compute_prec: int = FP64, stream=None) -> None:
@@ -383,7 +406,8 @@ class HODLR:
         o.max_rank = int(max_rank)
         o.skip_aca = 1 if skip_aca else 0
         o.mem_budget_bytes = int(mem_budget_bytes)
-        self.points = np.ascontiguousarray(points, dtype=np.float64)
+        self.points = points if _is_device_tensor(points) else np.ascontiguousarray(
+            points, dtype=np.float64)
         self.N, self.d = self.points.shape
         self.h = hodlr_build(self.points, kernel, leaf_size, tol, o, stream)
 
@@ -453,12 +477,18 @@ class Server:
             raise ValueError("requests take column-major tensors with leading dimension N")
         return X.shape
 
-    def submit(self, kind: int, set_id: int, X, Y, alpha=1.0, beta=1.0, tol=1e-8) -> int:
+    def submit(self, kind: int, set_id: int, X, Y, alpha=1.0, beta=1.0, tol=1e-8,
+               stream=None) -> int:
+        """X is read after the work queued so far on `stream` (default: torch's
+        current stream), where it is taken to be produced."""
         import torch
         if X.dtype != torch.float64 or Y.dtype != torch.float64:
             raise TypeError("requests take float64 tensors")
         _, nrhs = self._shape(X)
-        r = Request(kind, set_id, nrhs, X.data_ptr(), Y.data_ptr(), alpha, beta, tol)
+        if stream is None:
+            stream = torch.cuda.current_stream(X.device)
+        r = Request(kind, set_id, nrhs, X.data_ptr(), Y.data_ptr(), alpha, beta, tol,
+                    _stream_ptr(stream))
         rid = _i64()
         _check(lib().hodlr_server_submit(C.c_void_p(self.s), C.byref(r), C.byref(rid)))
         self._keep[rid.value] = (X, Y)

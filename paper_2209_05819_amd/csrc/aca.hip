@@ -4,13 +4,22 @@
 // whole iteration; larger ones iterate in a global FP64 workspace.  Finished
 // factors are packed into per-chunk arenas in the storage precision.
 //
-// The iteration (the same rule as the reference CPU implementation):
+// The iteration:
 //   row residual of pivot row i*, column pivot j* = largest |entry| (lowest
 //   index on ties); a zero pivot marks the row tried and restarts from the
-//   lowest untried row; otherwise v = row / pivot, u = residual of column j*;
-//   the candidate term u v is dropped and the iteration ends when
-//   |u||v| <= tol * |S|_F with S the approximation including it; the next
-//   pivot row is the untried row with the largest |u_i|.
+//   lowest untried row; otherwise v = row / pivot, u = residual of column j*.
+//   The candidate term u v is small when |u||v| <= tol * |S|_F with S the
+//   approximation including it.  A small term ends the iteration, dropped,
+//   only if sampled residuals of the approximation without it confirm the
+//   tolerance: 16 evenly spaced rows and 16 evenly spaced columns (every one
+//   in a smaller block; the c-th check of a block shifts them by 997c and
+//   991c modulo the spacing), each sum of squares scaled up to an estimate of
+//   |K - S|_F^2, both at most (tol/2)^2 |S|_F^2.  Otherwise the term is kept
+//   and the next pivot row is the untried row holding the largest sampled
+//   residual entry (lowest row on ties).  Without a check the next pivot row
+//   is the untried row with the largest |u_i|.  The per-term stop alone
+//   underestimates the error of large blocks whose residual gathers near a
+//   shared vertex, and the product then misses the tolerance.
 #include <algorithm>
 #include <climits>
 
@@ -25,6 +34,7 @@ namespace {
 
 constexpr int T = 256;
 constexpr int NW = T / 64;
+constexpr int kAcaSamples = 16;   // rows and columns sampled to confirm a stop
 
 struct AcaJob {
     int32_t a0, m, b0, n;
@@ -66,8 +76,9 @@ __global__ __launch_bounds__(T) void k_aca(const double* __restrict__ pts, int64
     extern __shared__ double dyn[];
     __shared__ double red_v[NW], red_w[NW], red_x[NW];
     __shared__ int red_i[NW], red_j[NW];
-    __shared__ int sh_k, sh_istar, sh_nused, sh_done, sh_jstar;
-    __shared__ double sh_S2, sh_piv;
+    __shared__ int sh_k, sh_istar, sh_nused, sh_done, sh_jstar, sh_small, sh_ix, sh_next,
+        sh_checks;
+    __shared__ double sh_S2, sh_piv, sh_S2new;
 
     const AcaJob J = jobs[blockIdx.x];
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
@@ -97,6 +108,7 @@ __global__ __launch_bounds__(T) void k_aca(const double* __restrict__ pts, int64
         sh_istar = 0;
         sh_nused = 0;
         sh_done = 0;
+        sh_checks = 0;
         sh_S2 = 0.0;
     }
     __syncthreads();
@@ -249,20 +261,97 @@ __global__ __launch_bounds__(T) void k_aca(const double* __restrict__ pts, int64
             double cross = 0.0;
             for (int p = 0; p < k; ++p) cross += s_a[p];
             const double S2new = sh_S2 + 2.0 * cross + tnu * tnv;
-            if (k > 0 && sqrt(tnu * tnv) <= tol * sqrt(S2new)) {
-                sh_done = 1;
-            } else {
-                sh_S2 = S2new;
-                sh_k = k + 1;
-                // the accepted term's pivots: row istar of A, column jstar of B
-                pivots[J.pv + 2 * k] = istar;
-                pivots[J.pv + 2 * k + 1] = jstar;
-                // ix is out of range only if every untried |u_i| is non-finite
-                if (sh_nused == m || ix < 0 || ix >= m)
-                    sh_done = 1;
+            sh_S2new = S2new;
+            sh_ix = ix;
+            sh_next = -1;
+            sh_small = (k > 0 && sqrt(tnu * tnv) <= tol * sqrt(S2new)) ? 1 : 0;
+        }
+        __syncthreads();
+        if (sh_small) {
+            // residual of the k-term approximation on sampled rows and columns
+            const int sr = min(m, kAcaSamples), str = m / sr;
+            const int sc = min(n, kAcaSamples), stc = n / sc;
+            const int c = sh_checks;
+            const int offr = (int)(((int64_t)c * 997) % str);
+            const int offc = (int)(((int64_t)c * 991) % stc);
+            const int64_t nrow = (int64_t)sr * n, total = nrow + (int64_t)sc * m;
+            double er = 0.0, ec = 0.0, bs = 0.0;
+            int bsi = INT_MAX;
+            for (int64_t t = tid; t < total; t += T) {
+                int i, j;
+                const bool row = t < nrow;
+                if (row) {
+                    const int q = (int)(t / n);
+                    j = (int)(t - (int64_t)q * n);
+                    i = q * str + offr;
+                } else {
+                    const int64_t t2 = t - nrow;
+                    const int q = (int)(t2 / m);
+                    i = (int)(t2 - (int64_t)q * m);
+                    j = q * stc + offc;
+                }
+                double r2 = 0.0;
+                for (int a = 0; a < d; ++a) {
+                    double dx = X[a * N + i] - Y[a * N + j];
+                    r2 += dx * dx;
+                }
+                double v = kfun(kp, r2);
+                for (int p = 0; p < k; ++p) v -= U[(int64_t)p * m + i] * V[(int64_t)p * n + j];
+                if (row)
+                    er += v * v;
                 else
-                    sh_istar = ix;
+                    ec += v * v;
+                const double av = fabs(v);
+                if (!used[i] && av > 0.0 && (av > bs || (av == bs && i < bsi))) {
+                    bs = av;
+                    bsi = i;
+                }
             }
+            er = wave_sum(er);
+            ec = wave_sum(ec);
+            wave_argmax(bs, bsi);
+            if (lane == 0) {
+                red_v[wv] = er;
+                red_w[wv] = ec;
+                red_x[wv] = bs;
+                red_i[wv] = bsi;
+            }
+            __syncthreads();
+            if (tid == 0) {
+                double ter = 0.0, tec = 0.0, b = red_x[0];
+                int bi = red_i[0];
+                for (int w = 0; w < NW; ++w) {
+                    ter += red_v[w];
+                    tec += red_w[w];
+                }
+                for (int w = 1; w < NW; ++w)
+                    if (red_x[w] > b || (red_x[w] == b && red_i[w] < bi)) {
+                        b = red_x[w];
+                        bi = red_i[w];
+                    }
+                ter *= (double)m / (double)sr;
+                tec *= (double)n / (double)sc;
+                const double lim = 0.25 * tol * tol * sh_S2;
+                sh_checks = c + 1;
+                if (ter <= lim && tec <= lim)
+                    sh_done = 1;
+                else if (b > 0.0 && bi >= 0 && bi < m)
+                    sh_next = bi;
+            }
+            __syncthreads();
+        }
+        if (tid == 0 && !sh_done) {
+            sh_S2 = sh_S2new;
+            sh_k = k + 1;
+            // the accepted term's pivots: row istar of A, column jstar of B
+            pivots[J.pv + 2 * k] = istar;
+            pivots[J.pv + 2 * k + 1] = jstar;
+            const int ix = sh_next >= 0 ? sh_next : sh_ix;
+            // ix is out of range only if every untried |u_i| is non-finite
+            if (sh_nused == m || ix < 0 || ix >= m)
+                sh_done = 1;
+            else
+                sh_istar = ix;
         }
         __syncthreads();
         if (sh_done) break;

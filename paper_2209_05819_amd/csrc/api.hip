@@ -198,6 +198,16 @@ hodlr_status hodlr_reserve_workspace(hodlr_t h, int nrhs, int compute_prec) {
     return guarded([&] { hodlr::reserve_workspace(h, nrhs, compute_prec, nullptr); });
 }
 
+hodlr_status hodlr_mfma_extent(int64_t rank, int64_t len, int nrhs, int64_t* extent) {
+    if (rank < 0 || len < 0 || nrhs < 1 || nrhs > 32 || !extent)
+        return set_error(HODLR_EINVAL, "rank, len >= 0, 1 <= nrhs <= 32, extent non-null");
+    const int nrp = nrhs <= 16 ? 16 : 32;
+    *extent = hodlr::mcore_extent(rank, len, nrp);
+    if (*extent >= hodlr::kMcoreRange)
+        return set_error(HODLR_EUNSUPPORTED, "factor exceeds the matrix-core buffer range");
+    return HODLR_OK;
+}
+
 hodlr_status hodlr_matvec(hodlr_t h, const void* X, int64_t ldx, int nrhs, int x_prec, void* Y,
                           int64_t ldy, int compute_prec, void* stream) {
     return matvec_checked(h, X, ldx, nrhs, x_prec, Y, ldy, compute_prec, stream, nullptr, 0);

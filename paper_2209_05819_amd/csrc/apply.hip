@@ -1544,6 +1544,20 @@ __global__ __launch_bounds__(256) void k_near_mfma(
 
 }  // namespace
 
+// Factor words: the projection pass reads terms up to r16(r) + 15 (the
+// prefetch after the last chunk) and columns up to len + 512 (the last wave
+// of a 512-column panel); the expansion pass terms up to r16(r) + 15 and
+// rows up to len + 512 (a tile of four 128-row waves); both read 16-byte
+// words.  x rows (projection pass) up to len + 576 of the slice, nrp BF16
+// each.  The bounds use len + 1024 and one term chunk more.
+int64_t mcore_extent(int64_t r, int64_t len, int nrp) {
+    const int64_t ld = fstride<bf16>(len);
+    const int64_t terms = ((r + 15) & ~(int64_t)15) + 32;
+    const int64_t f = 2 * (terms * ld + len + 1024) + 16;
+    const int64_t x = 2 * (len + 1024) * (int64_t)nrp + 16;
+    return std::max(f, x);
+}
+
 // Launch planning (host): which blocks one wave applies, how the others are
 // split, where every block writes its contributions, and the per-level tables
 // the gather needs.  Integer bookkeeping only.
@@ -1761,6 +1775,18 @@ void plan_apply(hodlr_t h) {
                 pt += np * r16(r);
             }
         };
+        // every offset the passes form must stay below 2^31 (see mcore_extent)
+        for (int64_t b = 0; b < h->nblocks; ++b) {
+            const BlockDesc& bd = h->hblocks[b];
+            if (bd.rank <= 0) continue;
+            if (mcore_extent(bd.rank, bd.m, 32) >= kMcoreRange ||
+                mcore_extent(bd.rank, bd.n, 32) >= kMcoreRange)
+                fail(HODLR_EUNSUPPORTED,
+                     "a BF16 factor is too large for the matrix-core product's 2^31-byte "
+                     "buffer range (rank " + std::to_string(bd.rank) + ", sides " +
+                         std::to_string(bd.m) + " x " + std::to_string(bd.n) +
+                         "); use FP32 or FP64 storage, or set max_rank");
+        }
         for (int64_t b = 0; b < h->nblocks; ++b) {
             const BlockDesc& bd = h->hblocks[b];
             if (bd.rank <= 0) continue;

@@ -358,6 +358,15 @@ void build_block_table(hodlr_t h, hipStream_t s);
 void compress_all(hodlr_t h, hipStream_t s);
 // apply.hip
 void plan_apply(hodlr_t h);
+
+// Largest byte offset, relative to a buffer resource's base, that the
+// matrix-core passes form for a BF16 factor of rank r and length len (up to
+// nrp <= 32 right-hand sides).  Their buffer loads move a lane with nothing
+// to read past the resource's range by adding 2^31 to its offset, so every
+// offset must stay below kMcoreRange for that sum to land past the range
+// instead of wrapping to a real address.
+constexpr int64_t kMcoreRange = (int64_t)1 << 31;
+int64_t mcore_extent(int64_t r, int64_t len, int nrp);
 // ev: nullptr or nev = 5 or 5 + kApplyClasses events: [0] before the
 // product, [1] after permute-in, [2] after all block projections (one-pass
 // blocks and split projections), [3] after the split expansions, [4] after

@@ -37,6 +37,7 @@ double us_between(clk::time_point a, clk::time_point b) {
 struct Req {
     int64_t id = 0;
     hodlr_request r{};
+    hipEvent_t ready = nullptr;   // recorded on the request's stream at submission
     int state = 0;   // 0 queued, 1 running, 2 done
     hodlr_status st = HODLR_OK;
     std::string msg;
@@ -119,6 +120,8 @@ void launch_products(hodlr_server_s* S, Slot& sl) {
     }
     const int prec = h->opts.storage == HODLR_FP64 ? HODLR_FP64 : HODLR_FP32;
     try {
+        // X is read only after the work queued before submission on its stream
+        for (Req* q : sl.reqs) HIP_CHECK(hipStreamWaitEvent(sl.s, q->ready, 0));
         for (size_t k = 0; k < sl.reqs.size(); ++k)
             HIP_CHECK(hipMemcpyAsync(sl.xb + (size_t)sl.col0[k] * N, sl.reqs[k]->r.X,
                                      sizeof(double) * N * sl.reqs[k]->r.nrhs,
@@ -155,6 +158,7 @@ void launch_solve(hodlr_server_s* S, Slot& sl) {
             so.max_outer = 40;
             so.lo_compute = HODLR_FP32;
             hodlr_solve_info info{};
+            HIP_CHECK(hipStreamWaitEvent(sl.s, q->ready, 0));
             solve(h, h, q->r.alpha, q->r.beta, q->r.X, h->N, q->r.nrhs, q->r.Y, h->N, so, &info,
                   sl.s);
             if (!info.converged) {
@@ -329,6 +333,7 @@ void server_destroy(hodlr_server_t S) {
         (void)hipStreamDestroy(sl->s);
     }
     for (auto& st : S->sets) hodlr_destroy(st.h);
+    for (auto& kv : S->reqs) (void)hipEventDestroy(kv.second->ready);
     delete S;
 }
 
@@ -367,6 +372,13 @@ hodlr_status server_submit(hodlr_server_t S, const hodlr_request& r, int64_t* id
         return HODLR_EINVAL;
     }
     auto q = std::make_unique<Req>();
+    if (hipEventCreateWithFlags(&q->ready, hipEventDisableTiming) != hipSuccess ||
+        hipEventRecord(q->ready, (hipStream_t)r.stream) != hipSuccess) {
+        (void)hipGetLastError();
+        if (q->ready) (void)hipEventDestroy(q->ready);
+        err = "could not record the request's stream";
+        return HODLR_EDEVICE;
+    }
     q->id = S->next_id++;
     q->r = r;
     q->t_submit = clk::now();
@@ -394,6 +406,7 @@ hodlr_status server_wait(hodlr_server_t S, int64_t id, int block, int* done, dou
     if (run_us) *run_us = us_between(q->t_start, q->t_done);
     const hodlr_status st = q->st;
     err = q->msg;
+    (void)hipEventDestroy(q->ready);
     S->reqs.erase(it);   // a finished request is reported once
     return st;
 }

@@ -93,6 +93,16 @@ __global__ void k_residual(const double* __restrict__ F, int64_t ldf, const doub
     R[t] = F[c * ldf + n] - alpha * U[c * ldu + n] - beta * KU[t];
 }
 
+// R = F (R packed N x nrhs); reads nothing but F
+__global__ void k_copy_cols(const double* __restrict__ F, int64_t ldf, double* __restrict__ R,
+                            int64_t N, int nrhs) {
+    const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (t >= N * nrhs) return;
+    const int c = (int)(t / N);
+    const int64_t n = t - (int64_t)c * N;
+    R[t] = F[c * ldf + n];
+}
+
 // U[c] += D[c]; or U[c] = 0 when D is null
 __global__ void k_update(double* __restrict__ U, int64_t ldu, const double* __restrict__ D,
                          int64_t N, int nrhs) {
@@ -185,10 +195,13 @@ void solve(hodlr_t hi, hodlr_t lo, double alpha, double beta, const double* F, i
 
     std::vector<double> fn;
     {
-        // ||F|| per column: copy F into R (packed) first
-        k_residual<<<g, TB, 0, s>>>(F, ldf, U, ldu, R, 0.0, 0.0, R, N, nrhs);
+        // ||F|| per column: copy F into R (packed) first; U and R may hold
+        // anything (the caller's output buffer, fresh memory)
+        k_copy_cols<<<g, TB, 0, s>>>(F, ldf, R, N, nrhs);
         HIP_CHECK(hipGetLastError());
         norms(R, fn);
+        for (int c = 0; c < nrhs; ++c)
+            if (!std::isfinite(fn[c])) fail(HODLR_ENONFINITE, "F holds NaN or Inf");
     }
     if (!o.use_initial_guess) k_update<<<g, TB, 0, s>>>(U, ldu, nullptr, N, nrhs);
     HIP_CHECK(hipGetLastError());
@@ -201,7 +214,7 @@ void solve(hodlr_t hi, hodlr_t lo, double alpha, double beta, const double* F, i
     for (int outer = 0;; ++outer) {
         // r = F - A_hi u
         if (outer == 0 && !o.use_initial_guess) {
-            k_residual<<<g, TB, 0, s>>>(F, ldf, U, ldu, R, 0.0, 0.0, R, N, nrhs);
+            k_copy_cols<<<g, TB, 0, s>>>(F, ldf, R, N, nrhs);
         } else {
             matvec(hi, U, ldu, nrhs, HODLR_FP64, KU, N, hi_prec, nullptr, 0, s);
             k_residual<<<g, TB, 0, s>>>(F, ldf, U, ldu, KU, alpha, beta, R, N, nrhs);
@@ -209,7 +222,14 @@ void solve(hodlr_t hi, hodlr_t lo, double alpha, double beta, const double* F, i
         HIP_CHECK(hipGetLastError());
         norms(R, rn);
         double rel = 0.0;
-        for (int c = 0; c < nrhs; ++c) rel = std::max(rel, fn[c] > 0 ? rn[c] / fn[c] : 0.0);
+        for (int c = 0; c < nrhs; ++c) {
+            if (!std::isfinite(rn[c]))
+                fail(HODLR_ENONFINITE, o.use_initial_guess && outer == 0
+                                           ? "the initial guess U holds NaN or Inf"
+                                           : "the residual became NaN or Inf");
+            // a zero right-hand side: the absolute residual
+            rel = std::max(rel, fn[c] > 0 ? rn[c] / fn[c] : rn[c]);
+        }
         if (outer < 64) info->history[outer] = rel;
         info->rel_residual = rel;
         info->outer_iters = outer;

@@ -157,7 +157,7 @@ __global__ void k_max_count(const int32_t* __restrict__ start, int64_t nb, int* 
 
 }  // namespace
 
-void build_tree(hodlr_t h, const double* points_host, hipStream_t s) {
+void build_tree(hodlr_t h, const double* points_in, hipStream_t s) {
     const int64_t N = h->N;
     const int d = h->d;
     const int L = std::min(63 / d, 30);
@@ -166,7 +166,7 @@ void build_tree(hodlr_t h, const double* points_host, hipStream_t s) {
     double* P = (double*)dalloc(h, sizeof(double) * N * d);
     double* lo_side = (double*)dalloc(h, sizeof(double) * 16);
     int* flags = (int*)dalloc(h, sizeof(int) * 4);
-    HIP_CHECK(hipMemcpyAsync(P, points_host, sizeof(double) * N * d, hipMemcpyHostToDevice, s));
+    HIP_CHECK(hipMemcpyAsync(P, points_in, sizeof(double) * N * d, hipMemcpyDefault, s));
     HIP_CHECK(hipMemsetAsync(flags, 0, sizeof(int) * 4, s));
     double ls_host[16] = {0};
     if (h->opts.has_domain) {

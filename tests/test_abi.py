@@ -42,7 +42,7 @@ def test_struct_layouts_match_header():
     assert C.sizeof(P.SolveOpts) == 8 * 2 + 4 * 4
     assert C.sizeof(P.SolveInfo) == 4 * 3 + 4 + 8 + 8 * 64
     assert C.sizeof(P.ServerOpts) == 8 + 4 + 4 + 8
-    assert C.sizeof(P.Request) == 4 * 3 + 4 + 8 * 2 + 8 * 3
+    assert C.sizeof(P.Request) == 4 * 3 + 4 + 8 * 2 + 8 * 3 + 8
     assert C.sizeof(P.ServerStats) == 8 * 6 + 8 * 2 + 4 + 4
 
 
@@ -78,3 +78,51 @@ def test_product_path_fails_loudly_without_library(tmp_path, monkeypatch):
     monkeypatch.setattr(P, "_lib", None)
     with pytest.raises(RuntimeError, match="not built"):
         P.lib()
+
+
+def test_mfma_extent_guard_without_gpu():
+    """The matrix-core passes address BF16 factors through buffer resources of a
+    2^31-byte range and move idle lanes past it by adding 2^31 to their
+    offset; the host check must reject every factor whose offsets could reach
+    2^31 (so that sum cannot wrap to a real address) and accept the rest."""
+    import paper_2209_05819_amd as P
+    if not os.path.exists(P.LIB_PATH):
+        pytest.skip("library not built")
+    lim = 1 << 31
+
+    def ld(n):
+        return (n + 7) // 8 * 8
+
+    rng = __import__("numpy").random.default_rng(7)
+    # synthetic factor tables: ranks up to the compressor's limit, lengths up
+    # to a level-1 box of N = 2^26
+    ranks = rng.integers(0, 1025, 400)
+    lens = (2.0 ** rng.uniform(3, 25, 400)).astype(int)
+    for r, n in zip(ranks.tolist(), lens.tolist()):
+        for nrhs in (1, 16, 17, 32):
+            st, ext = P.hodlr_mfma_extent(r, n, nrhs)
+            # at least the factor's own last byte and the last x row's bytes
+            assert ext >= 2 * r * ld(n) and ext >= 2 * n * (16 if nrhs <= 16 else 32)
+            assert (st == 0) == (ext < lim)
+            assert st in (0, 6)
+    # monotone in the rank and the length, so one boundary per length
+    for n in (4096, 1 << 20, (1 << 20) + 3):
+        prev = 0
+        flips = 0
+        last_ok = True
+        for r in range(0, 1100, 7):
+            st, ext = P.hodlr_mfma_extent(r, n, 32)
+            assert ext >= prev
+            prev = ext
+            if (st == 0) != last_ok:
+                flips += 1
+                last_ok = st == 0
+        assert flips <= 1
+    # the workloads' factors are far inside the range; a rank-1024 factor of
+    # 2^20 rows is not
+    assert P.hodlr_mfma_extent(1024, 65536, 32)[0] == 0
+    assert P.hodlr_mfma_extent(1024, 1 << 20, 32)[0] == 6
+    # an x slice of 2^25 rows with 32 right-hand sides alone exceeds it
+    assert P.hodlr_mfma_extent(0, 1 << 25, 32)[0] == 6
+    assert P.hodlr_mfma_extent(-1, 10, 1)[0] == 1
+    assert P.hodlr_mfma_extent(1, 10, 33)[0] == 1

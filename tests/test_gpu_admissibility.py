@@ -89,14 +89,8 @@ def test_pipeline_for_every_admissibility(P, orc, d, N, leaf, kern, adm, tol):
     bd = orc.direct(pts, ko, q, rows=rows)
     bg = _gpu_matvec(P, H, q)[rows]
     err = _rel(bg, bd)
-    # the oracle's own ACA on the same lists: ACA's stopping estimate is
-    # looser on blocks whose singular values decay slowly (adjacent boxes
-    # sharing an edge or a face), so the bar is the method's own accuracy
-    o = orc.OracleHODLR(pts, leaf, 1, adm_dim=adm)
-    o.compress(ko, tol)
-    err_or = _rel(o.matvec(ko, q)[rows], bd)
-    _say(f"  rel err {err:.2e} (oracle {err_or:.2e})")
-    assert err <= max(5 * tol, 3 * err_or)
+    _say(f"  rel err {err:.2e}")
+    assert err <= tol
 
 
 def test_admissibility_out_of_range(P):

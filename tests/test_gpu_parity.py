@@ -200,12 +200,13 @@ def test_full_pipeline_against_direct_sum(P, orc, d, N, leaf, kern, h, diag, tol
     bg = _gpu_matvec(P, H, q)
     err = _rel(bg, bd)
     _say(f"  rel err vs direct {err:.3e}")
-    assert err <= 5 * tol
+    assert err <= tol
     # ranks against the oracle's ACA on the same blocks
     o = orc.OracleHODLR(pts, leaf, rule, domain=domain)
     o.compress(ko, tol)
     bo = o.matvec(ko, q)
-    assert _rel(bg, bo) <= 10 * tol
+    # both within tol of the direct sum
+    assert _rel(bg, bo) <= 2 * tol
     # ranks of the stored blocks (A < B in symmetric mode: the transposed
     # entries reuse them) against the oracle's ACA of the same blocks
     info = H.info()
@@ -244,6 +245,21 @@ def test_multi_rhs_columns_match_single(P):
     for c in (0, 7, 12):
         b1 = _gpu_matvec(P, H, np.ascontiguousarray(q[:, c]))
         assert np.max(np.abs(bm[:, c] - b1)) <= 1e-13 * np.max(np.abs(b1))
+
+
+def test_device_points_build_the_same_handle(P):
+    """Points passed as a device pointer give the same tree, ranks and product
+    as the same points passed from the host."""
+    import torch
+    _say("[device points]")
+    pts = W.uniform_points(9000, 3, 21)
+    Hh = _build(P, pts, P.make_kernel("inv_r"), 64, 1e-8)
+    Hd = _build(P, torch.tensor(pts, device="cuda"), P.make_kernel("inv_r"), 64, 1e-8)
+    perm_h, keys_h = P.hodlr_export_tree(Hh.h, 9000)
+    perm_d, keys_d = P.hodlr_export_tree(Hd.h, 9000)
+    assert np.array_equal(perm_h, perm_d) and np.array_equal(keys_h, keys_d)
+    q = W.rhs_normal(9000, 1, 22)[:, 0]
+    assert np.array_equal(_gpu_matvec(P, Hh, q), _gpu_matvec(P, Hd, q))
 
 
 def test_deterministic_repeat(P):

@@ -119,6 +119,85 @@ def test_products_match_a_standalone_handle(P):
     srv.close()
 
 
+def test_served_results_against_the_oracle(P, orc):
+    """Every request of a concurrent mix, checked against the oracle's direct
+    sum on every row: a product within the accuracy its set was built for
+    (the ACA tolerance for FP64 factors, 1e-5 for FP32 factors); a solve of
+    (I + K~/N) u = f to 1e-8 through the direct-sum residual |f - (u + K u/N)|,
+    which may exceed 1e-8 by at most the product's own error on u."""
+    import torch
+    srv = P.Server(max_concurrent=4, max_batch_cols=32, max_points=20000)
+    specs = [
+        (W.uniform_points(12000, 3, 61), "inv_r", 1.0, 0.0, 1e-8, P.FP64),
+        (W.uniform_points(8000, 2, 62), "log", 1.0, 0.0, 1e-8, P.FP32),
+        (W.gaussian_mixture(10000, 3, 63), "gauss", 0.5, 1.001, 1e-8, P.FP64),
+        (W.uniform_points(5000, 2, 64), "gauss", 0.5, 1.0, 1e-8, P.FP32),
+    ]
+    ids, Ns = [], []
+    for pts, kern, h, diag, tol, st in specs:
+        ids.append(srv.add_set(pts, P.make_kernel(kern, h=h, diag=diag), 64, tol, storage=st))
+        Ns.append(pts.shape[0])
+    reqs = _requests(P, Ns, 32, 17)
+    X = [_tensor(torch, Ns[s], n, 300 + i) for i, (_, s, n) in enumerate(reqs)]
+    Y = [torch.zeros_like(x) for x in X]
+    kw = lambda kind, s: dict(alpha=1.0, beta=1.0 / Ns[s], tol=1e-8) if kind == P.REQ_SOLVE else {}
+    rids = [srv.submit(kind, ids[s], X[i], Y[i], **kw(kind, s))
+            for i, (kind, s, n) in enumerate(reqs)]
+    for r in rids:
+        srv.wait(r)
+    torch.cuda.synchronize()
+    st = srv.stats()
+    _say(f"[serve/oracle] {len(reqs)} requests, {st.launches} launches, "
+         f"most concurrent {st.max_concurrent}")
+    worst = {}
+    for i, (kind, s, n) in enumerate(reqs):
+        pts, kern, h, diag, tol, sto = specs[s]
+        ko = orc.kernel(kern, h=h, diag=diag)
+        x = X[i].cpu().numpy().reshape(Ns[s], -1)
+        y = Y[i].cpu().numpy().reshape(Ns[s], -1)
+        e_set = tol if sto == P.FP64 else 1e-5
+        if kind == P.REQ_MATVEC:
+            bd = orc.direct(pts, ko, x)
+            err = np.linalg.norm(y - bd) / np.linalg.norm(bd)
+            assert err <= e_set, (i, s, n, err)
+        else:
+            ku = orc.direct(pts, ko, y) / Ns[s]
+            res = np.linalg.norm(x - (y + ku), axis=0) / np.linalg.norm(x, axis=0)
+            bound = 1e-8 + e_set * np.linalg.norm(ku, axis=0) / np.linalg.norm(x, axis=0)
+            err = float(np.max(res / bound))
+            assert np.all(res <= bound), (i, s, n, res, bound)
+        worst[(kind, s)] = max(worst.get((kind, s), 0.0), float(err))
+    _say("  worst per (kind, set): " + ", ".join(f"{k}: {v:.2e}" for k, v in sorted(worst.items())))
+    assert st.failed == 0
+    srv.close()
+
+
+def test_request_reads_x_after_its_stream(P):
+    """X produced on a side stream right before submission (behind a spin of
+    about 20 ms): the request must read the finished X."""
+    import torch
+    pts = W.uniform_points(9000, 3, 71)
+    k = P.make_kernel("inv_r")
+    srv = P.Server(max_concurrent=2, max_batch_cols=16, max_points=10000)
+    sid = srv.add_set(pts, k, 64, 1e-8)
+    H = P.HODLR(pts, k, 64, 1e-8)
+    X0 = _tensor(torch, 9000, 3, 5)
+    Y = torch.zeros_like(X0)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        X = torch.zeros_like(X0)
+        torch.cuda._sleep(50_000_000)
+        X.copy_(X0)
+        rid = srv.submit(P.REQ_MATVEC, sid, X, Y)
+    srv.wait(rid)
+    Yh = H.matvec(X0)
+    torch.cuda.synchronize()
+    assert float(Yh.abs().max()) > 0
+    assert torch.allclose(Y, Yh, rtol=0, atol=1e-12 * float(Yh.abs().max()))
+    srv.close()
+
+
 def test_server_errors(P):
     import torch
     srv = P.Server(max_concurrent=1, max_batch_cols=4, max_points=4000)

@@ -147,3 +147,35 @@ def test_solve_argument_errors(P, orc):
     few.restart = 2
     info = P.hodlr_solve(H64.h, H32.h, 1.0, 1e-4, F, U, few)
     assert info.converged == 0 and info.outer_iters == 1
+
+
+def test_solve_ignores_output_contents_and_rejects_nonfinite(P, orc):
+    """U is an output: NaN in it before the call must not matter (the solution
+    still equals the dense LU solution); NaN in F, or in U when it is the
+    initial guess, is an error instead of a reported convergence."""
+    import torch
+    pts = W.uniform_points(600, 2, 9)
+    o, ko, (H,) = _handles(P, orc, pts, "gauss", 0.5, 1.0, 40, 1e-15, [P.FP64])
+    f = W.rhs_normal(600, 1, 10)[:, 0]
+    K = orc.kernel_block(ko, pts, pts)
+    np.fill_diagonal(K, 1.0)
+    u_ref = np.linalg.solve(np.eye(600) + K / 600, f)
+    opts = P.default_solve_opts()
+    opts.tol = 1e-13
+    opts.inner_tol = 1e-10
+    opts.lo_compute = P.FP64
+    U = torch.full((600,), float("nan"), dtype=torch.float64, device="cuda")
+    info = P.hodlr_solve(H.h, H.h, 1.0, 1.0 / 600, _dev(f), U, opts)
+    u = _host(U)
+    err = np.linalg.norm(u - u_ref) / np.linalg.norm(u_ref)
+    _say(f"[solve] NaN-filled output: err {err:.2e} converged {info.converged}")
+    assert info.converged == 1 and err <= 1e-11
+    fbad = f.copy()
+    fbad[17] = np.nan
+    with pytest.raises(RuntimeError, match="ENONFINITE"):
+        P.hodlr_solve(H.h, H.h, 1.0, 1.0 / 600, _dev(fbad), torch.zeros_like(U), opts)
+    guess = P.default_solve_opts()
+    guess.use_initial_guess = 1
+    U.fill_(float("nan"))
+    with pytest.raises(RuntimeError, match="ENONFINITE"):
+        P.hodlr_solve(H.h, H.h, 1.0, 1.0 / 600, _dev(f), U, guess)

@@ -172,9 +172,13 @@ def make_kernel(kind, h: float = 1.0, scale: float = 1.0, diag: float = 0.0) -> 
 
 
 def _stream_ptr(stream):
+    """A hipStream_t from None (torch's current stream), a torch stream or an
+    integer handle."""
     if stream is None:
         import torch
         return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if hasattr(stream, "cuda_stream"):
+        return C.c_void_p(stream.cuda_stream)
     return C.c_void_p(int(stream))
 
 
@@ -488,7 +492,7 @@ class Server:
         if stream is None:
             stream = torch.cuda.current_stream(X.device)
         r = Request(kind, set_id, nrhs, X.data_ptr(), Y.data_ptr(), alpha, beta, tol,
-                    _stream_ptr(stream))
+                    _stream_ptr(stream).value)
         rid = _i64()
         _check(lib().hodlr_server_submit(C.c_void_p(self.s), C.byref(r), C.byref(rid)))
         self._keep[rid.value] = (X, Y)

@@ -20,11 +20,14 @@
 //   is the untried row with the largest |u_i|.  The per-term stop alone
 //   underestimates the error of large blocks whose residual gathers near a
 //   shared vertex, and the product then misses the tolerance.
+#include <hip/hip_cooperative_groups.h>
+
 #include <algorithm>
 #include <climits>
 
 #include <cstdio>
 #include <cstdlib>
+#include <mutex>
 
 #include "hodlr_impl.hpp"
 
@@ -371,6 +374,408 @@ __global__ __launch_bounds__(T) void k_aca(const double* __restrict__ pts, int64
     }
 }
 
+// ---------------------------------------------------------------------------
+// The same iteration for the few largest blocks, each spread over `wpb`
+// workgroups of one cooperative launch (all workgroups resident at once).
+// Workgroup wl of a block owns rows [wl m / wpb, (wl + 1) m / wpb) of U and the
+// matching slice of V's columns.  Every step is a pass over the owned slices
+// followed by a grid-wide barrier; each workgroup then reduces the per-slice
+// partial results of its block in slice order and takes the same decision
+// (pivot, stop, next row) as every other workgroup of the block, so no
+// decision is broadcast.  Values one workgroup reads from another's slice
+// (the pivot row's U entries, the pivot column's V entries, the sampled rows
+// and columns of a stop check, the partials, the tried-row flags) go through
+// device-scope atomic loads and stores.  Blocks of one launch advance in
+// lockstep; a finished block idles through the barriers until every block of
+// the launch is done, so every workgroup runs the same number of barriers.
+// ---------------------------------------------------------------------------
+namespace coop {
+
+// per (block, workgroup) record of partial results, in doubles
+constexpr int R_ROWABS = 0, R_ROWIDX = 1, R_ROWVAL = 2, R_NU2 = 3, R_NV2 = 4, R_UABS = 5,
+              R_UIDX = 6, R_ER = 7, R_EC = 8, R_BABS = 9, R_BIDX = 10, R_CROSS = 16;
+
+__device__ __forceinline__ double ldd(const double* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void std_(double* p, double v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ int ldi(const int* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void sti(int* p, int v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ void gsync() {
+    __threadfence();
+    cooperative_groups::this_grid().sync();
+    __threadfence();
+}
+
+// workgroup sum of one value per thread (result in every thread)
+__device__ __forceinline__ double wg_sum(double v, double* red) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    v = wave_sum(v);
+    __syncthreads();
+    if (lane == 0) red[wv] = v;
+    __syncthreads();
+    double t = 0.0;
+    for (int w = 0; w < NW; ++w) t += red[w];
+    return t;
+}
+
+// workgroup argmax of (|value|, index) pairs, larger value then lower index
+// (result in every thread); idle threads pass (-1, INT_MAX)
+__device__ __forceinline__ void wg_argmax(double& v, int& i, double& sv, double* redv, int* redi,
+                                          double* reds) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    // carry the signed value along with the winning index
+    for (int o = 32; o > 0; o >>= 1) {
+        const double ov = __shfl_xor(v, o, 64);
+        const int oi = __shfl_xor(i, o, 64);
+        const double os = __shfl_xor(sv, o, 64);
+        if (ov > v || (ov == v && oi < i)) {
+            v = ov;
+            i = oi;
+            sv = os;
+        }
+    }
+    __syncthreads();
+    if (lane == 0) {
+        redv[wv] = v;
+        redi[wv] = i;
+        reds[wv] = sv;
+    }
+    __syncthreads();
+    v = redv[0];
+    i = redi[0];
+    sv = reds[0];
+    for (int w = 1; w < NW; ++w)
+        if (redv[w] > v || (redv[w] == v && redi[w] < i)) {
+            v = redv[w];
+            i = redi[w];
+            sv = reds[w];
+        }
+}
+
+}  // namespace coop
+
+__global__ __launch_bounds__(T) void k_aca_coop(const double* __restrict__ pts, int64_t N, int d,
+                                                KParams kp, double tol,
+                                                const AcaJob* __restrict__ jobs, int njobs,
+                                                int wpb, double* wsbase, int* usedbase,
+                                                const int64_t* __restrict__ usedoff, double* recs,
+                                                int recstride, int* doneflags,
+                                                int32_t* __restrict__ ranks,
+                                                int32_t* __restrict__ overflow,
+                                                int32_t* __restrict__ pivots) {
+    using namespace coop;
+    extern __shared__ double dyn[];
+    __shared__ double redv[NW], reds[NW];
+    __shared__ int redi[NW];
+    const int b = blockIdx.x / wpb, wl = blockIdx.x - b * wpb;
+    const int tid = threadIdx.x;
+    const AcaJob J = jobs[b];
+    const int m = J.m, n = J.n, cap = J.cap;
+    const int kcap = min(J.kmax, cap);
+    const int r0 = (int)((int64_t)wl * m / wpb), r1 = (int)((int64_t)(wl + 1) * m / wpb);
+    const int c0 = (int)((int64_t)wl * n / wpb), c1 = (int)((int64_t)(wl + 1) * n / wpb);
+    double* U = wsbase + J.ws;
+    double* V = U + (int64_t)cap * m;
+    int* used = usedbase + usedoff[b];
+    double* mine = recs + ((int64_t)b * wpb + wl) * recstride;
+    const double* brec = recs + (int64_t)b * wpb * recstride;
+    double* s_a = dyn;          // U entries of the pivot row (or of a sampled row)
+    double* s_b = dyn + cap;    // V entries of the pivot column (or of a sampled column)
+    const double* __restrict__ X = pts + J.a0;
+    const double* __restrict__ Y = pts + J.b0;
+
+    for (int i = r0 + tid; i < r1; i += T) sti(used + i, 0);
+    if (wl == 0 && tid == 0) sti(doneflags + b, 0);
+    int k = 0, istar = 0, nused = 0, checks = 0;
+    bool done = false, ovf = false;
+    double S2 = 0.0;
+    gsync();
+    for (;;) {
+        // ---- row residual of the pivot row over the owned columns
+        if (!done && k >= kcap) {
+            ovf = k < J.kmax;
+            done = true;
+        }
+        if (!done) {
+            if (wl == 0 && tid == 0) sti(used + istar, 1);
+            nused += 1;
+            for (int p = tid; p < k; p += T) s_a[p] = ldd(U + (int64_t)p * m + istar);
+            double xi[kMaxD];
+            for (int a = 0; a < d; ++a) xi[a] = X[a * N + istar];
+            __syncthreads();
+            double* Vk = V + (int64_t)k * n;
+            double bv = -1.0, bs = 0.0;
+            int bi = INT_MAX;
+            for (int j = c0 + tid; j < c1; j += T) {
+                double r2 = 0.0;
+                for (int a = 0; a < d; ++a) {
+                    const double t = xi[a] - Y[a * N + j];
+                    r2 += t * t;
+                }
+                double v = kfun(kp, r2);
+                for (int p = 0; p < k; ++p) v -= s_a[p] * V[(int64_t)p * n + j];
+                Vk[j] = v;
+                const double av = fabs(v);
+                if (av > bv) {
+                    bv = av;
+                    bi = j;
+                    bs = v;
+                }
+            }
+            wg_argmax(bv, bi, bs, redv, redi, reds);
+            if (tid == 0) {
+                std_(mine + R_ROWABS, bv);
+                std_(mine + R_ROWIDX, (double)bi);
+                std_(mine + R_ROWVAL, bs);
+            }
+        }
+        gsync();
+        // ---- pivot; residual of the pivot column over the owned rows
+        bool zero = false;
+        int jstar = INT_MAX;
+        if (!done) {
+            double bv = -1.0, piv = 0.0;
+            for (int w = 0; w < wpb; ++w) {
+                const double v = ldd(brec + (int64_t)w * recstride + R_ROWABS);
+                const int ix = (int)ldd(brec + (int64_t)w * recstride + R_ROWIDX);
+                if (v > bv || (v == bv && ix < jstar)) {
+                    bv = v;
+                    jstar = ix;
+                    piv = ldd(brec + (int64_t)w * recstride + R_ROWVAL);
+                }
+            }
+            // no finite maximum (non-finite entries): the row counts as zero
+            if (!(bv >= 0.0) || jstar < 0 || jstar >= n) piv = 0.0;
+            if (piv == 0.0) {
+                zero = true;
+                if (nused == m) {
+                    done = true;
+                } else {
+                    int mi = INT_MAX;
+                    for (int i = tid; i < m; i += T)
+                        if (!ldi(used + i)) {
+                            mi = i;
+                            break;
+                        }
+                    double ds = 0.0;
+                    // lowest untried row: an argmax of equal values picks the lowest index
+                    double key = mi < m ? 1.0 : -1.0;
+                    wg_argmax(key, mi, ds, redv, redi, reds);
+                    if (key < 0.0 || mi >= m)
+                        done = true;
+                    else
+                        istar = mi;
+                }
+            } else {
+                double* Vk = V + (int64_t)k * n;
+                double nv2 = 0.0;
+                for (int j = c0 + tid; j < c1; j += T) {
+                    const double v = Vk[j] / piv;
+                    Vk[j] = v;
+                    nv2 += v * v;
+                }
+                for (int p = tid; p < k; p += T) s_b[p] = ldd(V + (int64_t)p * n + jstar);
+                double yj[kMaxD];
+                for (int a = 0; a < d; ++a) yj[a] = Y[a * N + jstar];
+                __syncthreads();
+                double* Uk = U + (int64_t)k * m;
+                double nu2 = 0.0, bu = -1.0, bs = 0.0;
+                int bui = INT_MAX;
+                for (int i = r0 + tid; i < r1; i += T) {
+                    double r2 = 0.0;
+                    for (int a = 0; a < d; ++a) {
+                        const double t = X[a * N + i] - yj[a];
+                        r2 += t * t;
+                    }
+                    double u = kfun(kp, r2);
+                    for (int p = 0; p < k; ++p) u -= U[(int64_t)p * m + i] * s_b[p];
+                    Uk[i] = u;
+                    nu2 += u * u;
+                    if (!ldi(used + i) && fabs(u) > bu) {
+                        bu = fabs(u);
+                        bui = i;
+                    }
+                }
+                nu2 = wg_sum(nu2, redv);
+                nv2 = wg_sum(nv2, redv);
+                wg_argmax(bu, bui, bs, redv, redi, reds);
+                if (tid == 0) {
+                    std_(mine + R_NU2, nu2);
+                    std_(mine + R_NV2, nv2);
+                    std_(mine + R_UABS, bu);
+                    std_(mine + R_UIDX, (double)bui);
+                }
+                // cross products (U_p . u)(V_p . v) over the owned slices, p < k
+                const int lane = tid & 63, wv = tid >> 6;
+                for (int p = wv; p < k; p += NW) {
+                    double su = 0.0, sv = 0.0;
+                    const double* Up = U + (int64_t)p * m;
+                    const double* Vp = V + (int64_t)p * n;
+                    for (int i = r0 + lane; i < r1; i += 64) su += Up[i] * Uk[i];
+                    for (int j = c0 + lane; j < c1; j += 64) sv += Vp[j] * Vk[j];
+                    su = wave_sum(su);
+                    sv = wave_sum(sv);
+                    if (lane == 0) {
+                        std_(mine + R_CROSS + p, su);
+                        std_(mine + R_CROSS + cap + p, sv);
+                    }
+                }
+            }
+        }
+        gsync();
+        // ---- the candidate term's size; sampled residuals when it is small
+        bool small = false;
+        double S2new = 0.0;
+        int ix = -1;
+        const int sr = min(m, kAcaSamples), str = m / sr;
+        const int sc = min(n, kAcaSamples), stc = n / sc;
+        if (!done && !zero) {
+            double nu2 = 0.0, nv2 = 0.0, bu = -1.0;
+            int bui = INT_MAX;
+            for (int w = 0; w < wpb; ++w) {
+                const double* rw = brec + (int64_t)w * recstride;
+                nu2 += ldd(rw + R_NU2);
+                nv2 += ldd(rw + R_NV2);
+                const double v = ldd(rw + R_UABS);
+                const int i = (int)ldd(rw + R_UIDX);
+                if (v > bu || (v == bu && i < bui)) {
+                    bu = v;
+                    bui = i;
+                }
+            }
+            double cr = 0.0;
+            for (int p = tid; p < k; p += T) {
+                double su = 0.0, sv = 0.0;
+                for (int w = 0; w < wpb; ++w) {
+                    su += ldd(brec + (int64_t)w * recstride + R_CROSS + p);
+                    sv += ldd(brec + (int64_t)w * recstride + R_CROSS + cap + p);
+                }
+                cr += su * sv;
+            }
+            const double cross = wg_sum(cr, redv);
+            S2new = S2 + 2.0 * cross + nu2 * nv2;
+            ix = (bu >= 0.0 && bui >= 0 && bui < m) ? bui : -1;
+            small = k > 0 && sqrt(nu2 * nv2) <= tol * sqrt(S2new);
+            if (small) {
+                const int offr = (int)(((int64_t)checks * 997) % str);
+                const int offc = (int)(((int64_t)checks * 991) % stc);
+                double er = 0.0, ec = 0.0, bb = 0.0, bsv = 0.0;
+                int bbi = INT_MAX;
+                for (int q = 0; q < sr; ++q) {
+                    const int i = q * str + offr;
+                    __syncthreads();
+                    for (int p = tid; p < k; p += T) s_a[p] = ldd(U + (int64_t)p * m + i);
+                    __syncthreads();
+                    const bool untried = !ldi(used + i);
+                    for (int j = c0 + tid; j < c1; j += T) {
+                        double r2 = 0.0;
+                        for (int a = 0; a < d; ++a) {
+                            const double t = X[a * N + i] - Y[a * N + j];
+                            r2 += t * t;
+                        }
+                        double v = kfun(kp, r2);
+                        for (int p = 0; p < k; ++p) v -= s_a[p] * V[(int64_t)p * n + j];
+                        er += v * v;
+                        const double av = fabs(v);
+                        if (untried && av > 0.0 && (av > bb || (av == bb && i < bbi))) {
+                            bb = av;
+                            bbi = i;
+                        }
+                    }
+                }
+                for (int q = 0; q < sc; ++q) {
+                    const int j = q * stc + offc;
+                    __syncthreads();
+                    for (int p = tid; p < k; p += T) s_b[p] = ldd(V + (int64_t)p * n + j);
+                    __syncthreads();
+                    for (int i = r0 + tid; i < r1; i += T) {
+                        double r2 = 0.0;
+                        for (int a = 0; a < d; ++a) {
+                            const double t = X[a * N + i] - Y[a * N + j];
+                            r2 += t * t;
+                        }
+                        double v = kfun(kp, r2);
+                        for (int p = 0; p < k; ++p) v -= U[(int64_t)p * m + i] * s_b[p];
+                        ec += v * v;
+                        const double av = fabs(v);
+                        if (!ldi(used + i) && av > 0.0 && (av > bb || (av == bb && i < bbi))) {
+                            bb = av;
+                            bbi = i;
+                        }
+                    }
+                }
+                er = wg_sum(er, redv);
+                ec = wg_sum(ec, redv);
+                wg_argmax(bb, bbi, bsv, redv, redi, reds);
+                if (tid == 0) {
+                    std_(mine + R_ER, er);
+                    std_(mine + R_EC, ec);
+                    std_(mine + R_BABS, bb);
+                    std_(mine + R_BIDX, (double)bbi);
+                }
+            }
+        }
+        gsync();
+        // ---- decision (the same in every workgroup of the block)
+        if (!done && !zero) {
+            int next = -1;
+            if (small) {
+                double er = 0.0, ec = 0.0, bb = 0.0;
+                int bbi = INT_MAX;
+                for (int w = 0; w < wpb; ++w) {
+                    const double* rw = brec + (int64_t)w * recstride;
+                    er += ldd(rw + R_ER);
+                    ec += ldd(rw + R_EC);
+                    const double v = ldd(rw + R_BABS);
+                    const int i = (int)ldd(rw + R_BIDX);
+                    if (v > bb || (v == bb && i < bbi)) {
+                        bb = v;
+                        bbi = i;
+                    }
+                }
+                er *= (double)m / (double)sr;
+                ec *= (double)n / (double)sc;
+                const double lim = 0.25 * tol * tol * S2;
+                ++checks;
+                if (er <= lim && ec <= lim)
+                    done = true;
+                else if (bb > 0.0 && bbi >= 0 && bbi < m)
+                    next = bbi;
+            }
+            if (!done) {
+                S2 = S2new;
+                if (wl == 0 && tid == 0) {
+                    pivots[J.pv + 2 * k] = istar;
+                    pivots[J.pv + 2 * k + 1] = jstar;
+                }
+                k += 1;
+                const int nx = next >= 0 ? next : ix;
+                if (nused == m || nx < 0 || nx >= m)
+                    done = true;
+                else
+                    istar = nx;
+            }
+        }
+        if (wl == 0 && tid == 0) sti(doneflags + b, done ? 1 : 0);
+        gsync();
+        bool all = true;
+        for (int bb = 0; bb < njobs; ++bb) all = all && ldi(doneflags + bb) != 0;
+        if (all) break;
+    }
+    if (wl == 0 && tid == 0) {
+        ranks[b] = k;
+        overflow[b] = ovf ? 1 : 0;
+    }
+}
+
 template <typename S>
 __device__ __forceinline__ S to_storage(double v);
 template <>
@@ -507,9 +912,24 @@ struct ChunkResult {
     std::vector<int32_t> ranks, overflow;
 };
 
+enum class AcaMode { Global, Lds, Coop };
+
+}  // namespace
+bool verbose();
+namespace {
+
+// workgroups that can be resident at once for the cooperative kernel
+int coop_capacity(hodlr_t h, size_t lds_bytes) {
+    int per_cu = 0, cus = 0;
+    HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_aca_coop, T, lds_bytes));
+    HIP_CHECK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, h->device));
+    return std::max(per_cu, 0) * std::max(cus, 0);
+}
+
 // compress one chunk of jobs, pack into a new arena
-void run_chunk(hodlr_t h, std::vector<AcaJob>& jobs, bool lds, size_t lds_bytes,
+void run_chunk(hodlr_t h, std::vector<AcaJob>& jobs, AcaMode mode, size_t lds_bytes,
                std::vector<int32_t>& ranks_out, std::vector<int32_t>& ovf_out, hipStream_t s) {
+    const bool lds = mode == AcaMode::Lds;
     const int64_t nj = (int64_t)jobs.size();
     size_t ws_total = 0, pv_total = 0;
     for (auto& j : jobs) {
@@ -525,7 +945,58 @@ void run_chunk(hodlr_t h, std::vector<AcaJob>& jobs, bool lds, size_t lds_bytes,
     int32_t* dov = (int32_t*)dalloc(h, sizeof(int32_t) * nj);
     HIP_CHECK(hipMemcpyAsync(djobs, jobs.data(), sizeof(AcaJob) * nj, hipMemcpyHostToDevice, s));
     const double tol = h->tol;
-    if (lds) {
+    if (mode == AcaMode::Coop) {
+        // one cooperative launch: every job gets wpb workgroups, all resident
+        int capmax = 1;
+        std::vector<int64_t> uoff(nj);
+        int64_t ut = 0;
+        for (int64_t t = 0; t < nj; ++t) {
+            capmax = std::max(capmax, jobs[t].cap);
+            uoff[t] = ut;
+            ut += jobs[t].m;
+        }
+        const size_t clds = sizeof(double) * 2 * (size_t)capmax;
+        const int G = coop_capacity(h, clds);
+        if (G < nj)
+            fail(HODLR_EDEVICE, "cooperative ACA: fewer resident workgroups than blocks");
+        int wpb = (int)std::min<int64_t>(G / nj, 128);
+        for (auto& j : jobs) wpb = std::min(wpb, std::max(1, std::max(j.m, j.n) / 256));
+        wpb = std::max(wpb, 1);
+        const int recstride = coop::R_CROSS + 2 * capmax;
+        int* dused = (int*)dalloc(h, sizeof(int) * std::max<int64_t>(ut, 1));
+        int64_t* duoff = (int64_t*)dalloc(h, sizeof(int64_t) * nj);
+        double* drec = (double*)dalloc(h, sizeof(double) * (size_t)nj * wpb * recstride);
+        int* ddone = (int*)dalloc(h, sizeof(int) * nj);
+        HIP_CHECK(hipMemcpyAsync(duoff, uoff.data(), sizeof(int64_t) * nj, hipMemcpyHostToDevice, s));
+        const double* a_pts = h->pts;
+        int64_t a_N = h->N;
+        int a_d = h->d;
+        KParams a_kp = h->kp;
+        double a_tol = tol;
+        int a_nj = (int)nj;
+        void* args[] = {(void*)&a_pts, (void*)&a_N,   (void*)&a_d,    (void*)&a_kp,
+                        (void*)&a_tol, (void*)&djobs, (void*)&a_nj,   (void*)&wpb,
+                        (void*)&ws,    (void*)&dused, (void*)&duoff,  (void*)&drec,
+                        (void*)&recstride, (void*)&ddone, (void*)&dr, (void*)&dov,
+                        (void*)&dpiv};
+        if (verbose())
+            std::fprintf(stderr, "[hodlr] ACA (cooperative) %lld blocks x %d workgroups\n",
+                         (long long)nj, wpb);
+        {
+            // one cooperative launch in flight per process: two partly resident
+            // ones could wait on each other's workgroups
+            static std::mutex coop_mu;
+            std::lock_guard<std::mutex> lk(coop_mu);
+            HIP_CHECK(hipLaunchCooperativeKernel((const void*)k_aca_coop,
+                                                 dim3((unsigned)(nj * wpb)), dim3(T), args, clds,
+                                                 s));
+            HIP_CHECK(hipStreamSynchronize(s));
+        }
+        dfree(h, dused);
+        dfree(h, duoff);
+        dfree(h, drec);
+        dfree(h, ddone);
+    } else if (lds) {
         HIP_CHECK(hipFuncSetAttribute((const void*)k_aca<true>,
                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes));
         k_aca<true><<<(unsigned)nj, T, lds_bytes, s>>>(h->pts, h->N, h->d, h->kp, tol, djobs, ws,
@@ -644,7 +1115,12 @@ void compress_all(hodlr_t h, hipStream_t s) {
     const size_t ws_budget = std::max<size_t>(std::min<size_t>(freeb / 4, (size_t)16 << 30), 64 << 20);
     const int maxr = h->opts.max_rank > 0 ? h->opts.max_rank : INT_MAX;
 
-    std::vector<AcaJob> lds_jobs, glob_jobs;
+    // blocks with at least this many rows plus columns are spread over many
+    // workgroups (HODLR_ACA_COOP_MIN overrides it, for tests)
+    int64_t coop_min = 16384;
+    if (const char* e = std::getenv("HODLR_ACA_COOP_MIN"))
+        if (std::atoll(e) > 0) coop_min = std::atoll(e);
+    std::vector<AcaJob> lds_jobs, glob_jobs, coop_jobs;
     for (int64_t b = 0; b < h->nblocks; ++b) {
         const BlockDesc& bd = h->hblocks[b];
         AcaJob j{};
@@ -655,7 +1131,10 @@ void compress_all(hodlr_t h, hipStream_t s) {
         j.kmax = std::min(std::min(bd.m, bd.n), maxr);
         j.block = b;
         j.cap = j.kmax;
-        if (j.kmax <= kAcaMaxRank && job_lds_bytes(j) <= lds_limit) {
+        if ((int64_t)bd.m + bd.n >= coop_min && j.kmax > 0) {
+            j.cap = std::min(j.kmax, kAcaMaxRank);
+            coop_jobs.push_back(j);
+        } else if (j.kmax <= kAcaMaxRank && job_lds_bytes(j) <= lds_limit) {
             lds_jobs.push_back(j);
         } else {
             j.cap = std::min(j.kmax, 256);
@@ -663,6 +1142,27 @@ void compress_all(hodlr_t h, hipStream_t s) {
         }
     }
     std::vector<int32_t> rk, ov;
+    // the largest blocks first, cooperatively, in chunks that leave each block
+    // at least 16 workgroups and fit the workspace budget
+    if (!coop_jobs.empty()) {
+        const int G = coop_capacity(h, sizeof(double) * 2 * kAcaMaxRank);
+        const size_t per_launch = (size_t)std::max(1, G / 16);
+        for (size_t i = 0; i < coop_jobs.size();) {
+            std::vector<AcaJob> chunk;
+            size_t bytes = 0;
+            while (i < coop_jobs.size() && chunk.size() < per_launch &&
+                   (chunk.empty() || bytes + 8 * job_ws_doubles(coop_jobs[i]) <= ws_budget)) {
+                bytes += 8 * job_ws_doubles(coop_jobs[i]);
+                chunk.push_back(coop_jobs[i++]);
+            }
+            run_chunk(h, chunk, AcaMode::Coop, 0, rk, ov, s);
+            for (size_t t = 0; t < chunk.size(); ++t)
+                if (ov[t])
+                    fail(HODLR_EUNSUPPORTED,
+                         "an ACA rank exceeds the device compressor's limit of 1024; "
+                         "set max_rank");
+        }
+    }
     // LDS-resident blocks, in chunks bounded by the workspace budget
     for (size_t i = 0; i < lds_jobs.size();) {
         std::vector<AcaJob> chunk;
@@ -673,7 +1173,7 @@ void compress_all(hodlr_t h, hipStream_t s) {
             lmax = std::max(lmax, job_lds_bytes(lds_jobs[i]));
             chunk.push_back(lds_jobs[i++]);
         }
-        run_chunk(h, chunk, true, lmax, rk, ov, s);
+        run_chunk(h, chunk, AcaMode::Lds, lmax, rk, ov, s);
         if (verbose())
             std::fprintf(stderr, "[hodlr] ACA (LDS) %zu / %zu blocks\n", i, lds_jobs.size());
     }
@@ -688,7 +1188,7 @@ void compress_all(hodlr_t h, hipStream_t s) {
                 bytes += 8 * job_ws_doubles(glob_jobs[i]);
                 chunk.push_back(glob_jobs[i++]);
             }
-            run_chunk(h, chunk, false, 0, rk, ov, s);
+            run_chunk(h, chunk, AcaMode::Global, 0, rk, ov, s);
             if (verbose())
                 std::fprintf(stderr, "[hodlr] ACA (workspace, rank cap %d) %zu / %zu blocks\n",
                              chunk.empty() ? 0 : chunk[0].cap, i, glob_jobs.size());

@@ -181,6 +181,22 @@ hodlr_status hodlr_matvec_events(hodlr_t h, const void* X, int64_t ldx, int nrhs
  * nrhs < 1 or a bad precision. */
 hodlr_status hodlr_reserve_workspace(hodlr_t h, int nrhs, int compute_prec);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * product of hodlr_matvec with the same arguments and result, whose
+ * workspace is the library's static device scratch array of
+ * HODLR_NOALLOC_SCRATCH_BYTES (one per GPU, held until the process ends)
+ * and whose near field runs on `stream` itself (no second stream).  The call
+ * allocates nothing and creates nothing; the handle must belong to the
+ * current device.  Every call on one GPU shares that array: calls that
+ * overlap on one GPU (other streams, other threads, other handles) race and
+ * must be ordered by the caller.  Errors: those of hodlr_matvec, and EINVAL
+ * when the product's workspace (which grows with N, the number of stored
+ * blocks and nrhs) exceeds the scratch array. */
+#define HODLR_NOALLOC_SCRATCH_BYTES (64u << 20)
+hodlr_status hodlr_matvec_noalloc(hodlr_t h, const void* X, int64_t ldx, int nrhs, int x_prec,
+                                  void* Y, int64_t ldy, int compute_prec, void* stream);
+
 /* Largest byte offset the matrix-core product (BF16 factors, several
  * right-hand sides; the blocks of Alg. "HODLRdD matrix-vector Product")
  * forms within one factor of rank `rank` and length `len` or within the x

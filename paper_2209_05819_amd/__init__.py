@@ -108,6 +108,7 @@ def lib():
         L.hodlr_matvec.argtypes = [_P, _P, _i64, C.c_int, C.c_int, _P, _i64, C.c_int, _P]
         L.hodlr_matvec_events.argtypes = [_P, _P, _i64, C.c_int, C.c_int, _P, _i64, C.c_int, _P,
                                           C.POINTER(_P), C.c_int]
+        L.hodlr_matvec_noalloc.argtypes = [_P, _P, _i64, C.c_int, C.c_int, _P, _i64, C.c_int, _P]
         L.hodlr_get_info.argtypes = [_P, C.POINTER(Info)]
         L.hodlr_server_default_opts.argtypes = [C.POINTER(ServerOpts)]
         L.hodlr_server_default_opts.restype = None
@@ -138,7 +139,8 @@ def lib():
         L.hodlr_import_factors.argtypes = [_P, C.c_int, _P, _P, _P]
         L.hodlr_destroy.argtypes = [_P]
         L.hodlr_last_error.restype = C.c_char_p
-        for f in ("hodlr_build", "hodlr_matvec", "hodlr_matvec_events", "hodlr_get_info",
+        for f in ("hodlr_build", "hodlr_matvec", "hodlr_matvec_events", "hodlr_matvec_noalloc",
+                  "hodlr_get_info",
                   "hodlr_export_tree",
                   "hodlr_export_boxes", "hodlr_export_il", "hodlr_export_near",
                   "hodlr_export_near_level", "hodlr_export_box_flags", "hodlr_reserve_workspace",
@@ -232,6 +234,28 @@ def hodlr_matvec(h: int, X, Y, compute_prec: int = FP64, stream=None) -> None:
         ldx, ldy = X.stride(1) if nrhs > 1 else N, Y.stride(1) if nrhs > 1 else N
     _check(lib().hodlr_matvec(C.c_void_p(h), C.c_void_p(X.data_ptr()), ldx, nrhs, xp,
                               C.c_void_p(Y.data_ptr()), ldy, compute_prec, _stream_ptr(stream)))
+
+
+def hodlr_matvec_noalloc(h: int, X, Y, compute_prec: int = FP64, stream=None) -> None:
+    """hodlr_matvec with the library's static scratch array as workspace and
+    the near field on the same stream: allocates nothing (for callers that
+    cannot); calls on one GPU must not overlap."""
+    import torch
+    if X.dtype != Y.dtype or X.dtype not in (torch.float64, torch.float32):
+        raise TypeError("X and Y must both be float64 or float32")
+    if not (X.is_cuda and Y.is_cuda):
+        raise TypeError("X and Y must be device tensors")
+    xp = FP64 if X.dtype == torch.float64 else FP32
+    if X.dim() == 1:
+        nrhs, ldx, ldy = 1, X.shape[0], Y.shape[0]
+    else:
+        N, nrhs = X.shape
+        if X.stride(0) != 1 or Y.stride(0) != 1:
+            raise ValueError("X and Y must be column-major (stride 1 along N)")
+        ldx, ldy = X.stride(1) if nrhs > 1 else N, Y.stride(1) if nrhs > 1 else N
+    _check(lib().hodlr_matvec_noalloc(C.c_void_p(h), C.c_void_p(X.data_ptr()), ldx, nrhs, xp,
+                                      C.c_void_p(Y.data_ptr()), ldy, compute_prec,
+                                      _stream_ptr(stream)))
 
 
 def hodlr_reserve_workspace(h: int, nrhs: int, compute_prec: int = FP64) -> None:

@@ -165,7 +165,7 @@ hodlr_status hodlr_build(const double* points, int64_t N, int d, const hodlr_ker
 namespace {
 hodlr_status matvec_checked(hodlr_t h, const void* X, int64_t ldx, int nrhs, int x_prec, void* Y,
                             int64_t ldy, int compute_prec, void* stream, void* const* events,
-                            int nevents) {
+                            int nevents, bool noalloc = false) {
     if (!h || !X || !Y) return set_error(HODLR_EINVAL, "null pointer argument");
     if (nrhs < 1) return set_error(HODLR_EINVAL, "nrhs must be >= 1");
     if (ldx < h->N || ldy < h->N) return set_error(HODLR_EINVAL, "leading dimension < N");
@@ -183,9 +183,13 @@ hodlr_status matvec_checked(hodlr_t h, const void* X, int64_t ldx, int nrhs, int
         if (!h->lev[l].has_factors) return set_error(HODLR_EINVAL, "factors missing");
     if (!h->near_items) return set_error(HODLR_EINVAL, "factors missing");
     return guarded([&] {
-        hodlr::matvec(h, X, ldx, nrhs, x_prec, Y, ldy, compute_prec,
-                      reinterpret_cast<hipEvent_t const*>(events), events ? nevents : 0,
-                      (hipStream_t)stream);
+        if (noalloc)
+            hodlr::matvec_noalloc(h, X, ldx, nrhs, x_prec, Y, ldy, compute_prec,
+                                  (hipStream_t)stream);
+        else
+            hodlr::matvec(h, X, ldx, nrhs, x_prec, Y, ldy, compute_prec,
+                          reinterpret_cast<hipEvent_t const*>(events), events ? nevents : 0,
+                          (hipStream_t)stream);
     });
 }
 }  // namespace
@@ -211,6 +215,12 @@ hodlr_status hodlr_mfma_extent(int64_t rank, int64_t len, int nrhs, int64_t* ext
 hodlr_status hodlr_matvec(hodlr_t h, const void* X, int64_t ldx, int nrhs, int x_prec, void* Y,
                           int64_t ldy, int compute_prec, void* stream) {
     return matvec_checked(h, X, ldx, nrhs, x_prec, Y, ldy, compute_prec, stream, nullptr, 0);
+}
+
+hodlr_status hodlr_matvec_noalloc(hodlr_t h, const void* X, int64_t ldx, int nrhs, int x_prec,
+                                  void* Y, int64_t ldy, int compute_prec, void* stream) {
+    return matvec_checked(h, X, ldx, nrhs, x_prec, Y, ldy, compute_prec, stream, nullptr, 0,
+                          true);
 }
 
 hodlr_status hodlr_matvec_events(hodlr_t h, const void* X, int64_t ldx, int nrhs, int x_prec,

@@ -15,6 +15,8 @@
 // Each output is produced by one lane in a fixed order: results are bitwise
 // reproducible and no floating-point atomics are used.
 #include <algorithm>
+#include <mutex>
+#include <string>
 #include <type_traits>
 
 #include "hodlr_impl.hpp"
@@ -1888,9 +1890,11 @@ inline unsigned near_grid(hodlr_t h, int nc, size_t factor_elem_bytes) {
     return (unsigned)((double)h->near_pairs * nc <= light ? std::min(n, kNearGridCap) : n);
 }
 
+// aux: the stream of the near field (the handle's second stream, or s itself
+// for a product on one stream)
 template <typename XT, typename S, typename C, int NR>
 void run_matvec(hodlr_t h, const XT* X, int64_t ldx, int nrhs, XT* Y, int64_t ldy, char* ws,
-                hipEvent_t const* ev, int nev, hipStream_t s) {
+                hipEvent_t const* ev, int nev, hipStream_t s, hipStream_t aux) {
     const int64_t N = h->N;
     const int64_t TT = std::max<int64_t>(h->t_total, 1);
     const int64_t CT = std::max<int64_t>(h->contrib_total, 1);
@@ -1904,11 +1908,13 @@ void run_matvec(hodlr_t h, const XT* X, int64_t ldx, int nrhs, XT* Y, int64_t ld
     // the second stream starts after everything issued so far on s, and s
     // waits for all of its work at the join
     auto fork = [&] {
+        if (aux == s) return;
         HIP_CHECK(hipEventRecord(h->ev_fork, s));
-        HIP_CHECK(hipStreamWaitEvent(h->aux, h->ev_fork, 0));
+        HIP_CHECK(hipStreamWaitEvent(aux, h->ev_fork, 0));
     };
     auto join = [&] {
-        HIP_CHECK(hipEventRecord(h->ev_join, h->aux));
+        if (aux == s) return;
+        HIP_CHECK(hipEventRecord(h->ev_join, aux));
         HIP_CHECK(hipStreamWaitEvent(s, h->ev_join, 0));
     };
     if (ev) HIP_CHECK(hipEventRecord(ev[0], s));
@@ -1943,7 +1949,7 @@ void run_matvec(hodlr_t h, const XT* X, int64_t ldx, int nrhs, XT* Y, int64_t ld
                 switch (h->kp.kind * 2 + (h->d == 4 ? 1 : 0)) {
 #define HODLR_NEAR_MFMA(K, DC)                                                                  \
     case K * 2 + (DC == 4 ? 1 : 0):                                                             \
-        k_near_mfma<CTn, K, DC><<<(unsigned)h->n_near_items, 256, 0, h->aux>>>(         \
+        k_near_mfma<CTn, K, DC><<<(unsigned)h->n_near_items, 256, 0, aux>>>(              \
             h->near_items, h->n_near_items, h->near_rng, h->pts, N, h->d, h->kp, xr, nc, ynm);   \
         break;
 #define HODLR_NEAR_MFMA2(K) HODLR_NEAR_MFMA(K, 3) HODLR_NEAR_MFMA(K, 4)
@@ -2020,7 +2026,7 @@ void run_matvec(hodlr_t h, const XT* X, int64_t ldx, int nrhs, XT* Y, int64_t ld
             switch (h->kp.kind) {
 #define HODLR_NEAR(K)                                                                           \
     case K:                                                                                     \
-        k_gather_near<XT, C, NR, K, kNearOnly><<<gnear, TG, 0, h->aux>>>(                      \
+        k_gather_near<XT, C, NR, K, kNearOnly><<<gnear, TG, 0, aux>>>(                         \
             h->near_items, h->n_near_items, h->leaf_seg, h->near_rng, h->kappa, h->pts, N, h->d, \
             h->kp, x, contrib, CT, h->perm, nrhs, c0, Y, ldy, nullptr, yn);                     \
         break;
@@ -2036,7 +2042,7 @@ void run_matvec(hodlr_t h, const XT* X, int64_t ldx, int nrhs, XT* Y, int64_t ld
 #undef HODLR_NEAR
             }
         } else {
-            k_gather_near<XT, C, NR, -1, kNearOnly><<<gnear, TG, 0, h->aux>>>(
+            k_gather_near<XT, C, NR, -1, kNearOnly><<<gnear, TG, 0, aux>>>(
                 h->near_items, h->n_near_items, h->leaf_seg, h->near_rng, h->kappa, h->pts, N,
                 h->d, h->kp, x, contrib, CT, h->perm, nrhs, c0, Y, ldy, nullptr, yn);
         }
@@ -2140,28 +2146,27 @@ void run_matvec(hodlr_t h, const XT* X, int64_t ldx, int nrhs, XT* Y, int64_t ld
 
 template <typename XT, typename S, typename C>
 void dispatch_nr(hodlr_t h, const XT* X, int64_t ldx, int nrhs, XT* Y, int64_t ldy, char* ws,
-                 hipEvent_t const* ev, int nev, hipStream_t s) {
+                 hipEvent_t const* ev, int nev, hipStream_t s, hipStream_t aux) {
     if constexpr (std::is_same<S, bf16>::value) {
         // BF16 factors: matrix cores for several right-hand sides
         if (nrhs == 1)
-            run_matvec<XT, S, C, 1>(h, X, ldx, nrhs, Y, ldy, ws, ev, nev, s);
+            run_matvec<XT, S, C, 1>(h, X, ldx, nrhs, Y, ldy, ws, ev, nev, s, aux);
         else if (nrhs <= 16)
-            run_matvec<XT, S, C, 16>(h, X, ldx, nrhs, Y, ldy, ws, ev, nev, s);
+            run_matvec<XT, S, C, 16>(h, X, ldx, nrhs, Y, ldy, ws, ev, nev, s, aux);
         else
-            run_matvec<XT, S, C, 32>(h, X, ldx, nrhs, Y, ldy, ws, ev, nev, s);
+            run_matvec<XT, S, C, 32>(h, X, ldx, nrhs, Y, ldy, ws, ev, nev, s, aux);
         return;
     }
     if (nrhs == 1 || h->opts.skeleton)   // the skeleton form takes one column per pass
-        run_matvec<XT, S, C, 1>(h, X, ldx, nrhs, Y, ldy, ws, ev, nev, s);
+        run_matvec<XT, S, C, 1>(h, X, ldx, nrhs, Y, ldy, ws, ev, nev, s, aux);
     else if (nrhs <= 4)
-        run_matvec<XT, S, C, 4>(h, X, ldx, nrhs, Y, ldy, ws, ev, nev, s);
+        run_matvec<XT, S, C, 4>(h, X, ldx, nrhs, Y, ldy, ws, ev, nev, s, aux);
     else
-        run_matvec<XT, S, C, 8>(h, X, ldx, nrhs, Y, ldy, ws, ev, nev, s);
+        run_matvec<XT, S, C, 8>(h, X, ldx, nrhs, Y, ldy, ws, ev, nev, s, aux);
 }
 
-}  // namespace
-
-void reserve_workspace(hodlr_t h, int nrhs, int compute_prec, hipStream_t s) {
+// Workspace (per product, device memory) for nrhs columns in compute_prec.
+size_t workspace_need(hodlr_t h, int nrhs, int compute_prec) {
     const int64_t N = h->N;
     const size_t cs = compute_prec == HODLR_FP32 ? 4 : 8;
     const int64_t TT = std::max<int64_t>(h->t_total, 1);
@@ -2169,17 +2174,76 @@ void reserve_workspace(hodlr_t h, int nrhs, int compute_prec, hipStream_t s) {
     const bool b16 = h->opts.storage == HODLR_BF16;
     const int nr = (nrhs == 1 || h->opts.skeleton) ? 1
                    : b16 ? (nrhs <= 16 ? 16 : 32) : (nrhs <= 4 ? 4 : 8);
-    size_t need;
     if (b16 && nr >= 16)   // x, x rows, level sums, projections, panel partials, near sums
-        need = align256(cs * (size_t)N * nrhs) + align256(2 * (size_t)N * nr) +
+        return align256(cs * (size_t)N * nrhs) + align256(2 * (size_t)N * nr) +
                align256(4 * (size_t)N * nr) +
                align256(2 * (size_t)std::max<int64_t>(h->mt_total, 1) * nr) +
                align256(4 * (size_t)std::max<int64_t>(h->mpart_total, 1) * nr) +
                align256(4 * (size_t)N * nr) + 4096;
-    else   // x, contributions, projections, partials, near-field sums
-        need = cs * ((size_t)N * nrhs + (size_t)CT * nr + 2 * (size_t)TT * nr +
-                     2 * (size_t)kProjSegMax * (size_t)h->n_proj_sums * nr + (size_t)N * nr) +
-               4096;
+    // x, contributions, projections, partials, near-field sums
+    return cs * ((size_t)N * nrhs + (size_t)CT * nr + 2 * (size_t)TT * nr +
+                 2 * (size_t)kProjSegMax * (size_t)h->n_proj_sums * nr + (size_t)N * nr) +
+           4096;
+}
+
+void run_product(hodlr_t h, const void* X, int64_t ldx, int nrhs, int x_prec, void* Y,
+                 int64_t ldy, int compute_prec, char* ws, hipEvent_t const* ev, int nev,
+                 hipStream_t s, hipStream_t aux) {
+    const bool b16 = h->opts.storage == HODLR_BF16;
+    const bool s32 = h->opts.storage == HODLR_FP32;
+    const bool c32 = compute_prec == HODLR_FP32;
+    if (b16) {
+        // BF16 factors are applied in FP32 (checked by the caller)
+        if (x_prec == HODLR_FP64)
+            dispatch_nr<double, bf16, float>(h, (const double*)X, ldx, nrhs, (double*)Y, ldy, ws,
+                                             ev, nev, s, aux);
+        else
+            dispatch_nr<float, bf16, float>(h, (const float*)X, ldx, nrhs, (float*)Y, ldy, ws, ev,
+                                            nev, s, aux);
+        return;
+    }
+    if (x_prec == HODLR_FP64) {
+        const double* Xd = (const double*)X;
+        double* Yd = (double*)Y;
+        if (!s32 && !c32) dispatch_nr<double, double, double>(h, Xd, ldx, nrhs, Yd, ldy, ws, ev, nev, s, aux);
+        else if (!s32 && c32) dispatch_nr<double, double, float>(h, Xd, ldx, nrhs, Yd, ldy, ws, ev, nev, s, aux);
+        else if (s32 && !c32) dispatch_nr<double, float, double>(h, Xd, ldx, nrhs, Yd, ldy, ws, ev, nev, s, aux);
+        else dispatch_nr<double, float, float>(h, Xd, ldx, nrhs, Yd, ldy, ws, ev, nev, s, aux);
+    } else {
+        const float* Xf = (const float*)X;
+        float* Yf = (float*)Y;
+        if (!s32 && !c32) dispatch_nr<float, double, double>(h, Xf, ldx, nrhs, Yf, ldy, ws, ev, nev, s, aux);
+        else if (!s32 && c32) dispatch_nr<float, double, float>(h, Xf, ldx, nrhs, Yf, ldy, ws, ev, nev, s, aux);
+        else if (s32 && !c32) dispatch_nr<float, float, double>(h, Xf, ldx, nrhs, Yf, ldy, ws, ev, nev, s, aux);
+        else dispatch_nr<float, float, float>(h, Xf, ldx, nrhs, Yf, ldy, ws, ev, nev, s, aux);
+    }
+}
+
+// Static workspace of the product for callers that cannot allocate: one copy
+// per GPU, held until the process ends.  Host code uses it only through the
+// device address hipGetSymbolAddress returns for the current device.
+static __device__ __align__(256) char scratch[kScratchBytes];
+
+char* scratch_address(int device) {
+    constexpr int kMaxDev = 64;
+    static std::mutex mu;
+    static void* addr[kMaxDev] = {};
+    if (device < 0 || device >= kMaxDev) fail(HODLR_EINVAL, "device index out of range");
+    std::lock_guard<std::mutex> lk(mu);
+    if (!addr[device]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            fail(HODLR_EDEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        addr[device] = p;
+    }
+    return (char*)addr[device];
+}
+
+}  // namespace
+
+void reserve_workspace(hodlr_t h, int nrhs, int compute_prec, hipStream_t s) {
+    const size_t need = workspace_need(h, nrhs, compute_prec);
     // growing allocates and synchronises, and creating the second stream is
     // no stream operation: neither is allowed inside a graph capture
     auto capturing = [&] {
@@ -2212,35 +2276,23 @@ void reserve_workspace(hodlr_t h, int nrhs, int compute_prec, hipStream_t s) {
 void matvec(hodlr_t h, const void* X, int64_t ldx, int nrhs, int x_prec, void* Y, int64_t ldy,
             int compute_prec, hipEvent_t const* ev, int nev, hipStream_t s) {
     reserve_workspace(h, nrhs, compute_prec, s);
-    const bool b16 = h->opts.storage == HODLR_BF16;
-    char* ws = (char*)h->ws;
-    const bool s32 = h->opts.storage == HODLR_FP32;
-    const bool c32 = compute_prec == HODLR_FP32;
-    if (b16) {
-        // BF16 factors are applied in FP32 (checked by the caller)
-        if (x_prec == HODLR_FP64)
-            dispatch_nr<double, bf16, float>(h, (const double*)X, ldx, nrhs, (double*)Y, ldy, ws,
-                                             ev, nev, s);
-        else
-            dispatch_nr<float, bf16, float>(h, (const float*)X, ldx, nrhs, (float*)Y, ldy, ws, ev,
-                                            nev, s);
-        return;
-    }
-    if (x_prec == HODLR_FP64) {
-        const double* Xd = (const double*)X;
-        double* Yd = (double*)Y;
-        if (!s32 && !c32) dispatch_nr<double, double, double>(h, Xd, ldx, nrhs, Yd, ldy, ws, ev, nev, s);
-        else if (!s32 && c32) dispatch_nr<double, double, float>(h, Xd, ldx, nrhs, Yd, ldy, ws, ev, nev, s);
-        else if (s32 && !c32) dispatch_nr<double, float, double>(h, Xd, ldx, nrhs, Yd, ldy, ws, ev, nev, s);
-        else dispatch_nr<double, float, float>(h, Xd, ldx, nrhs, Yd, ldy, ws, ev, nev, s);
-    } else {
-        const float* Xf = (const float*)X;
-        float* Yf = (float*)Y;
-        if (!s32 && !c32) dispatch_nr<float, double, double>(h, Xf, ldx, nrhs, Yf, ldy, ws, ev, nev, s);
-        else if (!s32 && c32) dispatch_nr<float, double, float>(h, Xf, ldx, nrhs, Yf, ldy, ws, ev, nev, s);
-        else if (s32 && !c32) dispatch_nr<float, float, double>(h, Xf, ldx, nrhs, Yf, ldy, ws, ev, nev, s);
-        else dispatch_nr<float, float, float>(h, Xf, ldx, nrhs, Yf, ldy, ws, ev, nev, s);
-    }
+    run_product(h, X, ldx, nrhs, x_prec, Y, ldy, compute_prec, (char*)h->ws, ev, nev, s, h->aux);
+}
+
+void matvec_noalloc(hodlr_t h, const void* X, int64_t ldx, int nrhs, int x_prec, void* Y,
+                    int64_t ldy, int compute_prec, hipStream_t s) {
+    const size_t need = workspace_need(h, nrhs, compute_prec);
+    if (need > (size_t)kScratchBytes)
+        fail(HODLR_EINVAL, "this product needs " + std::to_string(need) +
+                               " bytes of workspace, more than the static scratch of " +
+                               std::to_string((size_t)kScratchBytes) +
+                               " bytes (fewer right-hand sides, or hodlr_matvec)");
+    int dev = -1;
+    HIP_CHECK(hipGetDevice(&dev));
+    if (dev != h->device) fail(HODLR_EINVAL, "the handle's device is not the current device");
+    // no second stream: the near field runs on s between the other stages
+    run_product(h, X, ldx, nrhs, x_prec, Y, ldy, compute_prec, scratch_address(dev), nullptr, 0,
+                s, s);
 }
 
 }  // namespace hodlr

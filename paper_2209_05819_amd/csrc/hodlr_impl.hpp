@@ -376,6 +376,11 @@ void matvec(hodlr_t h, const void* X, int64_t ldx, int nrhs, int x_prec, void* Y
             int compute_prec, hipEvent_t const* ev, int nev, hipStream_t s);
 // grows the handle's product workspace to what nrhs columns need
 void reserve_workspace(hodlr_t h, int nrhs, int compute_prec, hipStream_t s);
+// the product with its workspace in the library's static scratch array and
+// the near field on s (no allocation, no second stream)
+constexpr int64_t kScratchBytes = (int64_t)64 << 20;
+void matvec_noalloc(hodlr_t h, const void* X, int64_t ldx, int nrhs, int x_prec, void* Y,
+                    int64_t ldy, int compute_prec, hipStream_t s);
 // serve.hip
 hodlr_status server_create(const hodlr_server_opts& o, hodlr_server_t* out);
 void server_destroy(hodlr_server_t S);

@@ -303,7 +303,9 @@ def solve_bench(P, torch, W, n_override=0):
     secs = time.perf_counter() - t0
     print(f"[bench] solve {secs:.2f} s outer {info.outer_iters} inner {info.inner_iters} "
           f"rel {info.rel_residual:.2e}", file=sys.stderr, flush=True)
-    del H64, H16
+    del H16
+    c4 = gram_solve(P, torch, W, w, pts, q, H64, build)
+    del H64
     return {
         "workload": w.name, "system": "(I + K/N) U = F", "N": N, "nrhs": nrhs,
         "kernel": "exp(-r^2/0.25), diag 1+1e-3", "leaf": w.leaf, "aca_tol": w.tol,
@@ -315,10 +317,54 @@ def solve_bench(P, torch, W, n_override=0):
         "value": N * nrhs / secs, "unit": "N*nrhs/s solved", "build_s": round(build, 2),
         "history": [info.history[i] for i in range(min(info.outer_iters + 1, 64))],
         "product_16rhs_bf16": trees,
+        "gram_system": c4,
     }
 
 
-def serve_bench(P, torch, W, full=False):
+def gram_solve(P, torch, W, w, pts, q, H64, build, restart=50, max_outer=4):
+    """The Gaussian-mixture workload's own system: the Gram matrix
+    K~ U = F with K(i,i) = 1 + 1e-3 (the SVM-style regularised kernel matrix),
+    GMRES with iterative refinement to 1e-10, inner GMRES(restart) in FP64 on
+    the FP64 factors themselves (a low-precision inner operator perturbs this
+    system by more than its smallest eigenvalues), at most max_outer cycles.
+    Reported as it ends: converged or not, the residual history against the
+    operator, and the residual against the direct sum on 256 sampled rows."""
+    import oracle
+    N, nrhs = w.N, q.shape[1]
+    F = torch.tensor(np.ascontiguousarray(q.T), dtype=torch.float64, device="cuda").t()
+    U = torch.zeros((nrhs, N), dtype=torch.float64, device="cuda").t()
+    o = P.default_solve_opts()
+    o.tol, o.inner_tol, o.restart, o.max_outer = 1e-10, 1e-12, restart, max_outer
+    o.lo_compute = P.FP64
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    info = P.hodlr_solve(H64.h, H64.h, 0.0, 1.0, F, U, o)
+    torch.cuda.synchronize()
+    secs = time.perf_counter() - t0
+    u = U.t().contiguous().cpu().numpy().T
+    rows = np.sort(W.rng(212).choice(N, 256, replace=False))
+    oracle.build(force=False)
+    ku = oracle.direct(pts, oracle.kernel(w.kernel, h=w.h, diag=w.diag), u, rows=rows)
+    true_res = float(np.max(np.linalg.norm(q[rows] - ku, axis=0) /
+                            np.linalg.norm(q[rows], axis=0)))
+    print(f"[bench] Gram system: {secs:.1f} s, {info.inner_iters} products, converged "
+          f"{bool(info.converged)}, residual {info.rel_residual:.2e} (direct sum, sampled rows: "
+          f"{true_res:.2e})", file=sys.stderr, flush=True)
+    return {
+        "system": "K~ U = F, K(i,i) = 1 + 1e-3", "tol": o.tol,
+        "inner": f"GMRES({restart}) in FP64 on the FP64 factors",
+        "outer": "FP64 residuals on FP64 factors", "max_outer": max_outer,
+        "converged": bool(info.converged), "rel_residual": info.rel_residual,
+        "outer_iters": info.outer_iters, "inner_iters": info.inner_iters, "seconds": secs,
+        "history": [info.history[i] for i in range(min(info.outer_iters + 1, 64))],
+        "residual_vs_direct_sum_sampled": true_res,
+        "residual_ref": "max over columns of |F - K U| / |F| on 256 sampled rows (seed 212), "
+                        "K by the direct sum",
+        "build_s": round(build, 2),
+    }
+
+
+def serve_bench(P, torch, W, full=True):
     """Serving: resident point sets (N log-uniform, d in {2,3}, kernels log r,
     1/r, Gaussian h=0.5 drawn uniformly, FP32 factors, leaf 64, ACA 1e-8);
     requests half products (nrhs 1..64) and half solves of (I + K/N) u = f
@@ -337,6 +383,11 @@ def serve_bench(P, torch, W, full=False):
         pts = W.uniform_points(N, d, 500 + i)
         k = P.make_kernel(kn, h=0.5, diag=1.0 if kn == "gauss" else 0.0)
         sets.append((srv.add_set(pts, k, 64, 1e-8, storage=P.FP32), N))
+        if (i + 1) % 8 == 0:
+            st = srv.stats()
+            print(f"[bench] serve: {i + 1}/{nsets} sets resident, "
+                  f"{st.used_bytes / 2**30:.1f} GiB of {st.budget_bytes / 2**30:.1f}, "
+                  f"{time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
     build = time.perf_counter() - t0
     reqs = []
     for i in range(nreq):
@@ -367,6 +418,8 @@ def serve_bench(P, torch, W, full=False):
     run(None)   # warm-up
     wall0, _ = run(None)
     cap = nreq / wall0
+    print(f"[bench] serve: capacity {cap:.1f} requests/s (all submitted at once)",
+          file=sys.stderr, flush=True)
     st0 = srv.stats()
     wall, lat = run(0.7 * cap)
     st1 = srv.stats()
@@ -576,8 +629,10 @@ def main():
     ap.add_argument("--no-skeleton", action="store_true", help="skip the skeleton form")
     ap.add_argument("--no-adm", action="store_true",
                     help="skip the comparison of admissibility conditions")
-    ap.add_argument("--serve-full", action="store_true",
-                    help="serving with 64 sets up to 2^18 points and 256 requests")
+    ap.add_argument("--serve-small", action="store_true",
+                    help="serving reduced to 16 sets up to 2^16 points and 128 requests")
+    ap.add_argument("--no-depth-rule", action="store_true",
+                    help="skip the main workload under the max-count depth rule")
     ap.add_argument("--solve-n", type=int, default=0, help="override the solve's N")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain device copy of known size (counter calibration)")
@@ -674,6 +729,13 @@ def main():
         skel = skeleton_bench(P, torch, w, pts, q, args.steps, args.warmup, args.level_rule, bd,
                               rows)
 
+    depth = None
+    if not args.no_depth_rule and args.level_rule == 1:
+        depth = depth_rule_bench(P, torch, w, pts, q, bd, rows, max(5, args.steps // 2),
+                                 args.warmup)
+        print(f"[bench] max-count depth: kappa {depth['kappa']}, {depth['ms_per_step']:.2f} ms, "
+              f"build {depth['build_s']} s", file=sys.stderr, flush=True)
+
     mrhs = None
     if not args.no_multi_rhs:
         mrhs = multi_rhs(P, torch, W, max(3, args.steps // 4), 1, args.multi_rhs_n)
@@ -692,7 +754,7 @@ def main():
 
     serve = None
     if not args.no_serve:
-        serve = serve_bench(P, torch, W, args.serve_full)
+        serve = serve_bench(P, torch, W, not args.serve_small)
 
     adm = None
     if not args.no_adm:
@@ -754,6 +816,7 @@ def main():
                             "bytes": int(fb64 + vec_bytes)},
         "mixed": mixed,
         "skeleton": skel,
+        "depth_rule_max_count": depth,
         "multi_rhs": mrhs,
         "solve": solve,
         "small": small,

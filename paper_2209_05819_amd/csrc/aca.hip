@@ -75,13 +75,15 @@ __global__ __launch_bounds__(T) void k_aca(const double* __restrict__ pts, int64
                                            KParams kp, double tol, const AcaJob* __restrict__ jobs,
                                            double* __restrict__ wsbase, int32_t* __restrict__ ranks,
                                            int32_t* __restrict__ overflow,
-                                           int32_t* __restrict__ pivots) {
+                                           int32_t* __restrict__ pivots,
+                                           double* __restrict__ tsize,
+                                           double* __restrict__ s2out) {
     extern __shared__ double dyn[];
     __shared__ double red_v[NW], red_w[NW], red_x[NW];
     __shared__ int red_i[NW], red_j[NW];
     __shared__ int sh_k, sh_istar, sh_nused, sh_done, sh_jstar, sh_small, sh_ix, sh_next,
         sh_checks;
-    __shared__ double sh_S2, sh_piv, sh_S2new;
+    __shared__ double sh_S2, sh_piv, sh_S2new, sh_tsize;
 
     const AcaJob J = jobs[blockIdx.x];
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
@@ -265,6 +267,7 @@ __global__ __launch_bounds__(T) void k_aca(const double* __restrict__ pts, int64
             for (int p = 0; p < k; ++p) cross += s_a[p];
             const double S2new = sh_S2 + 2.0 * cross + tnu * tnv;
             sh_S2new = S2new;
+            sh_tsize = sqrt(tnu * tnv);
             sh_ix = ix;
             sh_next = -1;
             sh_small = (k > 0 && sqrt(tnu * tnv) <= tol * sqrt(S2new)) ? 1 : 0;
@@ -346,9 +349,11 @@ __global__ __launch_bounds__(T) void k_aca(const double* __restrict__ pts, int64
         if (tid == 0 && !sh_done) {
             sh_S2 = sh_S2new;
             sh_k = k + 1;
-            // the accepted term's pivots: row istar of A, column jstar of B
+            // the accepted term's pivots: row istar of A, column jstar of B;
+            // its size |u| |v|
             pivots[J.pv + 2 * k] = istar;
             pivots[J.pv + 2 * k + 1] = jstar;
+            tsize[J.pv / 2 + k] = sh_tsize;
             const int ix = sh_next >= 0 ? sh_next : sh_ix;
             // ix is out of range only if every untried |u_i| is non-finite
             if (sh_nused == m || ix < 0 || ix >= m)
@@ -371,6 +376,7 @@ __global__ __launch_bounds__(T) void k_aca(const double* __restrict__ pts, int64
     if (tid == 0) {
         ranks[blockIdx.x] = r;
         overflow[blockIdx.x] = ovf;
+        s2out[blockIdx.x] = sh_S2;
     }
 }
 
@@ -470,7 +476,9 @@ __global__ __launch_bounds__(T) void k_aca_coop(const double* __restrict__ pts, 
                                                 int recstride, int* doneflags,
                                                 int32_t* __restrict__ ranks,
                                                 int32_t* __restrict__ overflow,
-                                                int32_t* __restrict__ pivots) {
+                                                int32_t* __restrict__ pivots,
+                                                double* __restrict__ tsize,
+                                                double* __restrict__ s2out) {
     using namespace coop;
     extern __shared__ double dyn[];
     __shared__ double redv[NW], reds[NW];
@@ -633,7 +641,7 @@ __global__ __launch_bounds__(T) void k_aca_coop(const double* __restrict__ pts, 
         gsync();
         // ---- the candidate term's size; sampled residuals when it is small
         bool small = false;
-        double S2new = 0.0;
+        double S2new = 0.0, tsz = 0.0;
         int ix = -1;
         const int sr = min(m, kAcaSamples), str = m / sr;
         const int sc = min(n, kAcaSamples), stc = n / sc;
@@ -662,6 +670,7 @@ __global__ __launch_bounds__(T) void k_aca_coop(const double* __restrict__ pts, 
             }
             const double cross = wg_sum(cr, redv);
             S2new = S2 + 2.0 * cross + nu2 * nv2;
+            tsz = sqrt(nu2 * nv2);
             ix = (bu >= 0.0 && bui >= 0 && bui < m) ? bui : -1;
             small = k > 0 && sqrt(nu2 * nv2) <= tol * sqrt(S2new);
             if (small) {
@@ -755,6 +764,7 @@ __global__ __launch_bounds__(T) void k_aca_coop(const double* __restrict__ pts, 
                 if (wl == 0 && tid == 0) {
                     pivots[J.pv + 2 * k] = istar;
                     pivots[J.pv + 2 * k + 1] = jstar;
+                    tsize[J.pv / 2 + k] = tsz;
                 }
                 k += 1;
                 const int nx = next >= 0 ? next : ix;
@@ -773,7 +783,29 @@ __global__ __launch_bounds__(T) void k_aca_coop(const double* __restrict__ pts, 
     if (wl == 0 && tid == 0) {
         ranks[b] = k;
         overflow[b] = ovf ? 1 : 0;
+        s2out[b] = S2;
     }
+}
+
+// Precision-aware truncation of factors stored in a lower precision: the
+// trailing terms whose sizes |u_k| |v_k| add up to at most tau |S|_F (a few
+// units of the storage's rounding of the block) are dropped; their sum is a
+// bound on the Frobenius norm of what is dropped.  At least one term stays.
+__global__ void k_trunc(const AcaJob* __restrict__ jobs, int64_t njobs,
+                        const double* __restrict__ tsize, const double* __restrict__ s2,
+                        const int32_t* __restrict__ overflow, double tau,
+                        int32_t* __restrict__ ranks) {
+    const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (t >= njobs || overflow[t]) return;
+    const double* ts = tsize + jobs[t].pv / 2;
+    const double lim = tau * sqrt(fmax(s2[t], 0.0));
+    int r = ranks[t];
+    double tail = 0.0;
+    while (r > 1 && tail + ts[r - 1] <= lim) {
+        tail += ts[r - 1];
+        --r;
+    }
+    ranks[t] = r;
 }
 
 template <typename S>
@@ -914,6 +946,10 @@ struct ChunkResult {
 
 enum class AcaMode { Global, Lds, Coop };
 
+// Truncation level of FP32-stored factors: eight units of FP32 rounding
+// (2^-21), or the ACA tolerance when that is larger.
+double trunc_tau(hodlr_t h) { return std::max(h->tol, std::ldexp(1.0, -21)); }
+
 }  // namespace
 bool verbose();
 namespace {
@@ -939,6 +975,8 @@ void run_chunk(hodlr_t h, std::vector<AcaJob>& jobs, AcaMode mode, size_t lds_by
         pv_total += 2 * (size_t)j.cap;
     }
     int32_t* dpiv = (int32_t*)dalloc(h, sizeof(int32_t) * std::max<size_t>(pv_total, 1));
+    double* dts = (double*)dalloc(h, sizeof(double) * std::max<size_t>(pv_total / 2, 1));
+    double* ds2 = (double*)dalloc(h, sizeof(double) * std::max<int64_t>(nj, 1));
     AcaJob* djobs = (AcaJob*)dalloc(h, sizeof(AcaJob) * nj);
     double* ws = (double*)dalloc(h, sizeof(double) * std::max<size_t>(ws_total, 1));
     int32_t* dr = (int32_t*)dalloc(h, sizeof(int32_t) * nj);
@@ -978,7 +1016,7 @@ void run_chunk(hodlr_t h, std::vector<AcaJob>& jobs, AcaMode mode, size_t lds_by
                         (void*)&a_tol, (void*)&djobs, (void*)&a_nj,   (void*)&wpb,
                         (void*)&ws,    (void*)&dused, (void*)&duoff,  (void*)&drec,
                         (void*)&recstride, (void*)&ddone, (void*)&dr, (void*)&dov,
-                        (void*)&dpiv};
+                        (void*)&dpiv, (void*)&dts, (void*)&ds2};
         if (verbose())
             std::fprintf(stderr, "[hodlr] ACA (cooperative) %lld blocks x %d workgroups\n",
                          (long long)nj, wpb);
@@ -1000,16 +1038,21 @@ void run_chunk(hodlr_t h, std::vector<AcaJob>& jobs, AcaMode mode, size_t lds_by
         HIP_CHECK(hipFuncSetAttribute((const void*)k_aca<true>,
                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes));
         k_aca<true><<<(unsigned)nj, T, lds_bytes, s>>>(h->pts, h->N, h->d, h->kp, tol, djobs, ws,
-                                                       dr, dov, dpiv);
+                                                       dr, dov, dpiv, dts, ds2);
     } else {
         size_t small = 0;
         for (auto& j : jobs) small = std::max(small, sizeof(double) * 2 * (size_t)j.cap);
         HIP_CHECK(hipFuncSetAttribute((const void*)k_aca<false>,
                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)small));
         k_aca<false><<<(unsigned)nj, T, small, s>>>(h->pts, h->N, h->d, h->kp, tol, djobs, ws,
-                                                    dr, dov, dpiv);
+                                                    dr, dov, dpiv, dts, ds2);
     }
     HIP_CHECK(hipGetLastError());
+    // FP32 factors: drop the trailing terms below the storage's resolution
+    if (h->opts.storage == HODLR_FP32 && !h->opts.skeleton) {
+        k_trunc<<<nblk(nj, 256), 256, 0, s>>>(djobs, nj, dts, ds2, dov, trunc_tau(h), dr);
+        HIP_CHECK(hipGetLastError());
+    }
     ranks_out.resize(nj);
     ovf_out.resize(nj);
     HIP_CHECK(hipMemcpyAsync(ranks_out.data(), dr, sizeof(int32_t) * nj, hipMemcpyDeviceToHost, s));
@@ -1095,6 +1138,8 @@ void run_chunk(hodlr_t h, std::vector<AcaJob>& jobs, AcaMode mode, size_t lds_by
     dfree(h, dr);
     dfree(h, dov);
     dfree(h, dpiv);
+    dfree(h, dts);
+    dfree(h, ds2);
 }
 
 }  // namespace

@@ -181,6 +181,31 @@ hodlr_status hodlr_matvec_events(hodlr_t h, const void* X, int64_t ldx, int nrhs
  * nrhs < 1 or a bad precision. */
 hodlr_status hodlr_reserve_workspace(hodlr_t h, int nrhs, int compute_prec);
 
+/* Route of hodlr_matvec for this handle (Alg. "HODLRdD matrix-vector
+ * Product" either way): 1 = one persistent launch that walks every stage
+ * (permutation, the blocks of every level, the near field, the sums of the
+ * segmented blocks, the gather) as an ordered queue of work; 0 = one launch
+ * per stage and block size class, the near field on a second stream; -1
+ * (default, not chosen) = per-class launches.  The
+ * persistent route applies to FP64 factors in FP64 arithmetic and FP32
+ * factors in FP32 arithmetic (not BF16, not the skeleton form); other
+ * products take the per-class route whatever is set.  EINVAL for a null
+ * handle or another route. */
+hodlr_status hodlr_set_route(hodlr_t h, int route);
+
+/* Products of several handles (different point sets, sizes, dimensions and
+ * kernels) in one persistent launch: Y[t] = K~_t X[t] for t < nslots, each
+ * N_t x nrhs[t] column-major in its own user order, device pointers.  The
+ * handles must all store FP64 or all store FP32 factors (the arithmetic
+ * follows the storage) and appear once each; x_prec is that of every X and
+ * Y.  Each handle's workspace grows as hodlr_matvec's would; the call
+ * returns after the launch finished.  Calls must not overlap other calls on
+ * the same handles.  Errors: EINVAL (arguments, mixed or BF16 storage, the
+ * skeleton form, a repeated handle, factors missing), ENOMEM, EDEVICE. */
+hodlr_status hodlr_matvec_batch(int nslots, const hodlr_t* hs, const void* const* X,
+                                const int64_t* ldx, const int* nrhs, int x_prec, void* const* Y,
+                                const int64_t* ldy, void* stream);
+
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc): the
  * product of hodlr_matvec with the same arguments and result, whose

@@ -109,6 +109,8 @@ def lib():
         L.hodlr_matvec_events.argtypes = [_P, _P, _i64, C.c_int, C.c_int, _P, _i64, C.c_int, _P,
                                           C.POINTER(_P), C.c_int]
         L.hodlr_matvec_noalloc.argtypes = [_P, _P, _i64, C.c_int, C.c_int, _P, _i64, C.c_int, _P]
+        L.hodlr_set_route.argtypes = [_P, C.c_int]
+        L.hodlr_matvec_batch.argtypes = [C.c_int, _P, _P, _P, _P, C.c_int, _P, _P, _P]
         L.hodlr_get_info.argtypes = [_P, C.POINTER(Info)]
         L.hodlr_server_default_opts.argtypes = [C.POINTER(ServerOpts)]
         L.hodlr_server_default_opts.restype = None
@@ -140,6 +142,7 @@ def lib():
         L.hodlr_destroy.argtypes = [_P]
         L.hodlr_last_error.restype = C.c_char_p
         for f in ("hodlr_build", "hodlr_matvec", "hodlr_matvec_events", "hodlr_matvec_noalloc",
+                  "hodlr_set_route", "hodlr_matvec_batch",
                   "hodlr_get_info",
                   "hodlr_export_tree",
                   "hodlr_export_boxes", "hodlr_export_il", "hodlr_export_near",
@@ -256,6 +259,45 @@ def hodlr_matvec_noalloc(h: int, X, Y, compute_prec: int = FP64, stream=None) ->
     _check(lib().hodlr_matvec_noalloc(C.c_void_p(h), C.c_void_p(X.data_ptr()), ldx, nrhs, xp,
                                       C.c_void_p(Y.data_ptr()), ldy, compute_prec,
                                       _stream_ptr(stream)))
+
+
+def hodlr_set_route(h: int, route: int) -> None:
+    """1: one persistent launch per product; 0: per-stage, per-class launches;
+    -1: by size (the default)."""
+    _check(lib().hodlr_set_route(C.c_void_p(h), int(route)))
+
+
+def _cols(X):
+    if X.dim() == 1:
+        return 1, X.shape[0]
+    if X.stride(0) != 1:
+        raise ValueError("X and Y must be column-major (stride 1 along N)")
+    return X.shape[1], (X.stride(1) if X.shape[1] > 1 else X.shape[0])
+
+
+def hodlr_matvec_batch(hs, Xs, Ys, stream=None) -> None:
+    """Y[t] = K~_t X[t] for several handles in one persistent launch (device
+    tensors, all float64 or all float32; handles all FP64 or all FP32)."""
+    import torch
+    n = len(hs)
+    if not (len(Xs) == len(Ys) == n) or n < 1:
+        raise ValueError("one X and one Y per handle")
+    dt = Xs[0].dtype
+    if dt not in (torch.float64, torch.float32):
+        raise TypeError("X and Y must be float64 or float32")
+    ha = (C.c_void_p * n)(*[C.c_void_p(h) for h in hs])
+    xa = (C.c_void_p * n)(*[C.c_void_p(x.data_ptr()) for x in Xs])
+    ya = (C.c_void_p * n)(*[C.c_void_p(y.data_ptr()) for y in Ys])
+    ldx = (C.c_int64 * n)()
+    ldy = (C.c_int64 * n)()
+    nr = (C.c_int * n)()
+    for t in range(n):
+        if Xs[t].dtype != dt or Ys[t].dtype != dt or not (Xs[t].is_cuda and Ys[t].is_cuda):
+            raise TypeError("every X and Y a device tensor of one dtype")
+        nr[t], ldx[t] = _cols(Xs[t])
+        _, ldy[t] = _cols(Ys[t])
+    _check(lib().hodlr_matvec_batch(n, ha, xa, ldx, nr, FP64 if dt == torch.float64 else FP32,
+                                    ya, ldy, _stream_ptr(stream)))
 
 
 def hodlr_reserve_workspace(h: int, nrhs: int, compute_prec: int = FP64) -> None:

@@ -549,6 +549,7 @@ __global__ __launch_bounds__(T) void k_aca_coop(const double* __restrict__ pts, 
         // ---- pivot; residual of the pivot column over the owned rows
         bool zero = false;
         int jstar = INT_MAX;
+        done = __builtin_amdgcn_readfirstlane(done ? 1 : 0) != 0;
         if (!done) {
             double bv = -1.0, piv = 0.0;
             for (int w = 0; w < wpb; ++w) {
@@ -562,7 +563,8 @@ __global__ __launch_bounds__(T) void k_aca_coop(const double* __restrict__ pts, 
             }
             // no finite maximum (non-finite entries): the row counts as zero
             if (!(bv >= 0.0) || jstar < 0 || jstar >= n) piv = 0.0;
-            if (piv == 0.0) {
+            jstar = __builtin_amdgcn_readfirstlane(jstar);
+            if (__builtin_amdgcn_readfirstlane(piv == 0.0 ? 1 : 0)) {
                 zero = true;
                 if (nused == m) {
                     done = true;
@@ -645,6 +647,9 @@ __global__ __launch_bounds__(T) void k_aca_coop(const double* __restrict__ pts, 
         int ix = -1;
         const int sr = min(m, kAcaSamples), str = m / sr;
         const int sc = min(n, kAcaSamples), stc = n / sc;
+        done = __builtin_amdgcn_readfirstlane(done ? 1 : 0) != 0;
+        zero = __builtin_amdgcn_readfirstlane(zero ? 1 : 0) != 0;
+        istar = __builtin_amdgcn_readfirstlane(istar);
         if (!done && !zero) {
             double nu2 = 0.0, nv2 = 0.0, bu = -1.0;
             int bui = INT_MAX;
@@ -672,7 +677,8 @@ __global__ __launch_bounds__(T) void k_aca_coop(const double* __restrict__ pts, 
             S2new = S2 + 2.0 * cross + nu2 * nv2;
             tsz = sqrt(nu2 * nv2);
             ix = (bu >= 0.0 && bui >= 0 && bui < m) ? bui : -1;
-            small = k > 0 && sqrt(nu2 * nv2) <= tol * sqrt(S2new);
+            small = __builtin_amdgcn_readfirstlane(
+                        (k > 0 && sqrt(nu2 * nv2) <= tol * sqrt(S2new)) ? 1 : 0) != 0;
             if (small) {
                 const int offr = (int)(((int64_t)checks * 997) % str);
                 const int offc = (int)(((int64_t)checks * 991) % stc);
@@ -778,6 +784,14 @@ __global__ __launch_bounds__(T) void k_aca_coop(const double* __restrict__ pts, 
         gsync();
         bool all = true;
         for (int bb = 0; bb < njobs; ++bb) all = all && ldi(doneflags + bb) != 0;
+        // the state every lane computed alike, as scalars: the branches around
+        // the barriers are then uniform to the compiler too
+        all = __builtin_amdgcn_readfirstlane(all ? 1 : 0) != 0;
+        done = __builtin_amdgcn_readfirstlane(done ? 1 : 0) != 0;
+        k = __builtin_amdgcn_readfirstlane(k);
+        istar = __builtin_amdgcn_readfirstlane(istar);
+        nused = __builtin_amdgcn_readfirstlane(nused);
+        checks = __builtin_amdgcn_readfirstlane(checks);
         if (all) break;
     }
     if (wl == 0 && tid == 0) {

@@ -217,6 +217,42 @@ hodlr_status hodlr_matvec(hodlr_t h, const void* X, int64_t ldx, int nrhs, int x
     return matvec_checked(h, X, ldx, nrhs, x_prec, Y, ldy, compute_prec, stream, nullptr, 0);
 }
 
+hodlr_status hodlr_set_route(hodlr_t h, int route) {
+    if (!h) return set_error(HODLR_EINVAL, "null handle");
+    if (route < -1 || route > 1) return set_error(HODLR_EINVAL, "route must be -1, 0 or 1");
+    h->use_persistent = route;
+    return HODLR_OK;
+}
+
+hodlr_status hodlr_matvec_batch(int nslots, const hodlr_t* hs, const void* const* X,
+                                const int64_t* ldx, const int* nrhs, int x_prec, void* const* Y,
+                                const int64_t* ldy, void* stream) {
+    if (nslots < 1 || !hs || !X || !ldx || !nrhs || !Y || !ldy)
+        return set_error(HODLR_EINVAL, "null pointer argument or nslots < 1");
+    if (x_prec != HODLR_FP64 && x_prec != HODLR_FP32)
+        return set_error(HODLR_EINVAL, "x_prec must be FP64 or FP32");
+    for (int t = 0; t < nslots; ++t) {
+        hodlr_t h = hs[t];
+        if (!h || !X[t] || !Y[t]) return set_error(HODLR_EINVAL, "null handle or vector");
+        if (nrhs[t] < 1) return set_error(HODLR_EINVAL, "nrhs must be >= 1");
+        if (ldx[t] < h->N || ldy[t] < h->N) return set_error(HODLR_EINVAL, "leading dimension < N");
+        if (h->opts.storage != hs[0]->opts.storage || h->opts.storage == HODLR_BF16 ||
+            h->opts.skeleton)
+            return set_error(HODLR_EINVAL,
+                             "a batch takes handles with FP64 or FP32 factors of one precision, "
+                             "not the skeleton form");
+        for (int u = 0; u < t; ++u)
+            if (hs[u] == h) return set_error(HODLR_EINVAL, "a handle appears twice in the batch");
+        for (int l = 1; l <= h->kappa; ++l)
+            if (!h->lev[l].has_factors) return set_error(HODLR_EINVAL, "factors missing");
+        if (!h->near_items) return set_error(HODLR_EINVAL, "factors missing");
+    }
+    return guarded([&] {
+        hodlr::matvec_batch(nslots, hs, X, ldx, nrhs, x_prec, Y, ldy, nullptr,
+                            (hipStream_t)stream);
+    });
+}
+
 hodlr_status hodlr_matvec_noalloc(hodlr_t h, const void* X, int64_t ldx, int nrhs, int x_prec,
                                   void* Y, int64_t ldy, int compute_prec, void* stream) {
     return matvec_checked(h, X, ldx, nrhs, x_prec, Y, ldy, compute_prec, stream, nullptr, 0,

@@ -30,6 +30,7 @@ constexpr int TE = 256;   // split expansion workgroup (4 waves share 64 rows)
 constexpr int KB = 16;    // rows reduced together in the fused projection
 constexpr int kFusedMaxRank = 256;  // projections a fused wave keeps in LDS at once
 constexpr int kNumClasses = kApplyClasses;  // block size classes of the one-workgroup kernels
+constexpr int kPersistC5 = 2304;    // widest class-5 block one persistent workgroup streams
 
 
 // Cross-lane moves that stay in the vector ALU: DPP row permutations for
@@ -207,19 +208,30 @@ __global__ void k_permute_out(const float* __restrict__ yl, const float* __restr
         Y[(int64_t)(c0 + c) * ldy + u] = (XT)(yl[(int64_t)c * N + p] + yn[(int64_t)c * N + p]);
 }
 
+// Orders a wave's LDS writes before its later reads by other lanes of the
+// same wave (the LDS runs one wave's instructions in order; only the
+// compiler must not move them across).
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // One wave applies one stored block with NR right-hand sides: the
 // projections of up to RMAX terms (multi-row reductions in batches of K),
 // then their expansion re-reading the factors (cache hits); repeated over
 // chunks of RMAX terms, accumulating into the contribution segments.
+// The body works on one wave's own LDS (tw, sw: RMAX x NR each) and
+// synchronises within the wave only, so the waves of a larger workgroup can
+// each apply a block of their own.
 template <typename S, typename C, int NR, int RMAX>
-__global__ __launch_bounds__(64) void k_lr_fused(const BlockDesc* __restrict__ blocks, int sym,
-                                                 const C* __restrict__ x, int64_t N, int nrhs,
-                                                 int c0, int64_t CT, C* __restrict__ contrib) {
+__device__ __forceinline__ void lr_fused_body(const BlockDesc& b, int sym,
+                                              const C* __restrict__ x, int64_t N, int nrhs,
+                                              int c0, int64_t CT, C* __restrict__ contrib,
+                                              C (*tw)[NR], C (*sw)[NR]) {
     constexpr int K = NR == 1 ? KB : 4;
     constexpr int Q = Log2<K>::v;
-    __shared__ C tw[RMAX][NR], sw[RMAX][NR];
-    const BlockDesc b = blocks[blockIdx.x];
-    const int lane = threadIdx.x;
+    const int lane = threadIdx.x & 63;
     const gptr_t<S> U = as_global<S>(b.U);
     const gptr_t<S> V = as_global<S>(b.V);
     const int nc = min(NR, nrhs - c0);
@@ -274,7 +286,7 @@ __global__ __launch_bounds__(64) void k_lr_fused(const BlockDesc* __restrict__ b
                 }
             }
         }
-        __syncthreads();
+        wave_sync();
         // expansion of this chunk: c_A += U t (and c_B += V^T s)
         for (int i = lane; i < m; i += 64) {
             C acc[NR];
@@ -304,8 +316,16 @@ __global__ __launch_bounds__(64) void k_lr_fused(const BlockDesc* __restrict__ b
                 for (int c = 0; c < nc; ++c) contrib[(int64_t)c * CT + b.cbwd + j] = acc[c];
             }
         }
-        __syncthreads();
+        wave_sync();
     }
+}
+
+template <typename S, typename C, int NR, int RMAX>
+__global__ __launch_bounds__(64) void k_lr_fused(const BlockDesc* __restrict__ blocks, int sym,
+                                                 const C* __restrict__ x, int64_t N, int nrhs,
+                                                 int c0, int64_t CT, C* __restrict__ contrib) {
+    __shared__ C tw[RMAX][NR], sw[RMAX][NR];
+    lr_fused_body<S, C, NR, RMAX>(blocks[blockIdx.x], sym, x, N, nrhs, c0, CT, contrib, tw, sw);
 }
 
 // Single pass over a block's factors.  Each rank term k contributes
@@ -395,13 +415,13 @@ __device__ __forceinline__ void stream_step(const StreamBatch<S, C, W, CH, KB>& 
         }
 }
 
+// wv: the wave's index within the W waves applying the block (0 when W = 1,
+// whatever the wave's place in a larger workgroup)
 template <typename S, typename C, int W, int CH, int KB>
-__global__ __launch_bounds__(64 * W) void k_lr_stream(const BlockDesc* __restrict__ blocks, int sym,
-                                                      const C* __restrict__ x,
-                                                      C* __restrict__ contrib) {
-    __shared__ C part[W][2][KB];
-    const BlockDesc b = blocks[blockIdx.x];
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+__device__ __forceinline__ void lr_stream_body(const BlockDesc& b, int sym,
+                                               const C* __restrict__ x, C* __restrict__ contrib,
+                                               C (*part)[2][KB], int wv) {
+    const int lane = threadIdx.x & 63;
     const int r = b.rank, m = b.m, n = b.n;
     const gptr_t<S> U = as_global<S>(b.U);
     const gptr_t<S> V = as_global<S>(b.V);
@@ -431,6 +451,15 @@ __global__ __launch_bounds__(64 * W) void k_lr_stream(const BlockDesc* __restric
     }
 }
 
+template <typename S, typename C, int W, int CH, int KB>
+__global__ __launch_bounds__(64 * W) void k_lr_stream(const BlockDesc* __restrict__ blocks, int sym,
+                                                      const C* __restrict__ x,
+                                                      C* __restrict__ contrib) {
+    __shared__ C part[W][2][KB];
+    lr_stream_body<S, C, W, CH, KB>(blocks[blockIdx.x], sym, x, contrib, part,
+                                    W == 1 ? 0 : (int)(threadIdx.x >> 6));
+}
+
 // Reduction of G values per lane over a group of G lanes (G a power of two):
 // lane g of the group returns the group sum of row g.
 template <typename C, int G>
@@ -457,14 +486,14 @@ __device__ __forceinline__ C group_reduce_rows(C (&p)[G]) {
 // Blocks with |A|, |B|, rank <= G: a group of G lanes applies one block
 // (64/G blocks per wave).  Lane g holds column g of U^T (row g of U) in
 // registers; V is read twice, the second time from cache.
+// A 256-thread workgroup applies the blocks first .. first + 256 / G - 1.
 template <typename S, typename C, int G>
-__global__ __launch_bounds__(256) void k_lr_group(const BlockDesc* __restrict__ blocks,
-                                                  int64_t nitems, int sym,
-                                                  const C* __restrict__ x,
-                                                  C* __restrict__ contrib) {
+__device__ __forceinline__ void lr_group_body(const BlockDesc* __restrict__ blocks,
+                                              int64_t first, int64_t nitems, int sym,
+                                              const C* __restrict__ x, C* __restrict__ contrib) {
     const int g = threadIdx.x & (G - 1);
     const int base = (threadIdx.x & 63) & ~(G - 1);   // first lane of the group
-    const int64_t item = ((int64_t)blockIdx.x * 256 + threadIdx.x) / G;
+    const int64_t item = first + threadIdx.x / G;
     const bool valid = item < nitems;
     BlockDesc b{};
     if (valid) b = blocks[item];
@@ -497,6 +526,14 @@ __global__ __launch_bounds__(256) void k_lr_group(const BlockDesc* __restrict__ 
     }
     if (valid && g < m) contrib[b.cfwd + g] = ca;
     if (valid && sym && g < n) contrib[b.cbwd + g] = cb;
+}
+
+template <typename S, typename C, int G>
+__global__ __launch_bounds__(256) void k_lr_group(const BlockDesc* __restrict__ blocks,
+                                                  int64_t nitems, int sym,
+                                                  const C* __restrict__ x,
+                                                  C* __restrict__ contrib) {
+    lr_group_body<S, C, G>(blocks, (int64_t)blockIdx.x * (256 / G), nitems, sym, x, contrib);
 }
 
 // ---------------------------------------------------------------------------
@@ -915,12 +952,10 @@ __device__ __forceinline__ void row_dot(gptr_t<S> row, int len,
 }
 
 template <typename S, typename C, int NR>
-__global__ __launch_bounds__(TP) void k_project(const BlockDesc* __restrict__ blocks,
-                                                const ProjSeg* __restrict__ items, int sym,
-                                                const C* __restrict__ x, int64_t N, int nrhs,
-                                                int c0, C* __restrict__ part) {
-    __shared__ C red[TP / 64][NR];
-    const ProjSeg it = items[blockIdx.x];
+__device__ __forceinline__ void project_body(const BlockDesc* __restrict__ blocks,
+                                             const ProjSeg& it, int sym,
+                                             const C* __restrict__ x, int64_t N, int nrhs,
+                                             int c0, C* __restrict__ part, C (*red)[NR]) {
     const BlockDesc b = blocks[it.blk];
     const int nc = min(NR, nrhs - c0);
     const int k = it.k;
@@ -943,41 +978,57 @@ __global__ __launch_bounds__(TP) void k_project(const BlockDesc* __restrict__ bl
     }
 }
 
+template <typename S, typename C, int NR>
+__global__ __launch_bounds__(TP) void k_project(const BlockDesc* __restrict__ blocks,
+                                                const ProjSeg* __restrict__ items, int sym,
+                                                const C* __restrict__ x, int64_t N, int nrhs,
+                                                int c0, C* __restrict__ part) {
+    __shared__ C red[TP / 64][NR];
+    project_body<S, C, NR>(blocks, items[blockIdx.x], sym, x, N, nrhs, c0, part, red);
+}
+
 // t_k (and s_k) of the segmented projections: the partials summed in segment
 // order, one thread per (term, side, column)
-template <typename C, int NR>
-__global__ void k_proj_sum(const ProjSum* __restrict__ sums, int64_t nsum, int sym, int nc,
-                           const C* __restrict__ part, int64_t TT, C* __restrict__ tb,
-                           C* __restrict__ sb) {
-    const int64_t t = blockIdx.x * (int64_t)256 + threadIdx.x;
+// thread t of the nsum * 2 * NR (term, side, column) sums; part read through
+// P (a plain or a device-coherent load)
+template <typename C, int NR, typename P>
+__device__ __forceinline__ void proj_sum_body(int64_t t, const ProjSum* __restrict__ sums,
+                                              int64_t nsum, int sym, int nc, P part, int64_t TT,
+                                              C* __restrict__ tb, C* __restrict__ sb) {
     if (t >= nsum * 2 * NR) return;
     const int c = (int)(t % NR), side = (int)((t / NR) & 1);
     const int64_t i = t / (2 * NR);
     if (c >= nc || (side == 1 && !sym)) return;
     const ProjSum S = sums[i];
-    const C* __restrict__ pp = part + (S.p * 2 + side) * kProjSegMax * NR + c;
+    const int64_t pp = (S.p * 2 + side) * kProjSegMax * NR + c;
     C v = 0;
-    for (int g = 0; g < S.nseg; ++g) v += pp[(int64_t)g * NR];
+    for (int g = 0; g < S.nseg; ++g) v += part(pp + (int64_t)g * NR);
     (side ? sb : tb)[(int64_t)c * TT + S.dst] = v;
+}
+
+template <typename C, int NR>
+__global__ void k_proj_sum(const ProjSum* __restrict__ sums, int64_t nsum, int sym, int nc,
+                           const C* __restrict__ part, int64_t TT, C* __restrict__ tb,
+                           C* __restrict__ sb) {
+    proj_sum_body<C, NR>(blockIdx.x * (int64_t)256 + threadIdx.x, sums, nsum, sym, nc,
+                         [part](int64_t i) { return part[i]; }, TT, tb, sb);
 }
 
 // 64-row chunk of one side of a large block: side 0 writes U t into the rows
 // of A, side 1 writes V^T s into the rows of B; the 4 waves split the terms
-template <typename S, typename C, int NR>
-__global__ __launch_bounds__(TE) void k_expand_split(const BlockDesc* __restrict__ blocks,
-                                                     const WorkItem* __restrict__ items, int nrhs,
-                                                     int c0, int64_t TT, const C* __restrict__ tb,
-                                                     const C* __restrict__ sb, int64_t CT,
-                                                     C* __restrict__ contrib) {
-    __shared__ C part[TE / 64][NR][64];
-    const WorkItem it = items[blockIdx.x];
+// coefficients (t or s) read through P (a plain or a device-coherent load)
+template <typename S, typename C, int NR, typename P>
+__device__ __forceinline__ void expand_split_body(const BlockDesc* __restrict__ blocks,
+                                                  const WorkItem& it, int nrhs, int c0,
+                                                  int64_t TT, P tbs, int64_t CT,
+                                                  C* __restrict__ contrib, C (*part)[NR][64]) {
     const BlockDesc b = blocks[it.id];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const bool tr = it.level != 0;
     const gptr_t<S> W = as_global<S>(tr ? b.V : b.U);
     const int len = tr ? b.n : b.m;
     const int64_t ld = fstride<S>(len);
-    const C* __restrict__ coef = (tr ? sb : tb) + b.toff;
+    const int side = tr ? 1 : 0;
     const int o = it.lo + lane;
     const bool active = lane < it.cnt;
     const int nc = min(NR, nrhs - c0);
@@ -988,7 +1039,7 @@ __global__ __launch_bounds__(TE) void k_expand_split(const BlockDesc* __restrict
         for (int k = wv; k < b.rank; k += TE / 64) {
             const C w = ldf<C>(W, (int64_t)k * ld + o);
 #pragma unroll
-            for (int c = 0; c < NR; ++c) acc[c] += w * coef[(int64_t)c * TT + k];
+            for (int c = 0; c < NR; ++c) acc[c] += w * tbs(side, (int64_t)c * TT + b.toff + k);
         }
     }
 #pragma unroll
@@ -1002,6 +1053,18 @@ __global__ __launch_bounds__(TE) void k_expand_split(const BlockDesc* __restrict
             contrib[(int64_t)c * CT + seg + o] = s;
         }
     }
+}
+
+template <typename S, typename C, int NR>
+__global__ __launch_bounds__(TE) void k_expand_split(const BlockDesc* __restrict__ blocks,
+                                                     const WorkItem* __restrict__ items, int nrhs,
+                                                     int c0, int64_t TT, const C* __restrict__ tb,
+                                                     const C* __restrict__ sb, int64_t CT,
+                                                     C* __restrict__ contrib) {
+    __shared__ C part[TE / 64][NR][64];
+    expand_split_body<S, C, NR>(
+        blocks, items[blockIdx.x], nrhs, c0, TT,
+        [tb, sb](int side, int64_t i) { return side ? sb[i] : tb[i]; }, CT, contrib, part);
 }
 
 // rows [lo, lo+cnt) of one leaf: near field on the fly plus the low-rank
@@ -1019,18 +1082,45 @@ constexpr int kNearTile = 256;         // sources per LDS tile
 constexpr int kNearTileRanges = 1024;  // near boxes a tiled leaf may have
 constexpr int kNearFused = 0, kNearOnly = 1, kGatherOnly = 2;
 
-template <typename XT, typename C, int NR, int KIND = -1, int MODE = kNearFused>
-__global__ __launch_bounds__(TG) void k_gather_near(
-    const NearItem* __restrict__ items, int64_t nitems, const SegRef* __restrict__ lseg,
+// one LDS record per near-field source: its coordinates, and for d <= 3 with
+// one right-hand side its x value in the fourth slot
+template <typename C>
+struct alignas(4 * sizeof(C)) NearRec {
+    C v[4];
+};
+// the near-field body's LDS (one set per kernel, shared by every
+// instantiation of the body inside it)
+template <typename C, int NR>
+struct NearLds {
+    int pre[kNearTileRanges + 1];
+    int rs[kNearTileRanges];
+    NearRec<C> pt[kNearTile];
+    C x[NR][kNearTile];
+};
+
+// One item (rows of one leaf) of the near-field / gather kernel below.  CO:
+// read data that other workgroups of the same launch produced (x, the
+// contributions, the near sums) with device-coherent loads.
+template <typename XT, typename C, int NR, int KIND, int MODE, bool CO = false>
+__device__ __forceinline__ void gather_near_item(
+    const NearItem& it, const SegRef* __restrict__ lseg,
     const int2* __restrict__ nrng, int kappa, const double* __restrict__ pts, int64_t N, int d,
-    KParams kp, const C* __restrict__ x, const C* __restrict__ contrib, int64_t CT,
+    KParams kp, const C* x, const C* contrib, int64_t CT,
     const int32_t* __restrict__ perm, int nrhs, int c0, XT* __restrict__ Y, int64_t ldy,
-    const C* __restrict__ ylev, C* __restrict__ yn) {
-    __shared__ C red[TG / 64][NR][64];
-    // a grid smaller than the item count loops over the items: a capped grid
-    // keeps the kernel to a share of every CU while it runs beside others
-    for (int64_t bi = blockIdx.x; bi < nitems; bi += gridDim.x) {
-        const NearItem it = items[bi];
+    const C* __restrict__ ylev, C* yn, C (*red)[NR][64], NearLds<C, NR>& L) {
+    auto ldx = [&](int64_t i) -> C {
+        if constexpr (CO)
+            return __hip_atomic_load(x + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        else
+            return x[i];
+    };
+    auto ldc = [&](const C* p) -> C {
+        if constexpr (CO)
+            return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        else
+            return *p;
+    };
+    {
         // the wave index as a scalar: loop bounds built from it stay wave-uniform
         const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
         int mp = 1;
@@ -1052,18 +1142,15 @@ __global__ __launch_bounds__(TG) void k_gather_near(
             if (active && sg == 0)
 #pragma unroll
                 for (int c = 0; c < NR; ++c)
-                    if (c < nc) acc[c] = yn[(int64_t)c * N + i];
+                    if (c < nc) acc[c] = ldc(yn + (int64_t)c * N + i);
         } else if (d <= 4 && it.nn <= kNearTileRanges) {
             // sources staged through LDS in tiles: coalesced cooperative loads,
             // then every lane reads them as broadcasts
-            __shared__ int s_pre[kNearTileRanges + 1], s_rs[kNearTileRanges];
-            struct alignas(4 * sizeof(C)) C4 {
-                C v[4];
-            };
-            // one record per source: its coordinates, and for d <= 3 with one
-            // right-hand side its x value in the fourth slot (one LDS read)
-            __shared__ C4 s_pt[kNearTile];
-            __shared__ C s_x[NR][kNearTile];
+            int* s_pre = L.pre;
+            int* s_rs = L.rs;
+            using C4 = NearRec<C>;
+            C4* s_pt = L.pt;
+            C (*s_x)[kNearTile] = L.x;
             const bool packx = NR == 1 && d <= 3;
             // coordinates in the compute type: FP64 as they are; FP32 relative to
             // the leaf's first point, so that differences of nearby points keep
@@ -1156,10 +1243,10 @@ __global__ __launch_bounds__(TG) void k_gather_near(
 #pragma unroll
                     for (int a = 0; a < 4; ++a) pq.v[a] = a < d ? (C)(pts[a * N + j] - ref[a]) : (C)0;
                     if (packx) {
-                        pq.v[3] = x[(int64_t)c0 * N + j];
+                        pq.v[3] = ldx((int64_t)c0 * N + j);
                     } else {
 #pragma unroll
-                        for (int c = 0; c < NR; ++c) s_x[c][q] = c < nc ? x[(int64_t)(c0 + c) * N + j] : (C)0;
+                        for (int c = 0; c < NR; ++c) s_x[c][q] = c < nc ? ldx((int64_t)(c0 + c) * N + j) : (C)0;
                     }
                     s_pt[q] = pq;
                 }
@@ -1189,7 +1276,7 @@ __global__ __launch_bounds__(TG) void k_gather_near(
                     }
 #pragma unroll
                     for (int c = 0; c < NR; ++c)
-                        if (c < nc) acc[c] += kij * x[(int64_t)(c0 + c) * N + j];
+                        if (c < nc) acc[c] += kij * ldx((int64_t)(c0 + c) * N + j);
                 }
             }
         }
@@ -1204,12 +1291,12 @@ __global__ __launch_bounds__(TG) void k_gather_near(
                 const int64_t off = i - it.leaf0;
                 for (int l = 0; l < kappa; ++l) {
                     const SegRef sr = lseg[(int64_t)it.leaf * kappa + l];
-                    const C* __restrict__ seg = contrib + sr.base + off;
+                    const C* seg = contrib + sr.base + off;
 #pragma unroll 4
                     for (int64_t e = sg; e < sr.ne; e += SG)
 #pragma unroll
                         for (int c = 0; c < NR; ++c)
-                            if (c < nc) acc[c] += seg[(int64_t)c * CT + e * sr.len];
+                            if (c < nc) acc[c] += ldc(seg + (int64_t)c * CT + e * sr.len);
                 }
             }
         }
@@ -1231,6 +1318,23 @@ __global__ __launch_bounds__(TG) void k_gather_near(
         }
         __syncthreads();   // LDS is reused by the next item
     }
+}
+
+template <typename XT, typename C, int NR, int KIND = -1, int MODE = kNearFused>
+__global__ __launch_bounds__(TG) void k_gather_near(
+    const NearItem* __restrict__ items, int64_t nitems, const SegRef* __restrict__ lseg,
+    const int2* __restrict__ nrng, int kappa, const double* __restrict__ pts, int64_t N, int d,
+    KParams kp, const C* __restrict__ x, const C* __restrict__ contrib, int64_t CT,
+    const int32_t* __restrict__ perm, int nrhs, int c0, XT* __restrict__ Y, int64_t ldy,
+    const C* __restrict__ ylev, C* __restrict__ yn) {
+    __shared__ C red[TG / 64][NR][64];
+    __shared__ NearLds<C, NR> lds;
+    // a grid smaller than the item count loops over the items: a capped grid
+    // keeps the kernel to a share of every CU while it runs beside others
+    for (int64_t bi = blockIdx.x; bi < nitems; bi += gridDim.x)
+        gather_near_item<XT, C, NR, KIND, MODE>(items[bi], lseg, nrng, kappa, pts, N, d, kp, x,
+                                                contrib, CT, perm, nrhs, c0, Y, ldy, ylev, yn,
+                                                red, lds);
 }
 
 // Skeleton form (eqs. keq1/keq2): a stored block is its ACA pivots sigma
@@ -1544,6 +1648,284 @@ __global__ __launch_bounds__(256) void k_near_mfma(
     }
 }
 
+// ---------------------------------------------------------------------------
+// Persistent product: one launch runs every stage of the products of one or
+// more handles ("slots") by walking an ordered queue of claims.
+//
+// The host lists segments in stage order: the permutation into tree order,
+// then per batch of NR columns the low-rank blocks of every class with the
+// segmented projections and the near field, the sums of the segmented
+// projections, their expansions, and the gather to Y.  A workgroup claims
+// the next claim index with one atomic add; the claim names a segment and a
+// few items in it.  Before working on it the workgroup waits until every
+// claim of the earlier stages has completed, counted by a single completion
+// counter: claims are handed out in order and a claim of stage p completes
+// only after all claims of earlier stages did, so "completed claims >= first
+// claim of stage p" holds exactly when the earlier stages are done.  A
+// waiting workgroup only waits on claims handed out before its own, which
+// running workgroups hold, so the queue drains whatever the grid.  The wait
+// is bounded (an error flag instead of a hang).  Writes are released at
+// device scope before a claim is counted and acquired after a wait, and
+// values written inside the launch are read back through device-coherent
+// loads.  The last workgroup to leave resets the counters for the next
+// launch, so no clearing launch precedes it.
+// ---------------------------------------------------------------------------
+enum PKind : int32_t {
+    PK_PERM = 0,   // x = X[perm], 256 rows of every column per item
+    PK_G8,         // class 0: 32 blocks per claim (groups of 8 lanes)
+    PK_G16,        // class 1: 16 blocks per claim
+    PK_S2,         // class 2: one block per wave
+    PK_S3,         // class 3: one block per wave
+    PK_S4,         // class 4: one block per claim
+    PK_S5,         // class 5 (at most kPersistC5 rows and columns): one block per claim
+    PK_FUSED,      // NR > 1: any class, one block per wave
+    PK_PROJ,       // segmented projections
+    PK_NEAR,       // near field of a 64-row leaf chunk, into the near sums
+    PK_PSUM,       // sums of the segmented projections, 256 per claim
+    PK_EXP,        // 64-row expansion of a segmented block
+    PK_GATHER,     // near sums plus contributions of a leaf chunk, to Y
+};
+
+struct PSlot {
+    const BlockDesc* cblk;   // persistent class order
+    const BlockDesc* blocks;
+    const ProjSeg* proj;
+    const ProjSum* psum;
+    const WorkItem* ex;
+    const NearItem* near;
+    const SegRef* lseg;
+    const int2* nrng;
+    const double* pts;
+    const int32_t* perm;
+    const void* X;
+    void* Y;
+    void* x;
+    void* contrib;
+    void* tb;
+    void* sb;
+    void* pp;
+    void* yn;
+    KParams kp;
+    int64_t N, ldx, ldy, CT, TT, npsum;
+    int32_t d, kappa, sym, nrhs;
+};
+
+struct PSeg {
+    int64_t claim0;        // first claim index of the segment
+    int64_t need;          // claims that must have completed before it starts
+    int64_t first, nitems; // items [first, first + nitems) of the slot's table
+    int32_t slot, kind, c0, per;
+};
+
+constexpr int kPersistThreads = 256;
+constexpr int kPersistFusedRank = 64;       // projections one wave keeps in LDS at once
+// longest wait of one claim for the earlier stages: 1 s of the 100 MHz
+// constant-rate clock
+constexpr uint64_t kPersistWaitTicks = 100000000ull;
+
+// a value every lane holds alike, as a scalar: the compiler then treats the
+// branches that depend on it as uniform, so the barriers inside them are
+// executed by every wave alike
+__device__ __forceinline__ int64_t uniform64(int64_t v) {
+    const int lo = __builtin_amdgcn_readfirstlane((int)(v & 0xffffffffLL));
+    const int hi = __builtin_amdgcn_readfirstlane((int)(v >> 32));
+    return ((int64_t)hi << 32) | (uint32_t)lo;
+}
+
+template <typename C>
+__device__ __forceinline__ C ld_co(const C* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <typename XT, typename S, int NR>
+__global__ __launch_bounds__(kPersistThreads) void k_persist(const PSlot* __restrict__ slots,
+                                                             const PSeg* __restrict__ segs,
+                                                             int nseg, int64_t nclaims,
+                                                             int* ctr) {
+    using C = S;
+    constexpr int KB4 = sizeof(C) == 8 ? 2 : 4;
+    constexpr int KB5 = sizeof(C) == 8 ? 1 : 2;
+    __shared__ int64_t s_claim;
+    __shared__ C s_part[4][2][4];
+    __shared__ C s_red[TG / 64][NR][64];
+    __shared__ C s_pred[TP / 64][NR];
+    __shared__ C s_tw[NR > 1 ? 4 : 1][NR > 1 ? kPersistFusedRank : 1][NR];
+    __shared__ C s_sw[NR > 1 ? 4 : 1][NR > 1 ? kPersistFusedRank : 1][NR];
+    __shared__ NearLds<C, NR> s_near;
+    const int tid = threadIdx.x, lane = tid & 63;
+    // the wave index as a scalar: a branch on it is uniform within each wave
+    const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+    // No branch that splits the lanes of a wave may enclose or border the
+    // workgroup barriers of this loop (the compiler would give the lanes of a
+    // wave separate trips through them): wave 0 as a whole claims, waits
+    // and counts, with lane-dependent values instead of lane conditions.
+    for (;;) {
+        if (wv == 0) {
+            const int old = atomicAdd(ctr + 0, lane == 0 ? 1 : 0);
+            s_claim = (int64_t)__builtin_amdgcn_readfirstlane(old);
+        }
+        __syncthreads();
+        // the claim, and everything decided from it below, is uniform
+        const int64_t g = uniform64(s_claim);
+        __syncthreads();
+        if (g >= nclaims) break;
+        // the segment holding claim g
+        int lo = 0, hi = nseg - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (segs[mid].claim0 <= g)
+                lo = mid;
+            else
+                hi = mid - 1;
+        }
+        const PSeg sg = segs[lo];
+        const PSlot& sl = slots[sg.slot];
+        const int64_t i0 = sg.first + (g - sg.claim0) * sg.per;
+        const int64_t i1 = min(i0 + sg.per, sg.first + sg.nitems);
+        // earlier stages complete?
+        if (sg.need > 0) {
+            if (wv == 0) {
+                // wave 0 polls; the wait is bounded by the wall clock, and a
+                // timed-out wait anywhere ends every wait (wrong results and a
+                // flag the host reads, instead of a hang)
+                const long long t0 = wall_clock64();
+                for (;;) {
+                    const int done = __builtin_amdgcn_readfirstlane(__hip_atomic_load(
+                        ctr + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+                    if (done >= sg.need) break;
+                    const int abort = __builtin_amdgcn_readfirstlane(__hip_atomic_load(
+                        ctr + 3, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+                    const bool late = (uint64_t)(wall_clock64() - t0) > kPersistWaitTicks;
+                    if (abort || late) {
+                        const int prev = __builtin_amdgcn_readfirstlane(__hip_atomic_fetch_or(
+                            ctr + 3, lane == 0 ? 1 : 0, __ATOMIC_RELAXED,
+                            __HIP_MEMORY_SCOPE_AGENT));
+                        if (prev == 0) {
+                            // the first timeout: which claim waited for what
+                            ctr[4] = (int)g;
+                            ctr[5] = (int)sg.need;
+                            ctr[6] = done;
+                        }
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(8);
+                }
+            }
+            __syncthreads();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        }
+        const C* x = (const C*)sl.x;
+        C* contrib = (C*)sl.contrib;
+        switch (sg.kind) {
+        case PK_PERM: {
+            const XT* X = (const XT*)sl.X;
+            C* xw = (C*)sl.x;
+            const int64_t p = i0 * 256 + tid;
+            if (p < sl.N) {
+                const int64_t u = sl.perm[p];
+                for (int c = 0; c < sl.nrhs; ++c) xw[c * sl.N + p] = (C)X[c * sl.ldx + u];
+            }
+            break;
+        }
+        case PK_G8:
+            lr_group_body<S, C, 8>(sl.cblk, i0, i1, sl.sym, x, contrib);
+            break;
+        case PK_G16:
+            lr_group_body<S, C, 16>(sl.cblk, i0, i1, sl.sym, x, contrib);
+            break;
+        case PK_S2:
+            if (i0 + wv < i1)
+                lr_stream_body<S, C, 1, 1, 8>(sl.cblk[i0 + wv], sl.sym, x, contrib, nullptr, 0);
+            break;
+        case PK_S3:
+            if (i0 + wv < i1)
+                lr_stream_body<S, C, 1, 2, 4>(sl.cblk[i0 + wv], sl.sym, x, contrib, nullptr, 0);
+            break;
+        case PK_S4:
+            lr_stream_body<S, C, 4, 4, KB4>(sl.cblk[i0], sl.sym, x, contrib,
+                                            reinterpret_cast<C(*)[2][KB4]>(s_part), wv);
+            break;
+        case PK_S5:
+            lr_stream_body<S, C, 4, 9, KB5>(sl.cblk[i0], sl.sym, x, contrib,
+                                            reinterpret_cast<C(*)[2][KB5]>(s_part), wv);
+            break;
+        case PK_FUSED:
+            if constexpr (NR > 1) {
+                if (i0 + wv < i1)
+                    lr_fused_body<S, C, NR, kPersistFusedRank>(sl.cblk[i0 + wv], sl.sym, x, sl.N,
+                                                               sl.nrhs, sg.c0, sl.CT, contrib,
+                                                               s_tw[wv], s_sw[wv]);
+            }
+            break;
+        case PK_PROJ:
+            project_body<S, C, NR>(sl.blocks, sl.proj[i0], sl.sym, x, sl.N, sl.nrhs, sg.c0,
+                                   (C*)sl.pp, s_pred);
+            break;
+        case PK_PSUM: {
+            const C* pp = (const C*)sl.pp;
+            proj_sum_body<C, NR>(i0 * 256 + tid, sl.psum, sl.npsum, sl.sym,
+                                 min(NR, sl.nrhs - sg.c0),
+                                 [pp](int64_t i) { return ld_co(pp + i); }, sl.TT, (C*)sl.tb,
+                                 (C*)sl.sb);
+            break;
+        }
+        case PK_EXP: {
+            const C* tb = (const C*)sl.tb;
+            const C* sb = (const C*)sl.sb;
+            expand_split_body<S, C, NR>(
+                sl.blocks, sl.ex[i0], sl.nrhs, sg.c0, sl.TT,
+                [tb, sb](int side, int64_t i) { return ld_co((side ? sb : tb) + i); }, sl.CT,
+                contrib, s_red);
+            break;
+        }
+        case PK_NEAR:
+            switch (sl.kp.kind) {
+#define HODLR_PNEAR(K)                                                                          \
+    case K:                                                                                     \
+        gather_near_item<XT, C, NR, K, kNearOnly, true>(                                        \
+            sl.near[i0], sl.lseg, sl.nrng, sl.kappa, sl.pts, sl.N, sl.d, sl.kp, x, contrib,     \
+            sl.CT, sl.perm, sl.nrhs, sg.c0, (XT*)sl.Y, sl.ldy, nullptr, (C*)sl.yn, s_red,       \
+            s_near);                                                                            \
+        break;
+                HODLR_PNEAR(HODLR_K_LOG)
+                HODLR_PNEAR(HODLR_K_INV_R)
+                HODLR_PNEAR(HODLR_K_INV_R2)
+                HODLR_PNEAR(HODLR_K_GAUSS)
+                HODLR_PNEAR(HODLR_K_EXP)
+                HODLR_PNEAR(HODLR_K_R)
+                HODLR_PNEAR(HODLR_K_SIN)
+                default:
+                HODLR_PNEAR(HODLR_K_INV_SQRT1P)
+#undef HODLR_PNEAR
+            }
+            break;
+        case PK_GATHER:
+            gather_near_item<XT, C, NR, -1, kGatherOnly, true>(
+                sl.near[i0], sl.lseg, sl.nrng, sl.kappa, sl.pts, sl.N, sl.d, sl.kp, x, contrib,
+                sl.CT, sl.perm, sl.nrhs, sg.c0, (XT*)sl.Y, sl.ldy, nullptr, (C*)sl.yn, s_red,
+                s_near);
+            break;
+        default:
+            break;
+        }
+        // release this claim's writes, then count it
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        __syncthreads();
+        if (wv == 0)
+            __hip_atomic_fetch_add(ctr + 1, lane == 0 ? 1 : 0, __ATOMIC_RELEASE,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+    }
+    // the last workgroup out resets the counters (claim, done, exit)
+    if (tid == 0) {
+        if (__hip_atomic_fetch_add(ctr + 2, 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) ==
+            (int)gridDim.x - 1) {
+            __hip_atomic_store(ctr + 0, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(ctr + 1, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(ctr + 2, 0, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+}
+
 }  // namespace
 
 // Factor words: the projection pass reads terms up to r16(r) + 15 (the
@@ -1603,6 +1985,25 @@ void plan_apply(hodlr_t h) {
     std::vector<std::vector<std::pair<int64_t, int32_t>>> cls(kNumClasses);
     for (int c = 0; c < 8; ++c) h->cls_felems[c] = h->cls_velems[c] = 0;
     h->split_blocks = h->split_felems = 0;
+    // the segmented route of block b: projections per term and row segment
+    // (segments of at least 4096 rows so that enough workgroups stream the
+    // few large blocks at once), their per-term sums, 64-row expansions
+    auto add_split = [&](int64_t b, std::vector<ProjSeg>& pj, std::vector<ProjSum>& ps,
+                         std::vector<WorkItem>& xe) {
+        const BlockDesc& bd = h->hblocks[b];
+        const int nseg = std::max(1, std::min(kProjSegMax, std::max(bd.m, bd.n) / 4096));
+        for (int k = 0; k < bd.rank; ++k) {
+            const int64_t pidx = (int64_t)ps.size();
+            ps.push_back(ProjSum{bd.toff + k, pidx, nseg, 0});
+            for (int g = 0; g < nseg; ++g) pj.push_back(ProjSeg{(int32_t)b, k, g, nseg, pidx});
+        }
+        for (int32_t i = 0; i < bd.m; i += 64)
+            xe.push_back(WorkItem{(int32_t)b, i, std::min(64, bd.m - i), 0});
+        if (h->opts.symmetric)
+            for (int32_t j = 0; j < bd.n; j += 64)
+                xe.push_back(WorkItem{(int32_t)b, j, std::min(64, bd.n - j), 1});
+    };
+    std::vector<int64_t> split_ids;
     for (int64_t b = 0; b < h->nblocks; ++b) {
         const BlockDesc& bd = h->hblocks[b];
         const int64_t el = (int64_t)std::max(bd.rank, 0) * (bd.m + bd.n);
@@ -1623,19 +2024,8 @@ void plan_apply(hodlr_t h) {
         } else {
             ++h->split_blocks;
             h->split_felems += el;
-            // rows split into segments of at least 4096 so that enough
-            // workgroups stream the few large blocks at once
-            const int nseg = std::max(1, std::min(kProjSegMax, std::max(bd.m, bd.n) / 4096));
-            for (int k = 0; k < bd.rank; ++k) {
-                const int64_t pidx = (int64_t)psum.size();
-                psum.push_back(ProjSum{bd.toff + k, pidx, nseg, 0});
-                for (int g = 0; g < nseg; ++g) proj.push_back(ProjSeg{(int32_t)b, k, g, nseg, pidx});
-            }
-            for (int32_t i = 0; i < bd.m; i += 64)
-                ex.push_back(WorkItem{(int32_t)b, i, std::min(64, bd.m - i), 0});
-            if (h->opts.symmetric)
-                for (int32_t j = 0; j < bd.n; j += 64)
-                    ex.push_back(WorkItem{(int32_t)b, j, std::min(64, bd.n - j), 1});
+            split_ids.push_back(b);
+            add_split(b, proj, psum, ex);
         }
     }
     // largest first inside a class so the long workgroups start early
@@ -1648,6 +2038,25 @@ void plan_apply(hodlr_t h) {
         for (auto& p : cls[c]) grp.push_back(p.second);
     }
     h->class_off[kNumClasses] = (int64_t)grp.size();
+    // the persistent plan: the same classes in the same order, except the
+    // class-5 blocks wider than kPersistC5 (they join the segmented route)
+    std::vector<int32_t> pgrp;
+    std::vector<ProjSeg> pproj;
+    std::vector<ProjSum> ppsum;
+    std::vector<WorkItem> pex;
+    h->p_class_off.assign(kNumClasses + 1, 0);
+    for (int c = 0; c < kNumClasses; ++c) {
+        h->p_class_off[c] = (int64_t)pgrp.size();
+        for (auto& pr : cls[c]) {
+            const BlockDesc& bd = h->hblocks[pr.second];
+            if (c == kNumClasses - 1 && std::max(bd.m, bd.n) > kPersistC5)
+                add_split(pr.second, pproj, ppsum, pex);
+            else
+                pgrp.push_back(pr.second);
+        }
+    }
+    h->p_class_off[kNumClasses] = (int64_t)pgrp.size();
+    for (int64_t b : split_ids) add_split(b, pproj, ppsum, pex);
     // leaves: 64-row chunks, their near-field source ranges and, per level,
     // the contribution segments of the box containing them.  A leaf is a
     // leaf box of any level (in a uniform tree: the boxes of level kappa);
@@ -1737,6 +2146,17 @@ void plan_apply(hodlr_t h) {
     upload(nr.data(), sizeof(NearItem) * nr.size(), (void**)&h->near_items);
     h->n_near_items = (int64_t)nr.size();
     upload(rng.data(), sizeof(int2) * rng.size(), (void**)&h->near_rng);
+    {
+        std::vector<BlockDesc> pbd(pgrp.size());
+        for (size_t t = 0; t < pgrp.size(); ++t) pbd[t] = h->hblocks[pgrp[t]];
+        upload(pbd.data(), sizeof(BlockDesc) * pbd.size(), (void**)&h->p_class_blocks);
+        upload(pproj.data(), sizeof(ProjSeg) * pproj.size(), (void**)&h->p_proj);
+        upload(ppsum.data(), sizeof(ProjSum) * ppsum.size(), (void**)&h->p_psum);
+        upload(pex.data(), sizeof(WorkItem) * pex.size(), (void**)&h->p_exp);
+        h->p_n_proj = (int64_t)pproj.size();
+        h->p_n_psum = (int64_t)ppsum.size();
+        h->p_n_exp = (int64_t)pex.size();
+    }
     upload(seg.data(), sizeof(SegRef) * seg.size(), (void**)&h->leaf_seg);
     h->nleaf = nleaf;
     // matrix-core plan for BF16 factors (several right-hand sides)
@@ -1903,7 +2323,7 @@ void run_matvec(hodlr_t h, const XT* X, int64_t ldx, int nrhs, XT* Y, int64_t ld
     C* tb = contrib + CT * NR;
     C* sb = tb + TT * NR;
     C* pp = sb + TT * NR;   // partials of the segmented projections
-    C* yn = pp + 2 * kProjSegMax * h->n_proj_sums * NR;   // near-field sums
+    C* yn = pp + 2 * kProjSegMax * std::max(h->n_proj_sums, h->p_n_psum) * NR;   // near sums
     const int sym = h->opts.symmetric ? 1 : 0;
     // the second stream starts after everything issued so far on s, and s
     // waits for all of its work at the join
@@ -2165,6 +2585,163 @@ void dispatch_nr(hodlr_t h, const XT* X, int64_t ldx, int nrhs, XT* Y, int64_t l
         run_matvec<XT, S, C, 8>(h, X, ldx, nrhs, Y, ldy, ws, ev, nev, s, aux);
 }
 
+// ---- persistent product: host side -------------------------------------
+// One slot: a handle's product of nrhs columns, X -> Y, with the workspace
+// carved as in run_matvec.
+struct PSlotHost {
+    hodlr_t h;
+    const void* X;
+    int64_t ldx;
+    void* Y;
+    int64_t ldy;
+    int nrhs;
+    char* ws;
+};
+
+// The claim queue of a persistent launch (stage order, see k_persist).
+void persist_segments(const std::vector<PSlotHost>& sl, int NR, std::vector<PSeg>& segs,
+                      int64_t& nclaims) {
+    segs.clear();
+    int64_t claim = 0;
+    auto add = [&](int slot, int kind, int c0, int64_t first, int64_t n, int per, int64_t need) {
+        if (n <= 0) return;
+        segs.push_back(PSeg{claim, need, first, n, slot, kind, c0, per});
+        claim += (n + per - 1) / per;
+    };
+    int maxcb = 0;
+    for (auto& q : sl) maxcb = std::max(maxcb, (q.nrhs + NR - 1) / NR);
+    for (int t = 0; t < (int)sl.size(); ++t) add(t, PK_PERM, 0, 0, (sl[t].h->N + 255) / 256, 1, 0);
+    for (int cb = 0; cb < maxcb; ++cb) {
+        const int c0 = cb * NR;
+        int64_t need = claim;
+        for (int t = 0; t < (int)sl.size(); ++t) {
+            hodlr_t h = sl[t].h;
+            if (sl[t].nrhs <= c0) continue;
+            const std::vector<int64_t>& o = h->p_class_off;
+            add(t, PK_PROJ, c0, 0, h->p_n_proj, 1, need);
+            if (NR == 1) {
+                add(t, PK_S5, c0, o[5], o[6] - o[5], 1, need);
+                add(t, PK_S4, c0, o[4], o[5] - o[4], 1, need);
+            } else {
+                add(t, PK_FUSED, c0, o[0], o[6] - o[0], 4, need);
+            }
+            add(t, PK_NEAR, c0, 0, h->n_near_items, 1, need);
+            if (NR == 1) {
+                add(t, PK_S3, c0, o[3], o[4] - o[3], 4, need);
+                add(t, PK_S2, c0, o[2], o[3] - o[2], 4, need);
+                add(t, PK_G16, c0, o[1], o[2] - o[1], 16, need);
+                add(t, PK_G8, c0, o[0], o[1] - o[0], 32, need);
+            }
+        }
+        need = claim;
+        for (int t = 0; t < (int)sl.size(); ++t)
+            if (sl[t].nrhs > c0)
+                add(t, PK_PSUM, c0, 0, (sl[t].h->p_n_psum * 2 * NR + 255) / 256, 1, need);
+        need = claim;
+        for (int t = 0; t < (int)sl.size(); ++t)
+            if (sl[t].nrhs > c0) add(t, PK_EXP, c0, 0, sl[t].h->p_n_exp, 1, need);
+        need = claim;
+        for (int t = 0; t < (int)sl.size(); ++t)
+            if (sl[t].nrhs > c0) add(t, PK_GATHER, c0, 0, sl[t].h->n_near_items, 1, need);
+    }
+    nclaims = claim;
+}
+
+template <typename C>
+PSlot persist_slot(const PSlotHost& q, int NR) {
+    hodlr_t h = q.h;
+    const int64_t N = h->N;
+    const int64_t TT = std::max<int64_t>(h->t_total, 1);
+    const int64_t CT = std::max<int64_t>(h->contrib_total, 1);
+    C* x = (C*)q.ws;
+    C* contrib = x + N * q.nrhs;
+    C* tb = contrib + CT * NR;
+    C* sb = tb + TT * NR;
+    C* pp = sb + TT * NR;
+    C* yn = pp + 2 * kProjSegMax * std::max(h->n_proj_sums, h->p_n_psum) * NR;
+    PSlot p{};
+    p.cblk = h->p_class_blocks;
+    p.blocks = h->blocks;
+    p.proj = h->p_proj;
+    p.psum = h->p_psum;
+    p.ex = h->p_exp;
+    p.near = h->near_items;
+    p.lseg = h->leaf_seg;
+    p.nrng = h->near_rng;
+    p.pts = h->pts;
+    p.perm = h->perm;
+    p.X = q.X;
+    p.Y = q.Y;
+    p.x = x;
+    p.contrib = contrib;
+    p.tb = tb;
+    p.sb = sb;
+    p.pp = pp;
+    p.yn = yn;
+    p.kp = h->kp;
+    p.N = N;
+    p.ldx = q.ldx;
+    p.ldy = q.ldy;
+    p.CT = CT;
+    p.TT = TT;
+    p.npsum = h->p_n_psum;
+    p.d = h->d;
+    p.kappa = h->kappa;
+    p.sym = h->opts.symmetric ? 1 : 0;
+    p.nrhs = q.nrhs;
+    return p;
+}
+
+template <typename XT, typename S, int NR>
+unsigned persist_grid(int64_t nclaims) {
+    static int cap = -1;
+    static std::mutex mu;
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        if (cap < 0) {
+            int per_cu = 0, dev = 0, cus = 0;
+            HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_persist<XT, S, NR>,
+                                                                   kPersistThreads, 0));
+            HIP_CHECK(hipGetDevice(&dev));
+            HIP_CHECK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+            cap = std::max(1, per_cu) * std::max(1, cus);
+        }
+    }
+    return (unsigned)std::max<int64_t>(1, std::min<int64_t>(nclaims, cap));
+}
+
+// the error flag of a finished persistent launch (a wait that timed out)
+void persist_check(const int* ctr, hipStream_t s) {
+    int v[8] = {0};
+    HIP_CHECK(hipMemcpyAsync(v, ctr, sizeof(v), hipMemcpyDeviceToHost, s));
+    HIP_CHECK(hipStreamSynchronize(s));
+    if (v[3])
+        fail(HODLR_EDEVICE, "persistent product: a stage wait timed out (claim " +
+                                std::to_string(v[4]) + " waited for " + std::to_string(v[5]) +
+                                " completed claims, saw " + std::to_string(v[6]) + ")");
+}
+
+// Launches the persistent product of the slots on s.  dslots / dsegs: device
+// tables of at least slots.size() / segs.size() entries, written here when
+// `upload` is set; ctr: four zeroed ints (left zeroed by the launch).
+template <typename XT, typename S, int NR>
+void persist_launch(const std::vector<PSlotHost>& slots, const std::vector<PSeg>& segs,
+                    int64_t nclaims, PSlot* dslots, PSeg* dsegs, bool upload, int* ctr,
+                    hipStream_t s) {
+    if (upload) {
+        std::vector<PSlot> ps(slots.size());
+        for (size_t t = 0; t < slots.size(); ++t) ps[t] = persist_slot<S>(slots[t], NR);
+        HIP_CHECK(hipMemcpyAsync(dslots, ps.data(), sizeof(PSlot) * ps.size(),
+                                 hipMemcpyHostToDevice, s));
+        HIP_CHECK(hipMemcpyAsync(dsegs, segs.data(), sizeof(PSeg) * segs.size(),
+                                 hipMemcpyHostToDevice, s));
+    }
+    if (nclaims <= 0) return;
+    k_persist<XT, S, NR><<<persist_grid<XT, S, NR>(nclaims), kPersistThreads, 0, s>>>(
+        dslots, dsegs, (int)segs.size(), nclaims, ctr);
+    HIP_CHECK(hipGetLastError());
+}
+
 // Workspace (per product, device memory) for nrhs columns in compute_prec.
 size_t workspace_need(hodlr_t h, int nrhs, int compute_prec) {
     const int64_t N = h->N;
@@ -2182,7 +2759,8 @@ size_t workspace_need(hodlr_t h, int nrhs, int compute_prec) {
                align256(4 * (size_t)N * nr) + 4096;
     // x, contributions, projections, partials, near-field sums
     return cs * ((size_t)N * nrhs + (size_t)CT * nr + 2 * (size_t)TT * nr +
-                 2 * (size_t)kProjSegMax * (size_t)h->n_proj_sums * nr + (size_t)N * nr) +
+                 2 * (size_t)kProjSegMax * (size_t)std::max(h->n_proj_sums, h->p_n_psum) * nr +
+                 (size_t)N * nr) +
            4096;
 }
 
@@ -2261,6 +2839,12 @@ void reserve_workspace(hodlr_t h, int nrhs, int compute_prec, hipStream_t s) {
         HIP_CHECK(hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming));
         HIP_CHECK(hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming));
     }
+    if (!h->p_ctr) {
+        // the persistent launch's counters start at zero and each launch
+        // leaves them at zero
+        h->p_ctr = (int*)dalloc(h, 8 * sizeof(int));
+        HIP_CHECK(hipMemset(h->p_ctr, 0, 8 * sizeof(int)));
+    }
     if (h->ws_bytes < need) {
         if (h->ws) {
             HIP_CHECK(hipStreamSynchronize(s));
@@ -2273,10 +2857,133 @@ void reserve_workspace(hodlr_t h, int nrhs, int compute_prec, hipStream_t s) {
     }
 }
 
+bool persistent_route(hodlr_t h, int x_prec, int compute_prec) {
+    (void)x_prec;
+    const bool supported = !h->opts.skeleton && h->opts.storage != HODLR_BF16 &&
+                           ((h->opts.storage == HODLR_FP64) == (compute_prec == HODLR_FP64));
+    if (!supported) return false;
+    return h->use_persistent == 1;
+}
+
+namespace {
+template <typename XT, typename S, int NR>
+void persist_single(hodlr_t h, const void* X, int64_t ldx, int nrhs, void* Y, int64_t ldy,
+                    hipStream_t s) {
+    const std::vector<int64_t> key = {(int64_t)(uintptr_t)X, ldx, nrhs, (int64_t)(uintptr_t)Y,
+                                      ldy, (int64_t)(uintptr_t)h->ws, (int64_t)sizeof(XT),
+                                      (int64_t)sizeof(S), NR};
+    if (key != h->p_key) {
+        hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+        if (s && hipStreamIsCapturing(s, &cap) == hipSuccess && cap != hipStreamCaptureStatusNone)
+            fail(HODLR_EINVAL, "a persistent product captured with new arguments: run it once "
+                               "with the same X, Y and nrhs before the capture");
+        std::vector<PSlotHost> sl = {PSlotHost{h, X, ldx, Y, ldy, nrhs, (char*)h->ws}};
+        std::vector<PSeg> segs;
+        int64_t nclaims = 0;
+        persist_segments(sl, NR, segs, nclaims);
+        if (!h->p_dslot) h->p_dslot = dalloc(h, sizeof(PSlot));
+        if (h->p_segcap < segs.size()) {
+            HIP_CHECK(hipStreamSynchronize(s));
+            dfree(h, h->p_dsegs);
+            h->p_segcap = segs.size() + 16;
+            h->p_dsegs = dalloc(h, sizeof(PSeg) * h->p_segcap);
+        }
+        persist_launch<XT, S, NR>(sl, segs, nclaims, (PSlot*)h->p_dslot, (PSeg*)h->p_dsegs, true,
+                                  h->p_ctr, s);
+        persist_check(h->p_ctr, s);   // synchronises: the host tables may go
+        h->p_key = key;
+        h->p_nclaims = nclaims;
+        h->p_nseg = segs.size();
+        return;
+    }
+    std::vector<PSlotHost> none;
+    std::vector<PSeg> segs(h->p_nseg);   // only the count is used without upload
+    persist_launch<XT, S, NR>(none, segs, h->p_nclaims, (PSlot*)h->p_dslot, (PSeg*)h->p_dsegs,
+                              false, h->p_ctr, s);
+}
+
+template <typename XT, typename S>
+void persist_dispatch(hodlr_t h, const void* X, int64_t ldx, int nrhs, void* Y, int64_t ldy,
+                      hipStream_t s) {
+    if (nrhs == 1)
+        persist_single<XT, S, 1>(h, X, ldx, nrhs, Y, ldy, s);
+    else if (nrhs <= 4)
+        persist_single<XT, S, 4>(h, X, ldx, nrhs, Y, ldy, s);
+    else
+        persist_single<XT, S, 8>(h, X, ldx, nrhs, Y, ldy, s);
+}
+}  // namespace
+
 void matvec(hodlr_t h, const void* X, int64_t ldx, int nrhs, int x_prec, void* Y, int64_t ldy,
             int compute_prec, hipEvent_t const* ev, int nev, hipStream_t s) {
     reserve_workspace(h, nrhs, compute_prec, s);
+    if (!ev && persistent_route(h, x_prec, compute_prec)) {
+        const bool s64 = h->opts.storage == HODLR_FP64;
+        if (x_prec == HODLR_FP64) {
+            if (s64) persist_dispatch<double, double>(h, X, ldx, nrhs, Y, ldy, s);
+            else persist_dispatch<double, float>(h, X, ldx, nrhs, Y, ldy, s);
+        } else {
+            if (s64) persist_dispatch<float, double>(h, X, ldx, nrhs, Y, ldy, s);
+            else persist_dispatch<float, float>(h, X, ldx, nrhs, Y, ldy, s);
+        }
+        return;
+    }
     run_product(h, X, ldx, nrhs, x_prec, Y, ldy, compute_prec, (char*)h->ws, ev, nev, s, h->aux);
+}
+
+namespace {
+template <typename XT, typename S, int NR>
+void batch_launch(const std::vector<PSlotHost>& sl, int* ctr, hodlr_t h0, hipStream_t s) {
+    std::vector<PSeg> segs;
+    int64_t nclaims = 0;
+    persist_segments(sl, NR, segs, nclaims);
+    PSlot* dslot = (PSlot*)dalloc(h0, sizeof(PSlot) * sl.size());
+    PSeg* dsegs = (PSeg*)dalloc(h0, sizeof(PSeg) * std::max<size_t>(segs.size(), 1));
+    persist_launch<XT, S, NR>(sl, segs, nclaims, dslot, dsegs, true, ctr, s);
+    persist_check(ctr, s);
+    dfree(h0, dslot);
+    dfree(h0, dsegs);
+}
+}  // namespace
+
+void matvec_batch(int nslots, hodlr_t const* hs, const void* const* X, const int64_t* ldx,
+                  const int* nrhs, int x_prec, void* const* Y, const int64_t* ldy, int* ctr,
+                  hipStream_t s) {
+    if (nslots <= 0) return;
+    if (!ctr) {
+        // the first handle's counters (reserved with its workspace below)
+        reserve_workspace(hs[0], nrhs[0], hs[0]->opts.storage == HODLR_FP64 ? HODLR_FP64
+                                                                            : HODLR_FP32, s);
+        ctr = hs[0]->p_ctr;
+    }
+    const int st = hs[0]->opts.storage;
+    const int comp = st == HODLR_FP64 ? HODLR_FP64 : HODLR_FP32;
+    int maxr = 1;
+    std::vector<PSlotHost> sl;
+    for (int t = 0; t < nslots; ++t) {
+        hodlr_t h = hs[t];
+        if (h->opts.storage != st || h->opts.skeleton || st == HODLR_BF16)
+            fail(HODLR_EINVAL, "a batch needs FP64 or FP32 factors of one storage precision");
+        maxr = std::max(maxr, nrhs[t]);
+    }
+    const int NR = maxr == 1 ? 1 : (maxr <= 4 ? 4 : 8);
+    for (int t = 0; t < nslots; ++t) {
+        // every slot's workspace sized for the batch's column block NR (a
+        // column count that the sizing maps to NR)
+        const int sizing = NR == 1 ? 1 : std::max(nrhs[t], NR == 4 ? 2 : 5);
+        reserve_workspace(hs[t], sizing, comp, s);
+        sl.push_back(PSlotHost{hs[t], X[t], ldx[t], Y[t], ldy[t], nrhs[t], (char*)hs[t]->ws});
+    }
+    const bool s64 = st == HODLR_FP64;
+#define HODLR_BATCH(XT, S)                                                                          do {                                                                                                if (NR == 1) batch_launch<XT, S, 1>(sl, ctr, hs[0], s);                                         else if (NR == 4) batch_launch<XT, S, 4>(sl, ctr, hs[0], s);                                    else batch_launch<XT, S, 8>(sl, ctr, hs[0], s);                                             } while (0)
+    if (x_prec == HODLR_FP64) {
+        if (s64) HODLR_BATCH(double, double);
+        else HODLR_BATCH(double, float);
+    } else {
+        if (s64) HODLR_BATCH(float, double);
+        else HODLR_BATCH(float, float);
+    }
+#undef HODLR_BATCH
 }
 
 void matvec_noalloc(hodlr_t h, const void* X, int64_t ldx, int nrhs, int x_prec, void* Y,

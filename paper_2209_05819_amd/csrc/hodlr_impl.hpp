@@ -330,6 +330,24 @@ struct hodlr_handle_s {
     int64_t mexp_felems = 0;
     int64_t contrib_total = 0;             // contribution elements per right-hand side
     int64_t nleaf = 0;
+    // plan of the persistent product (one launch walks every stage): the
+    // size classes with class 5 limited to blocks of at most 2304 rows and
+    // columns, the larger blocks on the segmented route (projections per
+    // term and row segment, their sums, 64-row expansions)
+    hodlr::BlockDesc* p_class_blocks = nullptr;
+    std::vector<int64_t> p_class_off;
+    hodlr::ProjSeg* p_proj = nullptr;
+    hodlr::ProjSum* p_psum = nullptr;
+    hodlr::WorkItem* p_exp = nullptr;
+    int64_t p_n_proj = 0, p_n_psum = 0, p_n_exp = 0;
+    int* p_ctr = nullptr;       // its launch counters: claim, done, exit, error, diagnostics
+    int use_persistent = -1;    // product route: 1 persistent; 0 or -1 (not chosen) per-class
+    void* p_dslot = nullptr;    // device slot table and claim queue of the last product
+    void* p_dsegs = nullptr;
+    size_t p_segcap = 0;
+    std::vector<int64_t> p_key; // what they were built for (pointers, sizes, types)
+    int64_t p_nclaims = 0;
+    size_t p_nseg = 0;
     // matvec workspace
     void* ws = nullptr;
     size_t ws_bytes = 0;
@@ -376,6 +394,15 @@ void matvec(hodlr_t h, const void* X, int64_t ldx, int nrhs, int x_prec, void* Y
             int compute_prec, hipEvent_t const* ev, int nev, hipStream_t s);
 // grows the handle's product workspace to what nrhs columns need
 void reserve_workspace(hodlr_t h, int nrhs, int compute_prec, hipStream_t s);
+// whether a product takes the persistent route (one launch) with these types
+bool persistent_route(hodlr_t h, int x_prec, int compute_prec);
+// products of several handles in one persistent launch (same x_prec for all;
+// compute precision = storage precision, FP64 or FP32); ctr: four zeroed ints
+// owned by the caller, dslot/dsegs: device tables the caller owns, with room
+// for nslots slots and *segcap segments (grown with dalloc on h0 if needed)
+void matvec_batch(int nslots, hodlr_t const* hs, const void* const* X, const int64_t* ldx,
+                  const int* nrhs, int x_prec, void* const* Y, const int64_t* ldy, int* ctr,
+                  hipStream_t s);
 // the product with its workspace in the library's static scratch array and
 // the near field on s (no allocation, no second stream)
 constexpr int64_t kScratchBytes = (int64_t)64 << 20;

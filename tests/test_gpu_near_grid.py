@@ -40,7 +40,10 @@ def P():
 CASES = [
     # N, leaf, storage, light (capped grid) expected
     (32768, 64, "fp64", True),
-    (32768, 64, "fp32", True),
+    # FP32 factors are truncated (fewer bytes per dense pair): light from
+    # 2^17 points on, heavy at 2^15
+    (131072, 64, "fp32", True),
+    (32768, 64, "fp32", False),
     (32768, 512, "fp64", False),
 ]
 

@@ -163,29 +163,21 @@ def multi_rhs(P, torch, W, steps, warmup, n_override=0):
 
 def small_bench(P, torch, W, reps=200):
     """The small workload (4096 points uniform in [-1,1]^2, log r, leaf 64,
-    ACA 1e-8, FP64, one U[-1,1] right-hand side): per-call latency of the
-    product launched eagerly and replayed from a captured HIP graph, and its
-    error against the direct N^2 sum on every row."""
+    ACA 1e-8, FP64, one U[-1,1] right-hand side): the autotuner's choice
+    (tile shapes per block class, per-class launches or one persistent
+    launch), and the per-call latency of the product on both routes,
+    launched eagerly and replayed from a captured HIP graph; the error
+    against the direct N^2 sum on every row."""
     import oracle
     w = W.WORKLOADS["uniform2d_log_n4096"]
     pts, q = w.points(), w.rhs()[:, 0]
     N = w.N
     H = P.HODLR(pts, P.make_kernel(w.kernel, h=w.h, diag=w.diag), w.leaf, w.tol, domain=w.domain,
                 level_rule=1)
+    tune = P.hodlr_autotune(H.h, 1, P.FP64, P.FP64)
     P.hodlr_reserve_workspace(H.h, 1, P.FP64)
     X = torch.tensor(q, dtype=torch.float64, device="cuda")
     Y = torch.empty_like(X)
-    side = torch.cuda.Stream()
-    side.wait_stream(torch.cuda.current_stream())
-    with torch.cuda.stream(side):
-        for _ in range(3):
-            P.hodlr_matvec(H.h, X, Y)
-    torch.cuda.current_stream().wait_stream(side)
-    torch.cuda.synchronize()
-    g = torch.cuda.CUDAGraph()
-    with torch.cuda.graph(g):
-        P.hodlr_matvec(H.h, X, Y)
-    torch.cuda.synchronize()
 
     def per_call(fn):
         ev = _events(torch, reps + 1)
@@ -205,30 +197,55 @@ def small_bench(P, torch, W, reps=200):
             t[i] = (time.perf_counter() - t0) * 1e3
         return t
 
-    eager = per_call(lambda: P.hodlr_matvec(H.h, X, Y))
-    graph = per_call(g.replay)
-    eager_w = wall_per_call(lambda: P.hodlr_matvec(H.h, X, Y))
-    graph_w = wall_per_call(g.replay)
+    routes = {}
+    for name, route in (("per_class", 0), ("persistent", 1)):
+        P.hodlr_set_route(H.h, route)
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            for _ in range(3):
+                P.hodlr_matvec(H.h, X, Y)
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            P.hodlr_matvec(H.h, X, Y)
+        torch.cuda.synchronize()
+        eager = per_call(lambda: P.hodlr_matvec(H.h, X, Y))
+        graph = per_call(g.replay)
+        eager_w = wall_per_call(lambda: P.hodlr_matvec(H.h, X, Y))
+        graph_w = wall_per_call(g.replay)
+        routes[name] = {
+            "eager_p50_ms": float(np.percentile(eager, 50)),
+            "eager_p99_ms": float(np.percentile(eager, 99)),
+            "graph_p50_ms": float(np.percentile(graph, 50)),
+            "graph_p99_ms": float(np.percentile(graph, 99)),
+            "eager_wall_p50_ms": float(np.percentile(eager_w, 50)),
+            "graph_wall_p50_ms": float(np.percentile(graph_w, 50)),
+        }
+        del g
+    P.hodlr_set_route(H.h, tune.route)
+    Y = H.matvec(X)
+    torch.cuda.synchronize()
     y = Y.cpu().numpy()
     bd = oracle.direct(pts, oracle.kernel(w.kernel, h=w.h, diag=w.diag), q[:, None])[:, 0]
     err = float(np.linalg.norm(y - bd) / np.linalg.norm(bd))
     info = H.info()
-    del g, H
+    del H
+    best = min(min(r["eager_p50_ms"], r["graph_p50_ms"]) for r in routes.values())
     return {
         "workload": w.name, "N": N, "d": w.d, "kernel": "log r, diag 0", "leaf": w.leaf,
         "aca_tol": w.tol, "kappa": info.kappa, "dtype": "f64",
-        "eager_p50_ms": float(np.percentile(eager, 50)),
-        "eager_p99_ms": float(np.percentile(eager, 99)),
-        "graph_p50_ms": float(np.percentile(graph, 50)),
-        "graph_p99_ms": float(np.percentile(graph, 99)),
+        "autotune": {"route": "persistent" if tune.route == 1 else "per_class",
+                     "class_choice": list(tune.class_choice)[:6],
+                     "class_ms": [round(v, 5) for v in list(tune.class_ms)[:6]],
+                     "per_class_route_ms": tune.class_route_ms,
+                     "persistent_route_ms": tune.persistent_ms},
+        "routes": routes,
         "gpu_time": "HIP events between back-to-back calls on the stream",
-        "eager_wall_p50_ms": float(np.percentile(eager_w, 50)),
-        "eager_wall_p99_ms": float(np.percentile(eager_w, 99)),
-        "graph_wall_p50_ms": float(np.percentile(graph_w, 50)),
-        "graph_wall_p99_ms": float(np.percentile(graph_w, 99)),
         "wall_time": "host clock, one call then a synchronisation (launch included)",
-        "value": N / (min(float(np.percentile(eager, 50)), float(np.percentile(graph, 50))) * 1e-3),
-        "unit": "N*nrhs/s (back-to-back, the faster of eager and graph)",
+        "value": N / (best * 1e-3),
+        "unit": "N*nrhs/s (back-to-back, the fastest route and launch mode)",
         "rel_err": err, "rel_err_ref": "direct N^2 sum, every row",
     }
 
@@ -743,10 +760,12 @@ def main():
     small = None
     if not args.no_small:
         small = small_bench(P, torch, W)
-        print(f"[bench] small workload: eager {small['eager_p50_ms']:.3f} ms "
-              f"(wall {small['eager_wall_p50_ms']:.3f}), graph {small['graph_p50_ms']:.3f} ms "
-              f"(wall {small['graph_wall_p50_ms']:.3f}), rel err {small['rel_err']:.2e}",
-              file=sys.stderr, flush=True)
+        for name, r in small["routes"].items():
+            print(f"[bench] small workload, {name}: eager {r['eager_p50_ms']:.4f} ms "
+                  f"(wall {r['eager_wall_p50_ms']:.3f}), graph {r['graph_p50_ms']:.4f} ms "
+                  f"(wall {r['graph_wall_p50_ms']:.3f})", file=sys.stderr, flush=True)
+        print(f"[bench] small workload: autotuner kept {small['autotune']['route']}, "
+              f"rel err {small['rel_err']:.2e}", file=sys.stderr, flush=True)
 
     solve = None
     if not args.no_solve:

@@ -193,6 +193,34 @@ hodlr_status hodlr_reserve_workspace(hodlr_t h, int nrhs, int compute_prec);
  * handle or another route. */
 hodlr_status hodlr_set_route(hodlr_t h, int route);
 
+/* What hodlr_autotune measured and chose. */
+typedef struct {
+    int route;              /* product route kept: 0 per-class launches, 1 persistent */
+    int class_choice[8];    /* tile shape kept per single-RHS block class (index below) */
+    double class_ms[8];     /* that shape's time per launch of the class, ms */
+    double class_route_ms;  /* product time on the per-class route, ms */
+    double persistent_ms;   /* product time on the persistent route, ms (0: not applicable) */
+    int seg_side;           /* persistent route: widest block one workgroup streams alone */
+} hodlr_tuning;
+
+/* Autotuner of this handle's product (Alg. "HODLRdD matrix-vector Product"
+ * as the handle applies it), for nrhs columns of X in x_prec and
+ * compute_prec arithmetic: for nrhs = 1, every candidate tile shape
+ * <W waves per block, CH rows per lane, KB terms per batch> of the
+ * block-size classes 2..5 is timed alone on the handle's own blocks and the
+ * fastest is kept (class 2, blocks up to 64: <1,1,8> <1,1,4> <1,1,16>;
+ * class 3, up to 128: <1,2,4> <1,2,8> <2,1,8>; class 4, up to 1024:
+ * <4,4,K> <4,4,2K> <8,2,K>; class 5, up to 4608: <8,9,K'> <8,9,2K'>, with
+ * K = 2 and K' = 1 in FP64 arithmetic, 4 and 2 in FP32); then the product
+ * is timed on the per-class route and on the persistent route (there with
+ * the class-4 blocks wider than 1024, 512 or 256 rows segmented over many
+ * workgroups, the fastest of the three kept) and the faster route is kept
+ * (hodlr_set_route).  Allocates scratch X and Y, reserves
+ * the workspace, synchronises stream; out (host) receives the times.
+ * Errors: those of hodlr_matvec. */
+hodlr_status hodlr_autotune(hodlr_t h, int nrhs, int x_prec, int compute_prec,
+                            hodlr_tuning* out, void* stream);
+
 /* Products of several handles (different point sets, sizes, dimensions and
  * kernels) in one persistent launch: Y[t] = K~_t X[t] for t < nslots, each
  * N_t x nrhs[t] column-major in its own user order, device pointers.  The
@@ -310,6 +338,7 @@ typedef struct {
     int64_t submitted, completed, failed;
     int64_t launches;          /* products and solves started */
     int64_t batched_requests;  /* products that shared a launch with others */
+    int64_t multiset_launches; /* launches that applied the products of several sets */
     int64_t max_concurrent;    /* most launches in flight at once */
     size_t used_bytes, budget_bytes;
     int sets;
@@ -333,7 +362,11 @@ hodlr_status hodlr_server_add_set(hodlr_server_t srv, const double* points, int6
 
 /* Queue a request; returns at once with its id.  The scheduler starts it when
  * its set is idle, a slot is free and its workspace fits the budget; queued
- * products of one set are applied together as one product of their columns.
+ * products of one set are applied together as one product of their columns,
+ * and queued products of other idle sets with the same factor precision
+ * (FP64 or FP32) join the same launch: one persistent launch applies up to
+ * 16 sets (as far as the slot's buffer of max_points x max_batch_cols
+ * doubles holds their columns).
  * Solves run GMRES with iterative refinement on the set itself (FP64
  * residuals; inner GMRES(30) in FP32 arithmetic, to tol).  X and Y must stay
  * valid until the request completes.  Ordering: an event is recorded on

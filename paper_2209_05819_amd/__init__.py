@@ -59,6 +59,12 @@ class Info(C.Structure):
                 ("mfma_proj_elems", C.c_int64)]
 
 
+class Tuning(C.Structure):
+    _fields_ = [("route", C.c_int), ("class_choice", C.c_int * 8), ("class_ms", C.c_double * 8),
+                ("class_route_ms", C.c_double), ("persistent_ms", C.c_double),
+                ("seg_side", C.c_int)]
+
+
 class SolveOpts(C.Structure):
     _fields_ = [("tol", C.c_double), ("inner_tol", C.c_double), ("restart", C.c_int),
                 ("max_outer", C.c_int), ("lo_compute", C.c_int), ("use_initial_guess", C.c_int)]
@@ -83,6 +89,7 @@ class Request(C.Structure):
 class ServerStats(C.Structure):
     _fields_ = [("submitted", C.c_int64), ("completed", C.c_int64), ("failed", C.c_int64),
                 ("launches", C.c_int64), ("batched_requests", C.c_int64),
+                ("multiset_launches", C.c_int64),
                 ("max_concurrent", C.c_int64), ("used_bytes", C.c_size_t),
                 ("budget_bytes", C.c_size_t), ("sets", C.c_int)]
 
@@ -110,6 +117,7 @@ def lib():
                                           C.POINTER(_P), C.c_int]
         L.hodlr_matvec_noalloc.argtypes = [_P, _P, _i64, C.c_int, C.c_int, _P, _i64, C.c_int, _P]
         L.hodlr_set_route.argtypes = [_P, C.c_int]
+        L.hodlr_autotune.argtypes = [_P, C.c_int, C.c_int, C.c_int, C.POINTER(Tuning), _P]
         L.hodlr_matvec_batch.argtypes = [C.c_int, _P, _P, _P, _P, C.c_int, _P, _P, _P]
         L.hodlr_get_info.argtypes = [_P, C.POINTER(Info)]
         L.hodlr_server_default_opts.argtypes = [C.POINTER(ServerOpts)]
@@ -142,7 +150,7 @@ def lib():
         L.hodlr_destroy.argtypes = [_P]
         L.hodlr_last_error.restype = C.c_char_p
         for f in ("hodlr_build", "hodlr_matvec", "hodlr_matvec_events", "hodlr_matvec_noalloc",
-                  "hodlr_set_route", "hodlr_matvec_batch",
+                  "hodlr_set_route", "hodlr_matvec_batch", "hodlr_autotune",
                   "hodlr_get_info",
                   "hodlr_export_tree",
                   "hodlr_export_boxes", "hodlr_export_il", "hodlr_export_near",
@@ -265,6 +273,16 @@ def hodlr_set_route(h: int, route: int) -> None:
     """1: one persistent launch per product; 0: per-stage, per-class launches;
     -1: by size (the default)."""
     _check(lib().hodlr_set_route(C.c_void_p(h), int(route)))
+
+
+def hodlr_autotune(h: int, nrhs: int = 1, x_prec: int = FP64, compute_prec: int = FP64,
+                   stream=None) -> Tuning:
+    """Time the block classes' tile shapes and the two product routes on this
+    handle and keep the fastest (synchronous)."""
+    t = Tuning()
+    _check(lib().hodlr_autotune(C.c_void_p(h), int(nrhs), int(x_prec), int(compute_prec),
+                                C.byref(t), _stream_ptr(stream)))
+    return t
 
 
 def _cols(X):

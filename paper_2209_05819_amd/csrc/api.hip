@@ -224,6 +224,25 @@ hodlr_status hodlr_set_route(hodlr_t h, int route) {
     return HODLR_OK;
 }
 
+hodlr_status hodlr_autotune(hodlr_t h, int nrhs, int x_prec, int compute_prec,
+                            hodlr_tuning* out, void* stream) {
+    if (!h || !out) return set_error(HODLR_EINVAL, "null pointer argument");
+    if (nrhs < 1) return set_error(HODLR_EINVAL, "nrhs must be >= 1");
+    if (x_prec != HODLR_FP64 && x_prec != HODLR_FP32)
+        return set_error(HODLR_EINVAL, "x_prec must be FP64 or FP32");
+    if (compute_prec != HODLR_FP64 && compute_prec != HODLR_FP32)
+        return set_error(HODLR_EINVAL, "compute_prec must be FP64 or FP32");
+    if (h->opts.storage == HODLR_BF16 && compute_prec != HODLR_FP32)
+        return set_error(HODLR_EINVAL, "BF16 factors are applied in FP32 arithmetic");
+    if (h->opts.skeleton && compute_prec != HODLR_FP64)
+        return set_error(HODLR_EINVAL, "the skeleton form is applied in FP64 arithmetic");
+    for (int l = 1; l <= h->kappa; ++l)
+        if (!h->lev[l].has_factors) return set_error(HODLR_EINVAL, "factors missing");
+    return guarded([&] {
+        hodlr::autotune(h, nrhs, x_prec, compute_prec, out, (hipStream_t)stream);
+    });
+}
+
 hodlr_status hodlr_matvec_batch(int nslots, const hodlr_t* hs, const void* const* X,
                                 const int64_t* ldx, const int* nrhs, int x_prec, void* const* Y,
                                 const int64_t* ldy, void* stream) {

@@ -15,6 +15,7 @@
 // Each output is produced by one lane in a fixed order: results are bitwise
 // reproducible and no floating-point atomics are used.
 #include <algorithm>
+#include <cstring>
 #include <mutex>
 #include <string>
 #include <type_traits>
@@ -30,7 +31,9 @@ constexpr int TE = 256;   // split expansion workgroup (4 waves share 64 rows)
 constexpr int KB = 16;    // rows reduced together in the fused projection
 constexpr int kFusedMaxRank = 256;  // projections a fused wave keeps in LDS at once
 constexpr int kNumClasses = kApplyClasses;  // block size classes of the one-workgroup kernels
-constexpr int kPersistC5 = 2304;    // widest class-5 block one persistent workgroup streams
+// class-5 blocks (up to 4608 rows) take the segmented route in the persistent
+// plan: streaming one of them per workgroup needs more registers than the
+// other work of the persistent kernel and would cut its occupancy for all
 
 
 // Cross-lane moves that stay in the vector ALU: DPP row permutations for
@@ -208,6 +211,30 @@ __global__ void k_permute_out(const float* __restrict__ yl, const float* __restr
         Y[(int64_t)(c0 + c) * ldy + u] = (XT)(yl[(int64_t)c * N + p] + yn[(int64_t)c * N + p]);
 }
 
+// Loads and stores of the vectors one launch both writes and reads (x, the
+// contributions, projections and near sums).  CO: device-coherent accesses
+// (relaxed agent-scope atomics, which neither stop at nor hit stale lines of
+// an XCD's own L2), for a launch whose workgroups hand these vectors to each
+// other; otherwise plain ones.
+// (The vectors live in global memory: saying so gives global instead of
+// flat instructions, which would also wait on the LDS.)
+template <bool CO, typename C>
+__device__ __forceinline__ C ldv(const C* p) {
+    if constexpr (CO)
+        return __hip_atomic_load((const C __attribute__((address_space(1)))*)p, __ATOMIC_RELAXED,
+                                 __HIP_MEMORY_SCOPE_AGENT);
+    else
+        return *p;
+}
+template <bool CO, typename C>
+__device__ __forceinline__ void stv(C* p, C v) {
+    if constexpr (CO)
+        __hip_atomic_store((C __attribute__((address_space(1)))*)p, v, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+    else
+        *p = v;
+}
+
 // Orders a wave's LDS writes before its later reads by other lanes of the
 // same wave (the LDS runs one wave's instructions in order; only the
 // compiler must not move them across).
@@ -224,7 +251,7 @@ __device__ __forceinline__ void wave_sync() {
 // The body works on one wave's own LDS (tw, sw: RMAX x NR each) and
 // synchronises within the wave only, so the waves of a larger workgroup can
 // each apply a block of their own.
-template <typename S, typename C, int NR, int RMAX>
+template <typename S, typename C, int NR, int RMAX, bool CO = false>
 __device__ __forceinline__ void lr_fused_body(const BlockDesc& b, int sym,
                                               const C* __restrict__ x, int64_t N, int nrhs,
                                               int c0, int64_t CT, C* __restrict__ contrib,
@@ -251,7 +278,7 @@ __device__ __forceinline__ void lr_fused_body(const BlockDesc& b, int sym,
             for (int j = lane; j < n; j += 64) {
                 C xv[NR];
 #pragma unroll
-                for (int c = 0; c < NR; ++c) xv[c] = c < nc ? xB[(int64_t)c * N + j] : (C)0;
+                for (int c = 0; c < NR; ++c) xv[c] = c < nc ? ldv<CO>(xB + (int64_t)c * N + j) : (C)0;
 #pragma unroll
                 for (int kk = 0; kk < K; ++kk)
                     if (kk < kr) {
@@ -264,7 +291,8 @@ __device__ __forceinline__ void lr_fused_body(const BlockDesc& b, int sym,
                 for (int i = lane; i < m; i += 64) {
                     C xu[NR];
 #pragma unroll
-                    for (int c = 0; c < NR; ++c) xu[c] = c < nc ? xA[(int64_t)c * N + i] : (C)0;
+                    for (int c = 0; c < NR; ++c)
+                        xu[c] = c < nc ? ldv<CO>(xA + (int64_t)c * N + i) : (C)0;
 #pragma unroll
                     for (int kk = 0; kk < K; ++kk)
                         if (kk < kr) {
@@ -292,28 +320,30 @@ __device__ __forceinline__ void lr_fused_body(const BlockDesc& b, int sym,
             C acc[NR];
 #pragma unroll
             for (int c = 0; c < NR; ++c)
-                acc[c] = (kc > 0 && c < nc) ? contrib[(int64_t)c * CT + b.cfwd + i] : (C)0;
+                acc[c] = (kc > 0 && c < nc) ? ldv<CO>(contrib + (int64_t)c * CT + b.cfwd + i) : (C)0;
 #pragma unroll 4
             for (int k = 0; k < rc; ++k) {
                 const C u = ldf<C>(U, (int64_t)(kc + k) * lu + i);
 #pragma unroll
                 for (int c = 0; c < NR; ++c) acc[c] += u * tw[k][c];
             }
-            for (int c = 0; c < nc; ++c) contrib[(int64_t)c * CT + b.cfwd + i] = acc[c];
+            for (int c = 0; c < nc; ++c) stv<CO>(contrib + (int64_t)c * CT + b.cfwd + i, acc[c]);
         }
         if (sym) {
             for (int j = lane; j < n; j += 64) {
                 C acc[NR];
 #pragma unroll
                 for (int c = 0; c < NR; ++c)
-                    acc[c] = (kc > 0 && c < nc) ? contrib[(int64_t)c * CT + b.cbwd + j] : (C)0;
+                    acc[c] =
+                        (kc > 0 && c < nc) ? ldv<CO>(contrib + (int64_t)c * CT + b.cbwd + j) : (C)0;
 #pragma unroll 4
                 for (int k = 0; k < rc; ++k) {
                     const C v = ldf<C>(V, (int64_t)(kc + k) * lv + j);
 #pragma unroll
                     for (int c = 0; c < NR; ++c) acc[c] += v * sw[k][c];
                 }
-                for (int c = 0; c < nc; ++c) contrib[(int64_t)c * CT + b.cbwd + j] = acc[c];
+                for (int c = 0; c < nc; ++c)
+                    stv<CO>(contrib + (int64_t)c * CT + b.cbwd + j, acc[c]);
             }
         }
         wave_sync();
@@ -417,7 +447,7 @@ __device__ __forceinline__ void stream_step(const StreamBatch<S, C, W, CH, KB>& 
 
 // wv: the wave's index within the W waves applying the block (0 when W = 1,
 // whatever the wave's place in a larger workgroup)
-template <typename S, typename C, int W, int CH, int KB>
+template <typename S, typename C, int W, int CH, int KB, bool CO = false>
 __device__ __forceinline__ void lr_stream_body(const BlockDesc& b, int sym,
                                                const C* __restrict__ x, C* __restrict__ contrib,
                                                C (*part)[2][KB], int wv) {
@@ -430,8 +460,8 @@ __device__ __forceinline__ void lr_stream_body(const BlockDesc& b, int sym,
 #pragma unroll
     for (int c = 0; c < CH; ++c) {
         const int i = base + c * 64;
-        xa[c] = i < m ? x[b.a0 + i] : (C)0;
-        xb[c] = i < n ? x[b.b0 + i] : (C)0;
+        xa[c] = i < m ? ldv<CO>(x + b.a0 + i) : (C)0;
+        xb[c] = i < n ? ldv<CO>(x + b.b0 + i) : (C)0;
         ca[c] = cb[c] = 0;
     }
     StreamBatch<S, C, W, CH, KB> b0, b1;
@@ -446,8 +476,8 @@ __device__ __forceinline__ void lr_stream_body(const BlockDesc& b, int sym,
 #pragma unroll
     for (int c = 0; c < CH; ++c) {
         const int i = base + c * 64;
-        if (i < m) contrib[b.cfwd + i] = ca[c];
-        if (sym && i < n) contrib[b.cbwd + i] = cb[c];
+        if (i < m) stv<CO>(contrib + b.cfwd + i, ca[c]);
+        if (sym && i < n) stv<CO>(contrib + b.cbwd + i, cb[c]);
     }
 }
 
@@ -487,7 +517,7 @@ __device__ __forceinline__ C group_reduce_rows(C (&p)[G]) {
 // (64/G blocks per wave).  Lane g holds column g of U^T (row g of U) in
 // registers; V is read twice, the second time from cache.
 // A 256-thread workgroup applies the blocks first .. first + 256 / G - 1.
-template <typename S, typename C, int G>
+template <typename S, typename C, int G, bool CO = false>
 __device__ __forceinline__ void lr_group_body(const BlockDesc* __restrict__ blocks,
                                               int64_t first, int64_t nitems, int sym,
                                               const C* __restrict__ x, C* __restrict__ contrib) {
@@ -507,8 +537,8 @@ __device__ __forceinline__ void lr_group_body(const BlockDesc* __restrict__ bloc
         u[k] = (k < r && g < m) ? ldf<C>(U, k * lu + g) : (C)0;
         v[k] = (k < r && g < n) ? ldf<C>(V, k * lv + g) : (C)0;
     }
-    const C xa = (valid && g < m) ? x[b.a0 + g] : (C)0;
-    const C xb = (valid && g < n) ? x[b.b0 + g] : (C)0;
+    const C xa = (valid && g < m) ? ldv<CO>(x + b.a0 + g) : (C)0;
+    const C xb = (valid && g < n) ? ldv<CO>(x + b.b0 + g) : (C)0;
 #pragma unroll
     for (int k = 0; k < G; ++k) p[k] = v[k] * xb;
     const C t = group_reduce_rows<C, G>(p);    // t_g = V[g,:] . x_B
@@ -524,8 +554,8 @@ __device__ __forceinline__ void lr_group_body(const BlockDesc* __restrict__ bloc
         ca += u[k] * __shfl(t, base + k, 64);
         cb += v[k] * __shfl(s, base + k, 64);
     }
-    if (valid && g < m) contrib[b.cfwd + g] = ca;
-    if (valid && sym && g < n) contrib[b.cbwd + g] = cb;
+    if (valid && g < m) stv<CO>(contrib + b.cfwd + g, ca);
+    if (valid && sym && g < n) stv<CO>(contrib + b.cbwd + g, cb);
 }
 
 template <typename S, typename C, int G>
@@ -903,7 +933,7 @@ __global__ __launch_bounds__(64 * TW, RT > 8 ? 2 : 4) void k_mexp(
 // One term (row of V, column of U) of a large block per workgroup: the 256
 // threads stride over the row with four independent partial sums, then a
 // workgroup reduction gives t_k (and s_k).
-template <typename C, int NR>
+template <typename C, int NR, bool CO = false>
 __device__ __forceinline__ void wg_reduce_store(C (&acc)[NR], C (*red)[NR], int nc, C* out,
                                                 int64_t stride) {
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -917,12 +947,12 @@ __device__ __forceinline__ void wg_reduce_store(C (&acc)[NR], C (*red)[NR], int 
         for (int c = 0; c < nc; ++c) {
             C v = 0;
             for (int w = 0; w < TP / 64; ++w) v += red[w][c];
-            out[(int64_t)c * stride] = v;
+            stv<CO>(out + (int64_t)c * stride, v);
         }
     __syncthreads();
 }
 
-template <typename S, typename C, int NR>
+template <typename S, typename C, int NR, bool CO = false>
 __device__ __forceinline__ void row_dot(gptr_t<S> row, int len,
                                         const C* __restrict__ xs, int64_t N, int nc,
                                         C (&acc)[NR]) {
@@ -938,20 +968,20 @@ __device__ __forceinline__ void row_dot(gptr_t<S> row, int len,
             const C v = ldf<C>(row, j + u * TP);
 #pragma unroll
             for (int c = 0; c < NR; ++c)
-                if (c < nc) a[u][c] += v * xs[(int64_t)c * N + j + u * TP];
+                if (c < nc) a[u][c] += v * ldv<CO>(xs + (int64_t)c * N + j + u * TP);
         }
     }
     for (; j < len; j += TP) {
         const C v = ldf<C>(row, j);
 #pragma unroll
         for (int c = 0; c < NR; ++c)
-            if (c < nc) a[0][c] += v * xs[(int64_t)c * N + j];
+            if (c < nc) a[0][c] += v * ldv<CO>(xs + (int64_t)c * N + j);
     }
 #pragma unroll
     for (int c = 0; c < NR; ++c) acc[c] = (a[0][c] + a[1][c]) + (a[2][c] + a[3][c]);
 }
 
-template <typename S, typename C, int NR>
+template <typename S, typename C, int NR, bool CO = false>
 __device__ __forceinline__ void project_body(const BlockDesc* __restrict__ blocks,
                                              const ProjSeg& it, int sym,
                                              const C* __restrict__ x, int64_t N, int nrhs,
@@ -963,17 +993,17 @@ __device__ __forceinline__ void project_body(const BlockDesc* __restrict__ block
     {   // t_k partial: V[k, j0:j1] x_B[j0:j1]
         const int ln = (b.n + it.nseg - 1) / it.nseg, j0 = it.seg * ln;
         const int len = max(0, min(b.n, j0 + ln) - j0);
-        row_dot<S, C, NR>(as_global<S>(b.V) + (int64_t)k * fstride<S>(b.n) + j0, len,
-                          x + (int64_t)c0 * N + b.b0 + j0, N, nc, acc);
-        wg_reduce_store<C, NR>(acc, red, nc,
+        row_dot<S, C, NR, CO>(as_global<S>(b.V) + (int64_t)k * fstride<S>(b.n) + j0, len,
+                              x + (int64_t)c0 * N + b.b0 + j0, N, nc, acc);
+        wg_reduce_store<C, NR, CO>(acc, red, nc,
                                part + ((it.p * 2 + 0) * kProjSegMax + it.seg) * NR, 1);
     }
     if (sym) {   // s_k partial: U[i0:i1, k]^T x_A[i0:i1]
         const int ln = (b.m + it.nseg - 1) / it.nseg, i0 = it.seg * ln;
         const int len = max(0, min(b.m, i0 + ln) - i0);
-        row_dot<S, C, NR>(as_global<S>(b.U) + (int64_t)k * fstride<S>(b.m) + i0, len,
-                          x + (int64_t)c0 * N + b.a0 + i0, N, nc, acc);
-        wg_reduce_store<C, NR>(acc, red, nc,
+        row_dot<S, C, NR, CO>(as_global<S>(b.U) + (int64_t)k * fstride<S>(b.m) + i0, len,
+                              x + (int64_t)c0 * N + b.a0 + i0, N, nc, acc);
+        wg_reduce_store<C, NR, CO>(acc, red, nc,
                                part + ((it.p * 2 + 1) * kProjSegMax + it.seg) * NR, 1);
     }
 }
@@ -991,7 +1021,7 @@ __global__ __launch_bounds__(TP) void k_project(const BlockDesc* __restrict__ bl
 // order, one thread per (term, side, column)
 // thread t of the nsum * 2 * NR (term, side, column) sums; part read through
 // P (a plain or a device-coherent load)
-template <typename C, int NR, typename P>
+template <typename C, int NR, bool CO = false, typename P>
 __device__ __forceinline__ void proj_sum_body(int64_t t, const ProjSum* __restrict__ sums,
                                               int64_t nsum, int sym, int nc, P part, int64_t TT,
                                               C* __restrict__ tb, C* __restrict__ sb) {
@@ -1003,7 +1033,7 @@ __device__ __forceinline__ void proj_sum_body(int64_t t, const ProjSum* __restri
     const int64_t pp = (S.p * 2 + side) * kProjSegMax * NR + c;
     C v = 0;
     for (int g = 0; g < S.nseg; ++g) v += part(pp + (int64_t)g * NR);
-    (side ? sb : tb)[(int64_t)c * TT + S.dst] = v;
+    stv<CO>((side ? sb : tb) + (int64_t)c * TT + S.dst, v);
 }
 
 template <typename C, int NR>
@@ -1017,7 +1047,7 @@ __global__ void k_proj_sum(const ProjSum* __restrict__ sums, int64_t nsum, int s
 // 64-row chunk of one side of a large block: side 0 writes U t into the rows
 // of A, side 1 writes V^T s into the rows of B; the 4 waves split the terms
 // coefficients (t or s) read through P (a plain or a device-coherent load)
-template <typename S, typename C, int NR, typename P>
+template <typename S, typename C, int NR, bool CO = false, typename P>
 __device__ __forceinline__ void expand_split_body(const BlockDesc* __restrict__ blocks,
                                                   const WorkItem& it, int nrhs, int c0,
                                                   int64_t TT, P tbs, int64_t CT,
@@ -1050,7 +1080,7 @@ __device__ __forceinline__ void expand_split_body(const BlockDesc* __restrict__ 
         for (int c = 0; c < nc; ++c) {
             C s = part[0][c][lane];
             for (int w = 1; w < TE / 64; ++w) s += part[w][c][lane];
-            contrib[(int64_t)c * CT + seg + o] = s;
+            stv<CO>(contrib + (int64_t)c * CT + seg + o, s);
         }
     }
 }
@@ -1108,18 +1138,8 @@ __device__ __forceinline__ void gather_near_item(
     KParams kp, const C* x, const C* contrib, int64_t CT,
     const int32_t* __restrict__ perm, int nrhs, int c0, XT* __restrict__ Y, int64_t ldy,
     const C* __restrict__ ylev, C* yn, C (*red)[NR][64], NearLds<C, NR>& L) {
-    auto ldx = [&](int64_t i) -> C {
-        if constexpr (CO)
-            return __hip_atomic_load(x + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        else
-            return x[i];
-    };
-    auto ldc = [&](const C* p) -> C {
-        if constexpr (CO)
-            return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        else
-            return *p;
-    };
+    auto ldx = [&](int64_t i) -> C { return ldv<CO>(x + i); };
+    auto ldc = [&](const C* p) -> C { return ldv<CO>(p); };
     {
         // the wave index as a scalar: loop bounds built from it stay wave-uniform
         const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -1311,7 +1331,7 @@ __device__ __forceinline__ void gather_near_item(
                 C v = red[0][c][lane];
                 for (int w = 1; w < TG / 64; ++w) v += red[w][c][lane];
                 if constexpr (MODE == kNearOnly)
-                    yn[(int64_t)c * N + i] = v;
+                    stv<CO>(yn + (int64_t)c * N + i, v);
                 else
                     Y[(int64_t)(c0 + c) * ldy + perm[i]] = (XT)v;
             }
@@ -1677,7 +1697,7 @@ enum PKind : int32_t {
     PK_S2,         // class 2: one block per wave
     PK_S3,         // class 3: one block per wave
     PK_S4,         // class 4: one block per claim
-    PK_S5,         // class 5 (at most kPersistC5 rows and columns): one block per claim
+    PK_S5,         // (unused: class-5 blocks take the segmented route)
     PK_FUSED,      // NR > 1: any class, one block per wave
     PK_PROJ,       // segmented projections
     PK_NEAR,       // near field of a 64-row leaf chunk, into the near sums
@@ -1712,10 +1732,22 @@ struct PSlot {
 
 struct PSeg {
     int64_t claim0;        // first claim index of the segment
-    int64_t need;          // claims that must have completed before it starts
     int64_t first, nitems; // items [first, first + nitems) of the slot's table
     int32_t slot, kind, c0, per;
+    int32_t stage, ndep;   // its stage; the stages it needs complete
+    int32_t dep[3], dcnt[3];   // their ids and claim counts
 };
+// Launch counters: claim, unused, exit, error flag, three diagnostics, then
+// one completion count per stage.  Each stage count has a 128-byte line of
+// its own, away from the claim counter: hundreds of workgroups poll them, and
+// polls of one line queue with every other access to it.
+constexpr int kPersistLine = 32;   // ints per line
+constexpr int kPersistCtrBase = kPersistLine;
+constexpr int kPersistMaxStages = 1024;
+constexpr int kPersistCtrInts = kPersistCtrBase + kPersistLine * kPersistMaxStages;
+// right-hand sides one persistent launch takes (five stages per batch of
+// eight columns, and the permutation)
+constexpr int kPersistMaxCols = 8 * ((kPersistMaxStages - 1) / 5);
 
 constexpr int kPersistThreads = 256;
 constexpr int kPersistFusedRank = 64;       // projections one wave keeps in LDS at once
@@ -1732,19 +1764,24 @@ __device__ __forceinline__ int64_t uniform64(int64_t v) {
     return ((int64_t)hi << 32) | (uint32_t)lo;
 }
 
-template <typename C>
-__device__ __forceinline__ C ld_co(const C* p) {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+// waves per SIMD the persistent kernel is compiled for: FP64 factors need
+// about 250 registers a lane without spilling (two waves), FP32 about 170
+// (three)
+template <typename S>
+constexpr int persist_waves() {
+    return sizeof(S) == 8 ? 2 : 3;
 }
 
 template <typename XT, typename S, int NR>
-__global__ __launch_bounds__(kPersistThreads) void k_persist(const PSlot* __restrict__ slots,
+__global__ __launch_bounds__(kPersistThreads, persist_waves<S>()) void k_persist(const PSlot* __restrict__ slots,
                                                              const PSeg* __restrict__ segs,
                                                              int nseg, int64_t nclaims,
-                                                             int* ctr) {
+                                                             int nstages, int* ctr) {
     using C = S;
-    constexpr int KB4 = sizeof(C) == 8 ? 2 : 4;
-    constexpr int KB5 = sizeof(C) == 8 ? 1 : 2;
+    // tile shapes that keep the kernel at 3 waves per SIMD (the heaviest
+    // body decides every claim's occupancy): classes 1 and 2 one block per
+    // wave with batches of 4 terms, class 4 batches of one (FP64) or two terms
+    constexpr int KB4 = sizeof(C) == 8 ? 1 : 2;
     __shared__ int64_t s_claim;
     __shared__ C s_part[4][2][4];
     __shared__ C s_red[TG / 64][NR][64];
@@ -1759,6 +1796,29 @@ __global__ __launch_bounds__(kPersistThreads) void k_persist(const PSlot* __rest
     // workgroup barriers of this loop (the compiler would give the lanes of a
     // wave separate trips through them): wave 0 as a whole claims, waits
     // and counts, with lane-dependent values instead of lane conditions.
+    // Every vector one stage hands to another is written and read with
+    // device-coherent accesses (ldv / stv with CO), everything else the launch
+    // reads stays constant during it: so no cache needs writing back or
+    // invalidating between stages (on this chip either would act on a whole
+    // XCD's L2).  A stage's results are complete once every wave's stores
+    // have completed, which each wave waits for before its workgroup counts
+    // them; a workgroup reads them only after it saw the count.
+    // Claims finished but not yet counted, all of stage `cur`: a workgroup
+    // waits for a stage's dependencies once, on its first claim of the stage,
+    // and counts its claims of a stage when it moves on (before it waits for
+    // another stage) or leaves.
+    int pending = 0;
+    int cur = -1;
+    auto flush = [&] {
+        if (pending == 0) return;
+        __builtin_amdgcn_s_waitcnt(0);   // this wave's stores are complete
+        __syncthreads();
+        if (wv == 0)
+            __hip_atomic_fetch_add(ctr + kPersistCtrBase + kPersistLine * cur,
+                                   lane == 0 ? pending : 0, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+        pending = 0;
+    };
     for (;;) {
         if (wv == 0) {
             const int old = atomicAdd(ctr + 0, lane == 0 ? 1 : 0);
@@ -1782,37 +1842,47 @@ __global__ __launch_bounds__(kPersistThreads) void k_persist(const PSlot* __rest
         const PSlot& sl = slots[sg.slot];
         const int64_t i0 = sg.first + (g - sg.claim0) * sg.per;
         const int64_t i1 = min(i0 + sg.per, sg.first + sg.nitems);
-        // earlier stages complete?
-        if (sg.need > 0) {
+        // the stages this one needs complete?
+        if (sg.stage != cur) {
+            flush();
+            cur = sg.stage;
             if (wv == 0) {
                 // wave 0 polls; the wait is bounded by the wall clock, and a
                 // timed-out wait anywhere ends every wait (wrong results and a
                 // flag the host reads, instead of a hang)
                 const long long t0 = wall_clock64();
-                for (;;) {
-                    const int done = __builtin_amdgcn_readfirstlane(__hip_atomic_load(
-                        ctr + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
-                    if (done >= sg.need) break;
-                    const int abort = __builtin_amdgcn_readfirstlane(__hip_atomic_load(
-                        ctr + 3, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
-                    const bool late = (uint64_t)(wall_clock64() - t0) > kPersistWaitTicks;
-                    if (abort || late) {
-                        const int prev = __builtin_amdgcn_readfirstlane(__hip_atomic_fetch_or(
-                            ctr + 3, lane == 0 ? 1 : 0, __ATOMIC_RELAXED,
-                            __HIP_MEMORY_SCOPE_AGENT));
-                        if (prev == 0) {
-                            // the first timeout: which claim waited for what
-                            ctr[4] = (int)g;
-                            ctr[5] = (int)sg.need;
-                            ctr[6] = done;
+                for (int dd = 0; dd < sg.ndep; ++dd) {
+                    const int* cnt = ctr + kPersistCtrBase + kPersistLine * sg.dep[dd];
+                    int nap = 1;   // polls back off from 0.1 to 3.4 us
+                    for (;;) {
+                        const int done = __builtin_amdgcn_readfirstlane(__hip_atomic_load(
+                            cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+                        if (done >= sg.dcnt[dd]) break;
+                        // the flag shares the claim counter's line: read once backed off
+                        const int abort =
+                            nap < 32 ? 0
+                                     : __builtin_amdgcn_readfirstlane(__hip_atomic_load(
+                                           ctr + 3, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+                        const bool late = (uint64_t)(wall_clock64() - t0) > kPersistWaitTicks;
+                        if (abort || late) {
+                            const int prev = __builtin_amdgcn_readfirstlane(__hip_atomic_fetch_or(
+                                ctr + 3, lane == 0 ? 1 : 0, __ATOMIC_RELAXED,
+                                __HIP_MEMORY_SCOPE_AGENT));
+                            if (prev == 0) {
+                                // the first timeout: which claim waited for which stage
+                                ctr[4] = (int)g;
+                                ctr[5] = sg.dep[dd];
+                                ctr[6] = done;
+                            }
+                            dd = sg.ndep;
+                            break;
                         }
-                        break;
+                        for (int z = 0; z < nap; ++z) __builtin_amdgcn_s_sleep(4);
+                        nap = min(2 * nap, 32);
                     }
-                    __builtin_amdgcn_s_sleep(8);
                 }
             }
             __syncthreads();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         }
         const C* x = (const C*)sl.x;
         C* contrib = (C*)sl.contrib;
@@ -1823,58 +1893,54 @@ __global__ __launch_bounds__(kPersistThreads) void k_persist(const PSlot* __rest
             const int64_t p = i0 * 256 + tid;
             if (p < sl.N) {
                 const int64_t u = sl.perm[p];
-                for (int c = 0; c < sl.nrhs; ++c) xw[c * sl.N + p] = (C)X[c * sl.ldx + u];
+                for (int c = 0; c < sl.nrhs; ++c) stv<true>(xw + c * sl.N + p, (C)X[c * sl.ldx + u]);
             }
             break;
         }
         case PK_G8:
-            lr_group_body<S, C, 8>(sl.cblk, i0, i1, sl.sym, x, contrib);
+            lr_group_body<S, C, 8, true>(sl.cblk, i0, i1, sl.sym, x, contrib);
             break;
-        case PK_G16:
-            lr_group_body<S, C, 16>(sl.cblk, i0, i1, sl.sym, x, contrib);
-            break;
+        case PK_G16:   // class 1 as class 2
         case PK_S2:
             if (i0 + wv < i1)
-                lr_stream_body<S, C, 1, 1, 8>(sl.cblk[i0 + wv], sl.sym, x, contrib, nullptr, 0);
+                lr_stream_body<S, C, 1, 1, 4, true>(sl.cblk[i0 + wv], sl.sym, x, contrib, nullptr,
+                                                    0);
             break;
         case PK_S3:
             if (i0 + wv < i1)
-                lr_stream_body<S, C, 1, 2, 4>(sl.cblk[i0 + wv], sl.sym, x, contrib, nullptr, 0);
+                lr_stream_body<S, C, 1, 2, 4, true>(sl.cblk[i0 + wv], sl.sym, x, contrib, nullptr,
+                                                    0);
             break;
         case PK_S4:
-            lr_stream_body<S, C, 4, 4, KB4>(sl.cblk[i0], sl.sym, x, contrib,
+            lr_stream_body<S, C, 4, 4, KB4, true>(sl.cblk[i0], sl.sym, x, contrib,
                                             reinterpret_cast<C(*)[2][KB4]>(s_part), wv);
-            break;
-        case PK_S5:
-            lr_stream_body<S, C, 4, 9, KB5>(sl.cblk[i0], sl.sym, x, contrib,
-                                            reinterpret_cast<C(*)[2][KB5]>(s_part), wv);
             break;
         case PK_FUSED:
             if constexpr (NR > 1) {
                 if (i0 + wv < i1)
-                    lr_fused_body<S, C, NR, kPersistFusedRank>(sl.cblk[i0 + wv], sl.sym, x, sl.N,
+                    lr_fused_body<S, C, NR, kPersistFusedRank, true>(sl.cblk[i0 + wv], sl.sym, x, sl.N,
                                                                sl.nrhs, sg.c0, sl.CT, contrib,
                                                                s_tw[wv], s_sw[wv]);
             }
             break;
         case PK_PROJ:
-            project_body<S, C, NR>(sl.blocks, sl.proj[i0], sl.sym, x, sl.N, sl.nrhs, sg.c0,
+            project_body<S, C, NR, true>(sl.blocks, sl.proj[i0], sl.sym, x, sl.N, sl.nrhs, sg.c0,
                                    (C*)sl.pp, s_pred);
             break;
         case PK_PSUM: {
             const C* pp = (const C*)sl.pp;
-            proj_sum_body<C, NR>(i0 * 256 + tid, sl.psum, sl.npsum, sl.sym,
+            proj_sum_body<C, NR, true>(i0 * 256 + tid, sl.psum, sl.npsum, sl.sym,
                                  min(NR, sl.nrhs - sg.c0),
-                                 [pp](int64_t i) { return ld_co(pp + i); }, sl.TT, (C*)sl.tb,
+                                 [pp](int64_t i) { return ldv<true>(pp + i); }, sl.TT, (C*)sl.tb,
                                  (C*)sl.sb);
             break;
         }
         case PK_EXP: {
             const C* tb = (const C*)sl.tb;
             const C* sb = (const C*)sl.sb;
-            expand_split_body<S, C, NR>(
+            expand_split_body<S, C, NR, true>(
                 sl.blocks, sl.ex[i0], sl.nrhs, sg.c0, sl.TT,
-                [tb, sb](int side, int64_t i) { return ld_co((side ? sb : tb) + i); }, sl.CT,
+                [tb, sb](int side, int64_t i) { return ldv<true>((side ? sb : tb) + i); }, sl.CT,
                 contrib, s_red);
             break;
         }
@@ -1908,20 +1974,22 @@ __global__ __launch_bounds__(kPersistThreads) void k_persist(const PSlot* __rest
         default:
             break;
         }
-        // release this claim's writes, then count it
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        // LDS and the claim slot are reused by the next claim
         __syncthreads();
-        if (wv == 0)
-            __hip_atomic_fetch_add(ctr + 1, lane == 0 ? 1 : 0, __ATOMIC_RELEASE,
-                                   __HIP_MEMORY_SCOPE_AGENT);
+        ++pending;
     }
-    // the last workgroup out resets the counters (claim, done, exit)
+    flush();
+    // the last workgroup out resets the counters (claim, stages, exit); a
+    // workgroup's counts are complete before it counts itself out
+    __builtin_amdgcn_s_waitcnt(0);
     if (tid == 0) {
-        if (__hip_atomic_fetch_add(ctr + 2, 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) ==
+        if (__hip_atomic_fetch_add(ctr + 2, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ==
             (int)gridDim.x - 1) {
             __hip_atomic_store(ctr + 0, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_store(ctr + 1, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_store(ctr + 2, 0, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            for (int t = 0; t < nstages; ++t)
+                __hip_atomic_store(ctr + kPersistCtrBase + kPersistLine * t, 0, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(ctr + 2, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
     }
 }
@@ -1940,6 +2008,68 @@ int64_t mcore_extent(int64_t r, int64_t len, int nrp) {
     const int64_t f = 2 * (terms * ld + len + 1024) + 16;
     const int64_t x = 2 * (len + 1024) * (int64_t)nrp + 16;
     return std::max(f, x);
+}
+
+// The segmented route of block b: projections per term and row segment
+// (segments of at least 4096 rows so that enough workgroups stream the few
+// large blocks at once), their per-term sums, 64-row expansions.
+void split_route(hodlr_t h, int64_t b, std::vector<ProjSeg>& pj, std::vector<ProjSum>& ps,
+                 std::vector<WorkItem>& xe) {
+    const BlockDesc& bd = h->hblocks[b];
+    const int nseg = std::max(1, std::min(kProjSegMax, std::max(bd.m, bd.n) / 4096));
+    for (int k = 0; k < bd.rank; ++k) {
+        const int64_t pidx = (int64_t)ps.size();
+        ps.push_back(ProjSum{bd.toff + k, pidx, nseg, 0});
+        for (int g = 0; g < nseg; ++g) pj.push_back(ProjSeg{(int32_t)b, k, g, nseg, pidx});
+    }
+    for (int32_t i = 0; i < bd.m; i += 64)
+        xe.push_back(WorkItem{(int32_t)b, i, std::min(64, bd.m - i), 0});
+    if (h->opts.symmetric)
+        for (int32_t j = 0; j < bd.n; j += 64)
+            xe.push_back(WorkItem{(int32_t)b, j, std::min(64, bd.n - j), 1});
+}
+
+// The persistent plan: the per-class plan's classes in the same order,
+// except that class-4 blocks wider than seg_side and every class-5 block
+// join the segmented route (their terms projected by many workgroups at
+// once instead of streamed by one).  Replaces the persistent tables; the
+// next persistent launch rebuilds its claim queue.
+void plan_persistent(hodlr_t h, int seg_side) {
+    std::vector<int32_t> pgrp;
+    std::vector<ProjSeg> pproj;
+    std::vector<ProjSum> ppsum;
+    std::vector<WorkItem> pex;
+    h->p_class_off.assign(kNumClasses + 1, 0);
+    for (int c = 0; c < kNumClasses; ++c) {
+        h->p_class_off[c] = (int64_t)pgrp.size();
+        for (int64_t t = h->class_off[c]; t < h->class_off[c + 1]; ++t) {
+            const int32_t b = h->cls_ids[t];
+            const BlockDesc& bd = h->hblocks[b];
+            const int side = std::max(bd.m, bd.n);
+            if (c == kNumClasses - 1 || (c == kNumClasses - 2 && side > seg_side))
+                split_route(h, b, pproj, ppsum, pex);
+            else
+                pgrp.push_back(b);
+        }
+    }
+    h->p_class_off[kNumClasses] = (int64_t)pgrp.size();
+    for (int64_t b : h->split_ids) split_route(h, b, pproj, ppsum, pex);
+    auto upload = [&](const void* src, size_t bytes, void** dst) {
+        if (*dst) dfree(h, *dst);
+        *dst = dalloc(h, std::max<size_t>(bytes, 16));
+        if (bytes) HIP_CHECK(hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice));
+    };
+    std::vector<BlockDesc> pbd(pgrp.size());
+    for (size_t t = 0; t < pgrp.size(); ++t) pbd[t] = h->hblocks[pgrp[t]];
+    upload(pbd.data(), sizeof(BlockDesc) * pbd.size(), (void**)&h->p_class_blocks);
+    upload(pproj.data(), sizeof(ProjSeg) * pproj.size(), (void**)&h->p_proj);
+    upload(ppsum.data(), sizeof(ProjSum) * ppsum.size(), (void**)&h->p_psum);
+    upload(pex.data(), sizeof(WorkItem) * pex.size(), (void**)&h->p_exp);
+    h->p_n_proj = (int64_t)pproj.size();
+    h->p_n_psum = (int64_t)ppsum.size();
+    h->p_n_exp = (int64_t)pex.size();
+    h->p_seg_side = seg_side;
+    h->p_key.clear();
 }
 
 // Launch planning (host): which blocks one wave applies, how the others are
@@ -1985,24 +2115,8 @@ void plan_apply(hodlr_t h) {
     std::vector<std::vector<std::pair<int64_t, int32_t>>> cls(kNumClasses);
     for (int c = 0; c < 8; ++c) h->cls_felems[c] = h->cls_velems[c] = 0;
     h->split_blocks = h->split_felems = 0;
-    // the segmented route of block b: projections per term and row segment
-    // (segments of at least 4096 rows so that enough workgroups stream the
-    // few large blocks at once), their per-term sums, 64-row expansions
     auto add_split = [&](int64_t b, std::vector<ProjSeg>& pj, std::vector<ProjSum>& ps,
-                         std::vector<WorkItem>& xe) {
-        const BlockDesc& bd = h->hblocks[b];
-        const int nseg = std::max(1, std::min(kProjSegMax, std::max(bd.m, bd.n) / 4096));
-        for (int k = 0; k < bd.rank; ++k) {
-            const int64_t pidx = (int64_t)ps.size();
-            ps.push_back(ProjSum{bd.toff + k, pidx, nseg, 0});
-            for (int g = 0; g < nseg; ++g) pj.push_back(ProjSeg{(int32_t)b, k, g, nseg, pidx});
-        }
-        for (int32_t i = 0; i < bd.m; i += 64)
-            xe.push_back(WorkItem{(int32_t)b, i, std::min(64, bd.m - i), 0});
-        if (h->opts.symmetric)
-            for (int32_t j = 0; j < bd.n; j += 64)
-                xe.push_back(WorkItem{(int32_t)b, j, std::min(64, bd.n - j), 1});
-    };
+                         std::vector<WorkItem>& xe) { split_route(h, b, pj, ps, xe); };
     std::vector<int64_t> split_ids;
     for (int64_t b = 0; b < h->nblocks; ++b) {
         const BlockDesc& bd = h->hblocks[b];
@@ -2038,25 +2152,8 @@ void plan_apply(hodlr_t h) {
         for (auto& p : cls[c]) grp.push_back(p.second);
     }
     h->class_off[kNumClasses] = (int64_t)grp.size();
-    // the persistent plan: the same classes in the same order, except the
-    // class-5 blocks wider than kPersistC5 (they join the segmented route)
-    std::vector<int32_t> pgrp;
-    std::vector<ProjSeg> pproj;
-    std::vector<ProjSum> ppsum;
-    std::vector<WorkItem> pex;
-    h->p_class_off.assign(kNumClasses + 1, 0);
-    for (int c = 0; c < kNumClasses; ++c) {
-        h->p_class_off[c] = (int64_t)pgrp.size();
-        for (auto& pr : cls[c]) {
-            const BlockDesc& bd = h->hblocks[pr.second];
-            if (c == kNumClasses - 1 && std::max(bd.m, bd.n) > kPersistC5)
-                add_split(pr.second, pproj, ppsum, pex);
-            else
-                pgrp.push_back(pr.second);
-        }
-    }
-    h->p_class_off[kNumClasses] = (int64_t)pgrp.size();
-    for (int64_t b : split_ids) add_split(b, pproj, ppsum, pex);
+    h->cls_ids = grp;
+    h->split_ids = split_ids;
     // leaves: 64-row chunks, their near-field source ranges and, per level,
     // the contribution segments of the box containing them.  A leaf is a
     // leaf box of any level (in a uniform tree: the boxes of level kappa);
@@ -2146,17 +2243,7 @@ void plan_apply(hodlr_t h) {
     upload(nr.data(), sizeof(NearItem) * nr.size(), (void**)&h->near_items);
     h->n_near_items = (int64_t)nr.size();
     upload(rng.data(), sizeof(int2) * rng.size(), (void**)&h->near_rng);
-    {
-        std::vector<BlockDesc> pbd(pgrp.size());
-        for (size_t t = 0; t < pgrp.size(); ++t) pbd[t] = h->hblocks[pgrp[t]];
-        upload(pbd.data(), sizeof(BlockDesc) * pbd.size(), (void**)&h->p_class_blocks);
-        upload(pproj.data(), sizeof(ProjSeg) * pproj.size(), (void**)&h->p_proj);
-        upload(ppsum.data(), sizeof(ProjSum) * ppsum.size(), (void**)&h->p_psum);
-        upload(pex.data(), sizeof(WorkItem) * pex.size(), (void**)&h->p_exp);
-        h->p_n_proj = (int64_t)pproj.size();
-        h->p_n_psum = (int64_t)ppsum.size();
-        h->p_n_exp = (int64_t)pex.size();
-    }
+    plan_persistent(h, h->p_seg_side);
     upload(seg.data(), sizeof(SegRef) * seg.size(), (void**)&h->leaf_seg);
     h->nleaf = nleaf;
     // matrix-core plan for BF16 factors (several right-hand sides)
@@ -2308,6 +2395,43 @@ inline unsigned near_grid(hodlr_t h, int nc, size_t factor_elem_bytes) {
     const double light = kNearCapPairsPerByte * (double)fe * (double)factor_elem_bytes;
     const int64_t n = h->n_near_items;
     return (unsigned)((double)h->near_pairs * nc <= light ? std::min(n, kNearGridCap) : n);
+}
+
+// Candidate tile shapes <W, CH, KB> of the single-RHS block classes (W waves
+// per block, CH rows per lane, KB terms per register batch); candidate 0 is
+// the default, the autotuner may pick another per handle.  Classes 0 and 1
+// (a lane group per block) have one shape.
+constexpr int kTuneCands = 3;
+inline int class_candidates(int c) { return c <= 1 ? 1 : (c == 5 ? 2 : 3); }
+
+template <typename S, typename C>
+void launch_class(int c, int cand, const BlockDesc* it, int64_t cnt, int sym, const C* x,
+                  C* contrib, hipStream_t s) {
+    const unsigned g = (unsigned)cnt;
+    constexpr int K4 = sizeof(C) == 8 ? 2 : 4, K5 = sizeof(C) == 8 ? 1 : 2;
+    switch (c * kTuneCands + cand) {
+    case 0 * kTuneCands + 0:
+        k_lr_group<S, C, 8><<<nblk(cnt * 8, 256), 256, 0, s>>>(it, cnt, sym, x, contrib);
+        break;
+    case 1 * kTuneCands + 0:
+        k_lr_group<S, C, 16><<<nblk(cnt * 16, 256), 256, 0, s>>>(it, cnt, sym, x, contrib);
+        break;
+    case 2 * kTuneCands + 0: k_lr_stream<S, C, 1, 1, 8><<<g, 64, 0, s>>>(it, sym, x, contrib); break;
+    case 2 * kTuneCands + 1: k_lr_stream<S, C, 1, 1, 4><<<g, 64, 0, s>>>(it, sym, x, contrib); break;
+    case 2 * kTuneCands + 2: k_lr_stream<S, C, 1, 1, 16><<<g, 64, 0, s>>>(it, sym, x, contrib); break;
+    case 3 * kTuneCands + 0: k_lr_stream<S, C, 1, 2, 4><<<g, 64, 0, s>>>(it, sym, x, contrib); break;
+    case 3 * kTuneCands + 1: k_lr_stream<S, C, 1, 2, 8><<<g, 64, 0, s>>>(it, sym, x, contrib); break;
+    case 3 * kTuneCands + 2: k_lr_stream<S, C, 2, 1, 8><<<g, 128, 0, s>>>(it, sym, x, contrib); break;
+    case 4 * kTuneCands + 0: k_lr_stream<S, C, 4, 4, K4><<<g, 256, 0, s>>>(it, sym, x, contrib); break;
+    case 4 * kTuneCands + 1:
+        k_lr_stream<S, C, 4, 4, 2 * K4><<<g, 256, 0, s>>>(it, sym, x, contrib);
+        break;
+    case 4 * kTuneCands + 2: k_lr_stream<S, C, 8, 2, K4><<<g, 512, 0, s>>>(it, sym, x, contrib); break;
+    case 5 * kTuneCands + 0: k_lr_stream<S, C, 8, 9, K5><<<g, 512, 0, s>>>(it, sym, x, contrib); break;
+    default:
+        k_lr_stream<S, C, 8, 9, 2 * K5><<<g, 512, 0, s>>>(it, sym, x, contrib);
+        break;
+    }
 }
 
 // aux: the stream of the near field (the handle's second stream, or s itself
@@ -2507,30 +2631,8 @@ void run_matvec(hodlr_t h, const XT* X, int64_t ldx, int nrhs, XT* Y, int64_t ld
                     if (ev && nev > 5 && c0 == 0) HIP_CHECK(hipEventRecord(ev[5 + c], s));
                     continue;
                 }
-                const BlockDesc* it = h->class_blocks + n0;
-                const unsigned g = (unsigned)cnt;
-                switch (c) {
-                case 0:
-                    k_lr_group<S, C, 8><<<nblk(cnt * 8, 256), 256, 0, s>>>(it, cnt, sym, x, contrib);
-                    break;
-                case 1:
-                    k_lr_group<S, C, 16><<<nblk(cnt * 16, 256), 256, 0, s>>>(it, cnt, sym, x, contrib);
-                    break;
-                case 2:
-                    k_lr_stream<S, C, 1, 1, 8><<<g, 64, 0, s>>>(it, sym, x, contrib);
-                    break;
-                case 3:
-                    k_lr_stream<S, C, 1, 2, 4><<<g, 64, 0, s>>>(it, sym, x, contrib);
-                    break;
-                case 4:
-                    k_lr_stream<S, C, 4, 4, sizeof(C) == 8 ? 2 : 4><<<g, 256, 0, s>>>(it, sym, x,
-                                                                                   contrib);
-                    break;
-                default:
-                    k_lr_stream<S, C, 8, 9, sizeof(C) == 8 ? 1 : 2><<<g, 512, 0, s>>>(it, sym, x,
-                                                                                   contrib);
-                    break;
-                }
+                launch_class<S, C>(c, h->tune_cls[c], h->class_blocks + n0, cnt, sym, x, contrib,
+                                   s);
                 if (ev && nev > 5 && c0 == 0) HIP_CHECK(hipEventRecord(ev[5 + c], s));
             }
         } else {
@@ -2598,51 +2700,103 @@ struct PSlotHost {
     char* ws;
 };
 
-// The claim queue of a persistent launch (stage order, see k_persist).
+// The claim queue of a persistent launch.  Stages and what they need:
+//   P     the permutation into tree order
+//   A_b   column batch b: the blocks of every class and the segmented
+//         projections (needs P, and G_{b-1}, which last read the buffers)
+//   S_b   sums of the segmented projections (needs A_b)
+//   N_b   the near field (needs P and G_{b-1}; queued after S_b, so that it
+//         runs while S_b waits for A_b)
+//   E_b   expansions of the segmented blocks (needs S_b)
+//   G_b   the gather (needs A_b, N_b, E_b)
+// Every stage is queued after the stages it needs.
 void persist_segments(const std::vector<PSlotHost>& sl, int NR, std::vector<PSeg>& segs,
-                      int64_t& nclaims) {
+                      int64_t& nclaims, int& nstages) {
     segs.clear();
     int64_t claim = 0;
-    auto add = [&](int slot, int kind, int c0, int64_t first, int64_t n, int per, int64_t need) {
+    std::vector<int64_t> scnt;   // claims per stage
+    auto stage = [&] {
+        scnt.push_back(0);
+        return (int)scnt.size() - 1;
+    };
+    std::vector<int> deps;
+    auto add = [&](int st, int slot, int kind, int c0, int64_t first, int64_t n, int per) {
         if (n <= 0) return;
-        segs.push_back(PSeg{claim, need, first, n, slot, kind, c0, per});
-        claim += (n + per - 1) / per;
+        PSeg q{};
+        q.claim0 = claim;
+        q.first = first;
+        q.nitems = n;
+        q.slot = slot;
+        q.kind = kind;
+        q.c0 = c0;
+        q.per = per;
+        q.stage = st;
+        q.ndep = 0;
+        segs.push_back(q);
+        const int64_t c = (n + per - 1) / per;
+        claim += c;
+        scnt[st] += c;
+    };
+    // stage ids each segment depends on, set after all claims are known
+    std::vector<std::vector<int>> sdeps;
+    auto need = [&](int st, std::initializer_list<int> d) {
+        if ((int)sdeps.size() <= st) sdeps.resize(st + 1);
+        for (int x : d)
+            if (x >= 0) sdeps[st].push_back(x);
     };
     int maxcb = 0;
     for (auto& q : sl) maxcb = std::max(maxcb, (q.nrhs + NR - 1) / NR);
-    for (int t = 0; t < (int)sl.size(); ++t) add(t, PK_PERM, 0, 0, (sl[t].h->N + 255) / 256, 1, 0);
+    const int P = stage();
+    need(P, {});
+    for (int t = 0; t < (int)sl.size(); ++t)
+        add(P, t, PK_PERM, 0, 0, (sl[t].h->N + 255) / 256, 1);
+    int Gprev = -1;
     for (int cb = 0; cb < maxcb; ++cb) {
         const int c0 = cb * NR;
-        int64_t need = claim;
+        const int A = stage(), Sx = stage(), Nr = stage(), E = stage(), G = stage();
+        need(A, {P, Gprev});
+        need(Sx, {A});
+        need(Nr, {P, Gprev});
+        need(E, {Sx});
+        need(G, {A, Nr, E});
         for (int t = 0; t < (int)sl.size(); ++t) {
             hodlr_t h = sl[t].h;
             if (sl[t].nrhs <= c0) continue;
             const std::vector<int64_t>& o = h->p_class_off;
-            add(t, PK_PROJ, c0, 0, h->p_n_proj, 1, need);
+            add(A, t, PK_PROJ, c0, 0, h->p_n_proj, 1);
             if (NR == 1) {
-                add(t, PK_S5, c0, o[5], o[6] - o[5], 1, need);
-                add(t, PK_S4, c0, o[4], o[5] - o[4], 1, need);
+                add(A, t, PK_S4, c0, o[4], o[5] - o[4], 1);
+                add(A, t, PK_S3, c0, o[3], o[4] - o[3], 4);
+                add(A, t, PK_S2, c0, o[2], o[3] - o[2], 4);
+                add(A, t, PK_G16, c0, o[1], o[2] - o[1], 4);
+                add(A, t, PK_G8, c0, o[0], o[1] - o[0], 32);
             } else {
-                add(t, PK_FUSED, c0, o[0], o[6] - o[0], 4, need);
-            }
-            add(t, PK_NEAR, c0, 0, h->n_near_items, 1, need);
-            if (NR == 1) {
-                add(t, PK_S3, c0, o[3], o[4] - o[3], 4, need);
-                add(t, PK_S2, c0, o[2], o[3] - o[2], 4, need);
-                add(t, PK_G16, c0, o[1], o[2] - o[1], 16, need);
-                add(t, PK_G8, c0, o[0], o[1] - o[0], 32, need);
+                add(A, t, PK_FUSED, c0, o[0], o[6] - o[0], 4);
             }
         }
-        need = claim;
         for (int t = 0; t < (int)sl.size(); ++t)
             if (sl[t].nrhs > c0)
-                add(t, PK_PSUM, c0, 0, (sl[t].h->p_n_psum * 2 * NR + 255) / 256, 1, need);
-        need = claim;
+                add(Sx, t, PK_PSUM, c0, 0, (sl[t].h->p_n_psum * 2 * NR + 255) / 256, 1);
         for (int t = 0; t < (int)sl.size(); ++t)
-            if (sl[t].nrhs > c0) add(t, PK_EXP, c0, 0, sl[t].h->p_n_exp, 1, need);
-        need = claim;
+            if (sl[t].nrhs > c0) add(Nr, t, PK_NEAR, c0, 0, sl[t].h->n_near_items, 1);
         for (int t = 0; t < (int)sl.size(); ++t)
-            if (sl[t].nrhs > c0) add(t, PK_GATHER, c0, 0, sl[t].h->n_near_items, 1, need);
+            if (sl[t].nrhs > c0) add(E, t, PK_EXP, c0, 0, sl[t].h->p_n_exp, 1);
+        for (int t = 0; t < (int)sl.size(); ++t)
+            if (sl[t].nrhs > c0) add(G, t, PK_GATHER, c0, 0, sl[t].h->n_near_items, 1);
+        Gprev = G;
+    }
+    nstages = (int)scnt.size();
+    if (nstages > kPersistMaxStages)
+        fail(HODLR_EUNSUPPORTED, "more right-hand sides than one persistent launch takes");
+    sdeps.resize(nstages);
+    for (auto& q : segs) {
+        // a dependency with no claims is complete from the start
+        for (int x : sdeps[q.stage])
+            if (scnt[x] > 0) {
+                q.dep[q.ndep] = x;
+                q.dcnt[q.ndep] = (int32_t)scnt[x];
+                ++q.ndep;
+            }
     }
     nclaims = claim;
 }
@@ -2717,8 +2871,9 @@ void persist_check(const int* ctr, hipStream_t s) {
     HIP_CHECK(hipStreamSynchronize(s));
     if (v[3])
         fail(HODLR_EDEVICE, "persistent product: a stage wait timed out (claim " +
-                                std::to_string(v[4]) + " waited for " + std::to_string(v[5]) +
-                                " completed claims, saw " + std::to_string(v[6]) + ")");
+                                std::to_string(v[4]) + " waited for stage " +
+                                std::to_string(v[5]) + ", which had " + std::to_string(v[6]) +
+                                " completed claims)");
 }
 
 // Launches the persistent product of the slots on s.  dslots / dsegs: device
@@ -2726,8 +2881,8 @@ void persist_check(const int* ctr, hipStream_t s) {
 // `upload` is set; ctr: four zeroed ints (left zeroed by the launch).
 template <typename XT, typename S, int NR>
 void persist_launch(const std::vector<PSlotHost>& slots, const std::vector<PSeg>& segs,
-                    int64_t nclaims, PSlot* dslots, PSeg* dsegs, bool upload, int* ctr,
-                    hipStream_t s) {
+                    int64_t nclaims, int nstages, PSlot* dslots, PSeg* dsegs, bool upload,
+                    int* ctr, hipStream_t s) {
     if (upload) {
         std::vector<PSlot> ps(slots.size());
         for (size_t t = 0; t < slots.size(); ++t) ps[t] = persist_slot<S>(slots[t], NR);
@@ -2738,7 +2893,7 @@ void persist_launch(const std::vector<PSlotHost>& slots, const std::vector<PSeg>
     }
     if (nclaims <= 0) return;
     k_persist<XT, S, NR><<<persist_grid<XT, S, NR>(nclaims), kPersistThreads, 0, s>>>(
-        dslots, dsegs, (int)segs.size(), nclaims, ctr);
+        dslots, dsegs, (int)segs.size(), nclaims, nstages, ctr);
     HIP_CHECK(hipGetLastError());
 }
 
@@ -2842,8 +2997,8 @@ void reserve_workspace(hodlr_t h, int nrhs, int compute_prec, hipStream_t s) {
     if (!h->p_ctr) {
         // the persistent launch's counters start at zero and each launch
         // leaves them at zero
-        h->p_ctr = (int*)dalloc(h, 8 * sizeof(int));
-        HIP_CHECK(hipMemset(h->p_ctr, 0, 8 * sizeof(int)));
+        h->p_ctr = (int*)dalloc(h, kPersistCtrInts * sizeof(int));
+        HIP_CHECK(hipMemset(h->p_ctr, 0, kPersistCtrInts * sizeof(int)));
     }
     if (h->ws_bytes < need) {
         if (h->ws) {
@@ -2880,7 +3035,8 @@ void persist_single(hodlr_t h, const void* X, int64_t ldx, int nrhs, void* Y, in
         std::vector<PSlotHost> sl = {PSlotHost{h, X, ldx, Y, ldy, nrhs, (char*)h->ws}};
         std::vector<PSeg> segs;
         int64_t nclaims = 0;
-        persist_segments(sl, NR, segs, nclaims);
+        int nstages = 0;
+        persist_segments(sl, NR, segs, nclaims, nstages);
         if (!h->p_dslot) h->p_dslot = dalloc(h, sizeof(PSlot));
         if (h->p_segcap < segs.size()) {
             HIP_CHECK(hipStreamSynchronize(s));
@@ -2888,18 +3044,19 @@ void persist_single(hodlr_t h, const void* X, int64_t ldx, int nrhs, void* Y, in
             h->p_segcap = segs.size() + 16;
             h->p_dsegs = dalloc(h, sizeof(PSeg) * h->p_segcap);
         }
-        persist_launch<XT, S, NR>(sl, segs, nclaims, (PSlot*)h->p_dslot, (PSeg*)h->p_dsegs, true,
-                                  h->p_ctr, s);
+        persist_launch<XT, S, NR>(sl, segs, nclaims, nstages, (PSlot*)h->p_dslot,
+                                  (PSeg*)h->p_dsegs, true, h->p_ctr, s);
         persist_check(h->p_ctr, s);   // synchronises: the host tables may go
         h->p_key = key;
         h->p_nclaims = nclaims;
         h->p_nseg = segs.size();
+        h->p_nstages = nstages;
         return;
     }
     std::vector<PSlotHost> none;
     std::vector<PSeg> segs(h->p_nseg);   // only the count is used without upload
-    persist_launch<XT, S, NR>(none, segs, h->p_nclaims, (PSlot*)h->p_dslot, (PSeg*)h->p_dsegs,
-                              false, h->p_ctr, s);
+    persist_launch<XT, S, NR>(none, segs, h->p_nclaims, h->p_nstages, (PSlot*)h->p_dslot,
+                              (PSeg*)h->p_dsegs, false, h->p_ctr, s);
 }
 
 template <typename XT, typename S>
@@ -2917,7 +3074,7 @@ void persist_dispatch(hodlr_t h, const void* X, int64_t ldx, int nrhs, void* Y, 
 void matvec(hodlr_t h, const void* X, int64_t ldx, int nrhs, int x_prec, void* Y, int64_t ldy,
             int compute_prec, hipEvent_t const* ev, int nev, hipStream_t s) {
     reserve_workspace(h, nrhs, compute_prec, s);
-    if (!ev && persistent_route(h, x_prec, compute_prec)) {
+    if (!ev && nrhs <= kPersistMaxCols && persistent_route(h, x_prec, compute_prec)) {
         const bool s64 = h->opts.storage == HODLR_FP64;
         if (x_prec == HODLR_FP64) {
             if (s64) persist_dispatch<double, double>(h, X, ldx, nrhs, Y, ldy, s);
@@ -2936,15 +3093,222 @@ template <typename XT, typename S, int NR>
 void batch_launch(const std::vector<PSlotHost>& sl, int* ctr, hodlr_t h0, hipStream_t s) {
     std::vector<PSeg> segs;
     int64_t nclaims = 0;
-    persist_segments(sl, NR, segs, nclaims);
+    int nstages = 0;
+    persist_segments(sl, NR, segs, nclaims, nstages);
     PSlot* dslot = (PSlot*)dalloc(h0, sizeof(PSlot) * sl.size());
     PSeg* dsegs = (PSeg*)dalloc(h0, sizeof(PSeg) * std::max<size_t>(segs.size(), 1));
-    persist_launch<XT, S, NR>(sl, segs, nclaims, dslot, dsegs, true, ctr, s);
+    persist_launch<XT, S, NR>(sl, segs, nclaims, nstages, dslot, dsegs, true, ctr, s);
     persist_check(ctr, s);
     dfree(h0, dslot);
     dfree(h0, dsegs);
 }
 }  // namespace
+
+// Device tables of asynchronous batched launches (one set per server slot).
+struct BatchTables {
+    PSlot* dslot = nullptr;
+    PSeg* dsegs = nullptr;
+    int* ctr = nullptr;
+    int max_slots = 0;
+    size_t segcap = 0;
+};
+
+void* batch_tables_create(int max_slots, size_t segcap) {
+    auto* t = new BatchTables();
+    t->max_slots = max_slots;
+    t->segcap = segcap;
+    if (hipMalloc(&t->dslot, sizeof(PSlot) * max_slots) != hipSuccess ||
+        hipMalloc(&t->dsegs, sizeof(PSeg) * segcap) != hipSuccess ||
+        hipMalloc(&t->ctr, kPersistCtrInts * sizeof(int)) != hipSuccess) {
+        (void)hipGetLastError();
+        (void)hipFree(t->dslot);
+        (void)hipFree(t->dsegs);
+        delete t;
+        fail(HODLR_ENOMEM, "batch tables");
+    }
+    HIP_CHECK(hipMemset(t->ctr, 0, kPersistCtrInts * sizeof(int)));
+    return t;
+}
+
+void batch_tables_destroy(void* p) {
+    auto* t = (BatchTables*)p;
+    if (!t) return;
+    (void)hipFree(t->dslot);
+    (void)hipFree(t->dsegs);
+    (void)hipFree(t->ctr);
+    delete t;
+}
+
+namespace {
+template <typename XT, typename S, int NR>
+void batch_async(const std::vector<PSlotHost>& sl, BatchTables* t, hipStream_t s) {
+    std::vector<PSeg> segs;
+    int64_t nclaims = 0;
+    int nstages = 0;
+    persist_segments(sl, NR, segs, nclaims, nstages);
+    if ((int)sl.size() > t->max_slots || segs.size() > t->segcap)
+        fail(HODLR_EINVAL, "batch larger than its tables");
+    persist_launch<XT, S, NR>(sl, segs, nclaims, nstages, t->dslot, t->dsegs, true, t->ctr, s);
+}
+}  // namespace
+
+void matvec_batch_async(int nslots, hodlr_t const* hs, const void* const* X, const int64_t* ldx,
+                        const int* nrhs, int x_prec, void* const* Y, const int64_t* ldy,
+                        void* tables, hipStream_t s) {
+    if (nslots <= 0) return;
+    auto* t = (BatchTables*)tables;
+    const int st = hs[0]->opts.storage;
+    const int comp = st == HODLR_FP64 ? HODLR_FP64 : HODLR_FP32;
+    int maxr = 1;
+    for (int i = 0; i < nslots; ++i) {
+        if (hs[i]->opts.storage != st || hs[i]->opts.skeleton || st == HODLR_BF16)
+            fail(HODLR_EINVAL, "a batch needs FP64 or FP32 factors of one storage precision");
+        maxr = std::max(maxr, nrhs[i]);
+    }
+    const int NR = maxr == 1 ? 1 : (maxr <= 4 ? 4 : 8);
+    std::vector<PSlotHost> sl;
+    for (int i = 0; i < nslots; ++i) {
+        const int sizing = NR == 1 ? 1 : std::max(nrhs[i], NR == 4 ? 2 : 5);
+        reserve_workspace(hs[i], sizing, comp, s);
+        sl.push_back(PSlotHost{hs[i], X[i], ldx[i], Y[i], ldy[i], nrhs[i], (char*)hs[i]->ws});
+    }
+    const bool s64 = st == HODLR_FP64;
+#define HODLR_BATCH(XT, S)                                                                      \
+    do {                                                                                        \
+        if (NR == 1) batch_async<XT, S, 1>(sl, t, s);                                           \
+        else if (NR == 4) batch_async<XT, S, 4>(sl, t, s);                                      \
+        else batch_async<XT, S, 8>(sl, t, s);                                                   \
+    } while (0)
+    if (x_prec == HODLR_FP64) {
+        if (s64) HODLR_BATCH(double, double);
+        else HODLR_BATCH(double, float);
+    } else {
+        if (s64) HODLR_BATCH(float, double);
+        else HODLR_BATCH(float, float);
+    }
+#undef HODLR_BATCH
+}
+
+namespace {
+// mean time of `reps` calls of fn on s after one untimed call, in ms
+template <typename F>
+double time_ms(F&& fn, hipStream_t s, int reps) {
+    hipEvent_t a, b;
+    HIP_CHECK(hipEventCreate(&a));
+    HIP_CHECK(hipEventCreate(&b));
+    fn();
+    HIP_CHECK(hipEventRecord(a, s));
+    for (int i = 0; i < reps; ++i) fn();
+    HIP_CHECK(hipEventRecord(b, s));
+    HIP_CHECK(hipEventSynchronize(b));
+    float ms = 0.f;
+    HIP_CHECK(hipEventElapsedTime(&ms, a, b));
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    return (double)ms / reps;
+}
+
+// every tile-shape candidate of every single-RHS block class, timed alone on
+// the handle's own blocks (inputs: the workspace's x; outputs: its
+// contribution segments), the fastest kept
+template <typename S, typename C>
+void tune_classes(hodlr_t h, hodlr_tuning* out, hipStream_t s, int reps) {
+    C* x = (C*)h->ws;
+    C* contrib = x + h->N;
+    const int sym = h->opts.symmetric ? 1 : 0;
+    for (int c = 0; c < kNumClasses; ++c) {
+        const int64_t n0 = h->class_off[c], cnt = h->class_off[c + 1] - n0;
+        h->tune_cls[c] = 0;
+        out->class_choice[c] = 0;
+        out->class_ms[c] = 0.0;
+        if (!cnt) continue;
+        double best = 1e300;
+        for (int cand = 0; cand < class_candidates(c); ++cand) {
+            const double ms = time_ms(
+                [&] {
+                    launch_class<S, C>(c, cand, h->class_blocks + n0, cnt, sym, x, contrib, s);
+                    HIP_CHECK(hipGetLastError());
+                },
+                s, reps);
+            if (ms < best) {
+                best = ms;
+                h->tune_cls[c] = cand;
+            }
+        }
+        out->class_choice[c] = h->tune_cls[c];
+        out->class_ms[c] = best;
+    }
+}
+}  // namespace
+
+void autotune(hodlr_t h, int nrhs, int x_prec, int compute_prec, hodlr_tuning* out,
+              hipStream_t s) {
+    const int64_t N = h->N;
+    const size_t xs = x_prec == HODLR_FP64 ? 8 : 4;
+    std::memset(out, 0, sizeof(*out));
+    void* X = dalloc(h, xs * (size_t)N * nrhs);
+    void* Y = dalloc(h, xs * (size_t)N * nrhs);
+    HIP_CHECK(hipMemsetAsync(X, 0, xs * (size_t)N * nrhs, s));
+    reserve_workspace(h, nrhs, compute_prec, s);
+    const int reps = 5;
+    const int saved = h->use_persistent;
+    try {
+        if (nrhs == 1 && !h->opts.skeleton) {
+            const bool c32 = compute_prec == HODLR_FP32;
+            switch (h->opts.storage) {
+            case HODLR_FP64:
+                if (c32) tune_classes<double, float>(h, out, s, reps);
+                else tune_classes<double, double>(h, out, s, reps);
+                break;
+            case HODLR_FP32:
+                if (c32) tune_classes<float, float>(h, out, s, reps);
+                else tune_classes<float, double>(h, out, s, reps);
+                break;
+            default:
+                tune_classes<bf16, float>(h, out, s, reps);
+                break;
+            }
+        }
+        auto product = [&] { matvec(h, X, N, nrhs, x_prec, Y, N, compute_prec, nullptr, 0, s); };
+        h->use_persistent = 0;
+        out->class_route_ms = time_ms(product, s, reps);
+        h->use_persistent = 1;
+        if (persistent_route(h, x_prec, compute_prec)) {
+            // the persistent plan's widest block a workgroup streams alone:
+            // every class-4 block (1024), or only those up to 512 or 256 rows
+            // (the wider ones segmented over many workgroups)
+            const int sides[3] = {1024, 512, 256};
+            double best = 1e300;
+            int keep = sides[0];
+            for (int side : sides) {
+                plan_persistent(h, side);
+                product();   // builds the claim queue outside the timing
+                const double ms = time_ms(product, s, reps);
+                if (ms < best) {
+                    best = ms;
+                    keep = side;
+                }
+            }
+            if (keep != h->p_seg_side) plan_persistent(h, keep);
+            out->persistent_ms = best;
+            out->seg_side = keep;
+            out->route = out->persistent_ms < out->class_route_ms ? 1 : 0;
+        } else {
+            out->persistent_ms = 0.0;
+            out->route = 0;
+        }
+        h->use_persistent = out->route;
+    } catch (...) {
+        h->use_persistent = saved;
+        (void)hipStreamSynchronize(s);
+        dfree(h, X);
+        dfree(h, Y);
+        throw;
+    }
+    HIP_CHECK(hipStreamSynchronize(s));
+    dfree(h, X);
+    dfree(h, Y);
+}
 
 void matvec_batch(int nslots, hodlr_t const* hs, const void* const* X, const int64_t* ldx,
                   const int* nrhs, int x_prec, void* const* Y, const int64_t* ldy, int* ctr,

@@ -342,12 +342,17 @@ struct hodlr_handle_s {
     int64_t p_n_proj = 0, p_n_psum = 0, p_n_exp = 0;
     int* p_ctr = nullptr;       // its launch counters: claim, done, exit, error, diagnostics
     int use_persistent = -1;    // product route: 1 persistent; 0 or -1 (not chosen) per-class
+    int tune_cls[8]{};          // tile-shape candidate of each single-RHS block class
     void* p_dslot = nullptr;    // device slot table and claim queue of the last product
     void* p_dsegs = nullptr;
     size_t p_segcap = 0;
     std::vector<int64_t> p_key; // what they were built for (pointers, sizes, types)
     int64_t p_nclaims = 0;
     size_t p_nseg = 0;
+    int p_nstages = 0;
+    int p_seg_side = 1024;      // persistent plan: blocks wider than this take the segmented route
+    std::vector<int32_t> cls_ids;   // stored blocks in class order (host)
+    std::vector<int64_t> split_ids; // the blocks wider than 4608 (host)
     // matvec workspace
     void* ws = nullptr;
     size_t ws_bytes = 0;
@@ -400,6 +405,18 @@ bool persistent_route(hodlr_t h, int x_prec, int compute_prec);
 // compute precision = storage precision, FP64 or FP32); ctr: four zeroed ints
 // owned by the caller, dslot/dsegs: device tables the caller owns, with room
 // for nslots slots and *segcap segments (grown with dalloc on h0 if needed)
+// asynchronous batched products (no synchronisation; completion by the
+// caller's events) with preallocated tables of up to max_slots handles and
+// segcap queue segments
+void* batch_tables_create(int max_slots, size_t segcap);
+void batch_tables_destroy(void* tables);
+void matvec_batch_async(int nslots, hodlr_t const* hs, const void* const* X, const int64_t* ldx,
+                        const int* nrhs, int x_prec, void* const* Y, const int64_t* ldy,
+                        void* tables, hipStream_t s);
+// times the tile-shape candidates of the block classes and the two routes
+// on this handle, keeps the fastest of each (see hodlr_autotune)
+void autotune(hodlr_t h, int nrhs, int x_prec, int compute_prec, hodlr_tuning* out,
+              hipStream_t s);
 void matvec_batch(int nslots, hodlr_t const* hs, const void* const* X, const int64_t* ldx,
                   const int* nrhs, int x_prec, void* const* Y, const int64_t* ldy, int* ctr,
                   hipStream_t s);

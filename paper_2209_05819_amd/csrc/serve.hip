@@ -7,10 +7,13 @@
 //   - Requests (products and solves) queue in arrival order.  A scheduler
 //     thread starts work whenever a set is idle and one of max_concurrent
 //     stream slots is free: all queued products of that set (in order, up to
-//     max_batch_cols columns) are gathered into one batch and applied in one
-//     product; a solve runs on a worker thread on its own slot.  Work on
-//     different sets overlaps on the device; requests arriving while others
-//     run are admitted as slots and memory free up.
+//     max_batch_cols columns) are gathered into one product, and the queued
+//     products of other idle sets with the same factor precision (FP64 or
+//     FP32) join the same launch (one persistent launch applies every set of
+//     the batch, up to kBatchSets sets and the slot's buffer); a solve runs
+//     on a worker thread on its own slot.  Work on different slots overlaps
+//     on the device; requests arriving while others run are admitted as
+//     slots and memory free up.
 //   - Completion is observed through an event per slot; each request records
 //     its queueing and running time.
 #include <algorithm>
@@ -49,17 +52,22 @@ struct Set {
     bool busy = false;
 };
 
+constexpr int kBatchSets = 16;        // sets one batched launch applies at most
+constexpr size_t kBatchSegs = 8192;   // claim-queue segments of one batched launch
+
 struct Slot {
     hipStream_t s = nullptr;
     hipEvent_t ev = nullptr;
-    double* xb = nullptr;   // batch input, max_points x max_batch_cols
+    double* xb = nullptr;   // batch input, max_points x max_batch_cols elements
     double* yb = nullptr;
+    void* bt = nullptr;     // device tables of batched launches
     bool busy = false;
-    // the running job
-    int set = -1;
+    // the running job: its sets and, per set, its requests (in order)
+    std::vector<int> sets;
     bool solve = false;
     std::vector<Req*> reqs;
-    std::vector<int> col0;
+    std::vector<int> req_set;      // position in `sets` of each request
+    std::vector<int64_t> xoff;     // element offset of each request's columns in xb / yb
     size_t bytes = 0;
     std::thread worker;
     std::atomic<bool> worker_done{false};
@@ -100,37 +108,68 @@ void finish_job(hodlr_server_s* S, Slot& sl, hodlr_status st, const std::string&
         else
             ++S->stats.failed;
     }
-    S->sets[sl.set].busy = false;
+    for (int st : sl.sets) S->sets[st].busy = false;
     S->used -= sl.bytes;
     sl.bytes = 0;
     sl.busy = false;
     sl.reqs.clear();
-    sl.col0.clear();
+    sl.req_set.clear();
+    sl.xoff.clear();
+    sl.sets.clear();
     --S->running;
 }
 
-// start the matrix-vector batch in slot sl (called with the lock held)
+// start the products of slot sl (called with the lock held): the requests
+// of each set side by side in the slot's buffer (set g's columns at offset
+// xoff), one product per set, or one batched launch for several sets
 void launch_products(hodlr_server_s* S, Slot& sl) {
-    hodlr_t h = S->sets[sl.set].h;
-    const int64_t N = h->N;
-    int cols = 0;
-    for (Req* q : sl.reqs) {
-        sl.col0.push_back(cols);
-        cols += q->r.nrhs;
+    const int ng = (int)sl.sets.size();
+    std::vector<hodlr_t> hs(ng);
+    std::vector<int> cols(ng, 0);
+    std::vector<int64_t> goff(ng, 0);
+    for (int g = 0; g < ng; ++g) hs[g] = S->sets[sl.sets[g]].h;
+    // element offsets: sets one after the other, each set's requests in order
+    int64_t off = 0;
+    for (int g = 0; g < ng; ++g) {
+        goff[g] = off;
+        for (size_t k = 0; k < sl.reqs.size(); ++k)
+            if (sl.req_set[k] == g) {
+                sl.xoff[k] = off;
+                off += hs[g]->N * sl.reqs[k]->r.nrhs;
+                cols[g] += sl.reqs[k]->r.nrhs;
+            }
     }
-    const int prec = h->opts.storage == HODLR_FP64 ? HODLR_FP64 : HODLR_FP32;
     try {
         // X is read only after the work queued before submission on its stream
         for (Req* q : sl.reqs) HIP_CHECK(hipStreamWaitEvent(sl.s, q->ready, 0));
-        for (size_t k = 0; k < sl.reqs.size(); ++k)
-            HIP_CHECK(hipMemcpyAsync(sl.xb + (size_t)sl.col0[k] * N, sl.reqs[k]->r.X,
+        for (size_t k = 0; k < sl.reqs.size(); ++k) {
+            const int64_t N = hs[sl.req_set[k]]->N;
+            HIP_CHECK(hipMemcpyAsync(sl.xb + sl.xoff[k], sl.reqs[k]->r.X,
                                      sizeof(double) * N * sl.reqs[k]->r.nrhs,
                                      hipMemcpyDeviceToDevice, sl.s));
-        matvec(h, sl.xb, N, cols, HODLR_FP64, sl.yb, N, prec, nullptr, 0, sl.s);
-        for (size_t k = 0; k < sl.reqs.size(); ++k)
-            HIP_CHECK(hipMemcpyAsync(sl.reqs[k]->r.Y, sl.yb + (size_t)sl.col0[k] * N,
+        }
+        if (ng == 1) {
+            hodlr_t h = hs[0];
+            const int prec = h->opts.storage == HODLR_FP64 ? HODLR_FP64 : HODLR_FP32;
+            matvec(h, sl.xb, h->N, cols[0], HODLR_FP64, sl.yb, h->N, prec, nullptr, 0, sl.s);
+        } else {
+            std::vector<const void*> X(ng);
+            std::vector<void*> Y(ng);
+            std::vector<int64_t> ld(ng);
+            for (int g = 0; g < ng; ++g) {
+                X[g] = sl.xb + goff[g];
+                Y[g] = sl.yb + goff[g];
+                ld[g] = hs[g]->N;
+            }
+            matvec_batch_async(ng, hs.data(), X.data(), ld.data(), cols.data(), HODLR_FP64,
+                               Y.data(), ld.data(), sl.bt, sl.s);
+        }
+        for (size_t k = 0; k < sl.reqs.size(); ++k) {
+            const int64_t N = hs[sl.req_set[k]]->N;
+            HIP_CHECK(hipMemcpyAsync(sl.reqs[k]->r.Y, sl.yb + sl.xoff[k],
                                      sizeof(double) * N * sl.reqs[k]->r.nrhs,
                                      hipMemcpyDeviceToDevice, sl.s));
+        }
         HIP_CHECK(hipEventRecord(sl.ev, sl.s));
     } catch (const Error& e) {
         (void)hipStreamSynchronize(sl.s);
@@ -139,10 +178,11 @@ void launch_products(hodlr_server_s* S, Slot& sl) {
     }
     ++S->stats.launches;
     if (sl.reqs.size() > 1) S->stats.batched_requests += (int64_t)sl.reqs.size();
+    if (ng > 1) ++S->stats.multiset_launches;
 }
 
 void launch_solve(hodlr_server_s* S, Slot& sl) {
-    hodlr_t h = S->sets[sl.set].h;
+    hodlr_t h = S->sets[sl.sets[0]].h;
     Req* q = sl.reqs[0];
     sl.worker_done = false;
     ++S->stats.launches;
@@ -226,43 +266,81 @@ void scheduler(hodlr_server_s* S) {
                 ++qi;
                 continue;
             }
-            const int64_t N = st.h->N;
             Slot& sl = *free_slot;
             sl.reqs.clear();
-            sl.col0.clear();
-            size_t bytes;
+            sl.req_set.clear();
+            sl.sets.clear();
+            size_t bytes = 0;
             if (q->r.kind == HODLR_REQ_SOLVE) {
-                bytes = sizeof(double) * (size_t)N * q->r.nrhs * (30 + 5);
+                bytes = sizeof(double) * (size_t)st.h->N * q->r.nrhs * (30 + 5);
                 if (S->used + bytes > S->o.mem_budget_bytes && S->running > 0) {
                     ++qi;
                     continue;
                 }
+                sl.sets.push_back(q->r.set);
                 sl.reqs.push_back(q);
+                sl.req_set.push_back(0);
                 S->queue.erase(S->queue.begin() + qi);
             } else {
-                // this set's queued products, in order, up to the column cap
-                bytes = 0;
-                int cols = 0;
-                for (size_t k = qi; k < S->queue.size();) {
-                    Req* p = S->queue[k];
-                    if (p->r.set == q->r.set && p->r.kind == HODLR_REQ_MATVEC &&
-                        cols + p->r.nrhs <= S->o.max_batch_cols) {
-                        cols += p->r.nrhs;
-                        sl.reqs.push_back(p);
-                        S->queue.erase(S->queue.begin() + k);
-                    } else {
-                        ++k;
+                // this set's queued products, in order, up to the column cap;
+                // then those of other idle sets with the same factor precision
+                const size_t cap = (size_t)S->o.max_points * S->o.max_batch_cols;
+                size_t elems = 0;
+                const int prec = st.h->opts.storage;
+                const bool batchable =
+                    (prec == HODLR_FP64 || prec == HODLR_FP32) && !st.h->opts.skeleton;
+                auto take_set = [&](int set) {
+                    const int64_t N = S->sets[set].h->N;
+                    int cols = 0;
+                    std::vector<size_t> picked;
+                    for (size_t k = 0; k < S->queue.size(); ++k) {
+                        Req* p = S->queue[k];
+                        if (p->r.set == set && p->r.kind == HODLR_REQ_MATVEC &&
+                            cols + p->r.nrhs <= S->o.max_batch_cols &&
+                            elems + (size_t)N * (cols + p->r.nrhs) <= cap) {
+                            cols += p->r.nrhs;
+                            picked.push_back(k);
+                        }
+                    }
+                    if (picked.empty()) return;
+                    const int g = (int)sl.sets.size();
+                    sl.sets.push_back(set);
+                    for (size_t k : picked) {
+                        sl.reqs.push_back(S->queue[k]);
+                        sl.req_set.push_back(g);
+                    }
+                    for (size_t t = picked.size(); t-- > 0;)
+                        S->queue.erase(S->queue.begin() + picked[t]);
+                    elems += (size_t)N * cols;
+                };
+                take_set(q->r.set);
+                if (batchable) {
+                    for (size_t k = 0; k < S->queue.size() && (int)sl.sets.size() < kBatchSets;) {
+                        Req* p = S->queue[k];
+                        const Set& ps = S->sets[p->r.set];
+                        bool mine = false;
+                        for (int x : sl.sets) mine = mine || x == p->r.set;
+                        if (p->r.kind == HODLR_REQ_MATVEC && !mine && !ps.busy &&
+                            ps.h->opts.storage == prec && !ps.h->opts.skeleton &&
+                            elems + (size_t)ps.h->N * p->r.nrhs <= cap) {
+                            const size_t before = S->queue.size();
+                            take_set(p->r.set);
+                            if (S->queue.size() == before) ++k;   // nothing fitted
+                            // requests before k stay; k now names the next one
+                        } else {
+                            ++k;
+                        }
                     }
                 }
+                sl.xoff.assign(sl.reqs.size(), 0);
             }
             const auto now = clk::now();
             for (Req* p : sl.reqs) {
                 p->state = 1;
                 p->t_start = now;
             }
-            st.busy = true;
+            for (int x : sl.sets) S->sets[x].busy = true;
             sl.busy = true;
-            sl.set = q->r.set;
             sl.solve = q->r.kind == HODLR_REQ_SOLVE;
             sl.bytes = bytes;
             S->used += bytes;
@@ -309,6 +387,7 @@ hodlr_status server_create(const hodlr_server_opts& o, hodlr_server_t* out) {
             fail(HODLR_ENOMEM, "server batch buffers");
         }
         S->used += 2 * sizeof(double) * n;
+        sl->bt = batch_tables_create(kBatchSets, kBatchSegs);
         S->slots.push_back(std::move(sl));
     }
     if (S->used > o.mem_budget_bytes) fail(HODLR_ENOMEM, "budget below the batch buffers");
@@ -329,6 +408,7 @@ void server_destroy(hodlr_server_t S) {
         (void)hipStreamSynchronize(sl->s);
         (void)hipFree(sl->xb);
         (void)hipFree(sl->yb);
+        batch_tables_destroy(sl->bt);
         (void)hipEventDestroy(sl->ev);
         (void)hipStreamDestroy(sl->s);
     }

@@ -164,3 +164,27 @@ def test_batch_of_handles_equals_separate_products(P, st):
         err = _rel(_host(Ys[i]), refs[i])
         _say(f"[batch {st}] slot {i}: {err:.2e}")
         assert err <= rel
+
+
+@pytest.mark.parametrize("d,N,kern,tol,st", [(2, 4096, "log", 1e-8, "fp64"),
+                                             (3, 30000, "inv_r", 1e-10, "fp64"),
+                                             (3, 30000, "inv_r", 1e-8, "fp32")])
+def test_autotuner_keeps_the_product(P, d, N, kern, tol, st):
+    """The autotuner times every tile shape of every block class and both
+    routes and keeps the fastest; the product after tuning equals the default
+    one (the shapes change only the order of the sums)."""
+    import torch
+    storage = P.FP64 if st == "fp64" else P.FP32
+    dt = torch.float64 if st == "fp64" else torch.float32
+    rel = 1e-13 if st == "fp64" else 1e-5
+    pts = W.uniform_points(N, d, 990 + d)
+    H = P.HODLR(pts, P.make_kernel(kern), 64, tol, storage=storage)
+    X = _dev(torch, W.rhs_normal(N, 1, 991)[:, 0], dt)
+    y0 = _host(H.matvec(X, compute_prec=storage))
+    t = P.hodlr_autotune(H.h, 1, P.FP64 if st == "fp64" else P.FP32, storage)
+    _say(f"[autotune] d={d} N={N} {st}: route {t.route}, shapes {list(t.class_choice)[:6]}, "
+         f"per-class {t.class_route_ms:.4f} ms, persistent {t.persistent_ms:.4f} ms")
+    assert t.route in (0, 1) and t.class_route_ms > 0 and t.persistent_ms > 0
+    assert t.route == (1 if t.persistent_ms < t.class_route_ms else 0)
+    y1 = _host(H.matvec(X, compute_prec=storage))
+    assert _rel(y1, y0) <= rel

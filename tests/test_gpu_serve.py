@@ -69,7 +69,9 @@ def _tensor(torch, N, nrhs, seed):
 
 def test_results_same_alone_and_in_the_mix(P):
     import torch
-    srv = P.Server(max_concurrent=4, max_batch_cols=32, max_points=20000)
+    # fewer stream slots than sets: requests queue while others run, and the
+    # queued products of idle sets share launches
+    srv = P.Server(max_concurrent=2, max_batch_cols=32, max_points=20000)
     ids, Ns, precs = _sets(P, srv)
     reqs = _requests(P, Ns, 40, 7)
     X = [_tensor(torch, Ns[s], n, 100 + i) for i, (_, s, n) in enumerate(reqs)]
@@ -94,10 +96,13 @@ def test_results_same_alone_and_in_the_mix(P):
     launches = st1.launches - st0.launches
     _say(f"[serve] mix: {len(reqs)} requests in {launches} launches, "
          f"batched {st1.batched_requests - st0.batched_requests}, "
+         f"multi-set launches {st1.multiset_launches - st0.multiset_launches}, "
          f"most concurrent {st1.max_concurrent}, "
          f"p50 {np.percentile([q + r for q, r in lat], 50) / 1e3:.2f} ms")
     assert launches < len(reqs)
     assert st1.batched_requests > st0.batched_requests
+    # products of different sets (same factor precision) share launches
+    assert st1.multiset_launches > st0.multiset_launches
     assert st1.max_concurrent >= 2
     assert st1.failed == 0 and st1.completed == 2 * len(reqs)
     srv.close()

@@ -1737,12 +1737,13 @@ struct PSeg {
     int32_t stage, ndep;   // its stage; the stages it needs complete
     int32_t dep[3], dcnt[3];   // their ids and claim counts
 };
-// Launch counters: claim, unused, exit, error flag, three diagnostics, then
-// one completion count per stage.  Each stage count has a 128-byte line of
-// its own, away from the claim counter: hundreds of workgroups poll them, and
-// polls of one line queue with every other access to it.
+// Launch counters, each group on 128-byte lines of its own (hundreds of
+// workgroups poll them, and the polls of one line queue with every other
+// access to it): the claim and exit counts; the error flag and three
+// diagnostics; one completion count per stage.
 constexpr int kPersistLine = 32;   // ints per line
-constexpr int kPersistCtrBase = kPersistLine;
+constexpr int kPersistAbort = kPersistLine;
+constexpr int kPersistCtrBase = 2 * kPersistLine;
 constexpr int kPersistMaxStages = 1024;
 constexpr int kPersistCtrInts = kPersistCtrBase + kPersistLine * kPersistMaxStages;
 // right-hand sides one persistent launch takes (five stages per batch of
@@ -1778,10 +1779,10 @@ __global__ __launch_bounds__(kPersistThreads, persist_waves<S>()) void k_persist
                                                              int nseg, int64_t nclaims,
                                                              int nstages, int* ctr) {
     using C = S;
-    // tile shapes that keep the kernel at 3 waves per SIMD (the heaviest
-    // body decides every claim's occupancy): classes 1 and 2 one block per
-    // wave with batches of 4 terms, class 4 batches of one (FP64) or two terms
-    constexpr int KB4 = sizeof(C) == 8 ? 1 : 2;
+    // tile shapes (the heaviest body decides every claim's occupancy):
+    // classes 1 and 2 one block per wave with batches of 4 terms, class 4
+    // batches of two
+    constexpr int KB4 = 2;
     __shared__ int64_t s_claim;
     __shared__ C s_part[4][2][4];
     __shared__ C s_red[TG / 64][NR][64];
@@ -1858,21 +1859,22 @@ __global__ __launch_bounds__(kPersistThreads, persist_waves<S>()) void k_persist
                         const int done = __builtin_amdgcn_readfirstlane(__hip_atomic_load(
                             cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
                         if (done >= sg.dcnt[dd]) break;
-                        // the flag shares the claim counter's line: read once backed off
+                        // the error flag, once backed off
                         const int abort =
                             nap < 32 ? 0
                                      : __builtin_amdgcn_readfirstlane(__hip_atomic_load(
-                                           ctr + 3, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+                                           ctr + kPersistAbort, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT));
                         const bool late = (uint64_t)(wall_clock64() - t0) > kPersistWaitTicks;
                         if (abort || late) {
                             const int prev = __builtin_amdgcn_readfirstlane(__hip_atomic_fetch_or(
-                                ctr + 3, lane == 0 ? 1 : 0, __ATOMIC_RELAXED,
+                                ctr + kPersistAbort, lane == 0 ? 1 : 0, __ATOMIC_RELAXED,
                                 __HIP_MEMORY_SCOPE_AGENT));
                             if (prev == 0) {
                                 // the first timeout: which claim waited for which stage
-                                ctr[4] = (int)g;
-                                ctr[5] = sg.dep[dd];
-                                ctr[6] = done;
+                                ctr[kPersistAbort + 1] = (int)g;
+                                ctr[kPersistAbort + 2] = sg.dep[dd];
+                                ctr[kPersistAbort + 3] = done;
                             }
                             dd = sg.ndep;
                             break;
@@ -2705,8 +2707,8 @@ struct PSlotHost {
 //   A_b   column batch b: the blocks of every class and the segmented
 //         projections (needs P, and G_{b-1}, which last read the buffers)
 //   S_b   sums of the segmented projections (needs A_b)
-//   N_b   the near field (needs P and G_{b-1}; queued after S_b, so that it
-//         runs while S_b waits for A_b)
+//   N_b   the near field (needs P and G_{b-1}; queued between the largest
+//         blocks of A_b and the rest, so that it runs beside them)
 //   E_b   expansions of the segmented blocks (needs S_b)
 //   G_b   the gather (needs A_b, N_b, E_b)
 // Every stage is queued after the stages it needs.
@@ -2766,19 +2768,19 @@ void persist_segments(const std::vector<PSlotHost>& sl, int NR, std::vector<PSeg
             add(A, t, PK_PROJ, c0, 0, h->p_n_proj, 1);
             if (NR == 1) {
                 add(A, t, PK_S4, c0, o[4], o[5] - o[4], 1);
+                add(Nr, t, PK_NEAR, c0, 0, h->n_near_items, 1);
                 add(A, t, PK_S3, c0, o[3], o[4] - o[3], 4);
                 add(A, t, PK_S2, c0, o[2], o[3] - o[2], 4);
                 add(A, t, PK_G16, c0, o[1], o[2] - o[1], 4);
                 add(A, t, PK_G8, c0, o[0], o[1] - o[0], 32);
             } else {
                 add(A, t, PK_FUSED, c0, o[0], o[6] - o[0], 4);
+                add(Nr, t, PK_NEAR, c0, 0, h->n_near_items, 1);
             }
         }
         for (int t = 0; t < (int)sl.size(); ++t)
             if (sl[t].nrhs > c0)
                 add(Sx, t, PK_PSUM, c0, 0, (sl[t].h->p_n_psum * 2 * NR + 255) / 256, 1);
-        for (int t = 0; t < (int)sl.size(); ++t)
-            if (sl[t].nrhs > c0) add(Nr, t, PK_NEAR, c0, 0, sl[t].h->n_near_items, 1);
         for (int t = 0; t < (int)sl.size(); ++t)
             if (sl[t].nrhs > c0) add(E, t, PK_EXP, c0, 0, sl[t].h->p_n_exp, 1);
         for (int t = 0; t < (int)sl.size(); ++t)
@@ -2865,20 +2867,25 @@ unsigned persist_grid(int64_t nclaims) {
 }
 
 // the error flag of a finished persistent launch (a wait that timed out)
-void persist_check(const int* ctr, hipStream_t s) {
-    int v[8] = {0};
-    HIP_CHECK(hipMemcpyAsync(v, ctr, sizeof(v), hipMemcpyDeviceToHost, s));
+void persist_check(int* ctr, hipStream_t s) {
+    int v[4] = {0};
+    HIP_CHECK(hipMemcpyAsync(v, ctr + kPersistAbort, sizeof(v), hipMemcpyDeviceToHost, s));
     HIP_CHECK(hipStreamSynchronize(s));
-    if (v[3])
+    if (v[0]) {
+        // the flag is cleared for the next launch (every other count was
+        // reset by the launch's last workgroup)
+        HIP_CHECK(hipMemsetAsync(ctr + kPersistAbort, 0, sizeof(v), s));
+        HIP_CHECK(hipStreamSynchronize(s));
         fail(HODLR_EDEVICE, "persistent product: a stage wait timed out (claim " +
-                                std::to_string(v[4]) + " waited for stage " +
-                                std::to_string(v[5]) + ", which had " + std::to_string(v[6]) +
+                                std::to_string(v[1]) + " waited for stage " +
+                                std::to_string(v[2]) + ", which had " + std::to_string(v[3]) +
                                 " completed claims)");
+    }
 }
 
 // Launches the persistent product of the slots on s.  dslots / dsegs: device
 // tables of at least slots.size() / segs.size() entries, written here when
-// `upload` is set; ctr: four zeroed ints (left zeroed by the launch).
+// `upload` is set; ctr: kPersistCtrInts zeroed ints (left zeroed by the launch).
 template <typename XT, typename S, int NR>
 void persist_launch(const std::vector<PSlotHost>& slots, const std::vector<PSeg>& segs,
                     int64_t nclaims, int nstages, PSlot* dslots, PSeg* dsegs, bool upload,

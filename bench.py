@@ -161,6 +161,50 @@ def multi_rhs(P, torch, W, steps, warmup, n_override=0):
     }
 
 
+def multi_rhs_fp32(P, torch, W, steps, n_override=0):
+    """The same 32-RHS product with FP32 factors (precision-aware truncation)
+    and FP32 arithmetic on the lane-parallel block kernels, eight columns per
+    pass over the factors: error against the direct sum on the same sampled
+    rows, and the factor bytes streamed per product."""
+    import oracle
+    w = W.WORKLOADS["uniform4d_invr2_n524288"]
+    if n_override:
+        w = W.scaled(w, n_override)
+    pts, q = w.points(), w.rhs()
+    N, nrhs = w.N, q.shape[1]
+    kern = P.make_kernel(w.kernel, h=w.h, diag=w.diag)
+    t0 = time.perf_counter()
+    H = P.HODLR(pts, kern, w.leaf, w.tol, domain=w.domain, storage=P.FP32)
+    torch.cuda.synchronize()
+    build = time.perf_counter() - t0
+    info = H.info()
+    print(f"[bench] multi-RHS FP32 build {build:.1f} s kappa={info.kappa}", file=sys.stderr,
+          flush=True)
+    X = torch.tensor(np.ascontiguousarray(q.T), dtype=torch.float32, device="cuda").t()
+    Y = torch.empty((nrhs, N), dtype=torch.float32, device="cuda").t()
+    wall, per, cls, lat = time_matvecs(P, torch, H, X, Y, P.FP32, 1, steps)
+    ms = wall / steps * 1e3
+    y = Y.t().contiguous().cpu().numpy().T.astype(np.float64)
+    rows = np.sort(W.rng(203).choice(N, size=min(N, 512), replace=False))
+    bd = oracle.direct(pts, oracle.kernel(w.kernel, diag=w.diag), q, rows=rows)
+    err = float(np.linalg.norm(y[rows] - bd) / np.linalg.norm(bd))
+    fe = sum(info.factor_elems[l] for l in range(1, info.kappa + 1))
+    passes = (nrhs + 7) // 8
+    streamed = 4 * fe * passes
+    print(f"[bench] multi-RHS FP32 {ms:.2f} ms per product, rel err {err:.2e}", file=sys.stderr,
+          flush=True)
+    del H
+    return {
+        "dtype": "f32 factors, f32 arithmetic", "value": N * nrhs / (ms * 1e-3),
+        "unit": "N*nrhs/s", "ms_per_step": ms,
+        "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+        "rel_err": err, "rel_err_ref": "direct sum on 512 sampled rows (seed 203)",
+        "build_s": round(build, 2), "factor_bytes": int(4 * fe),
+        "passes_over_factors": passes, "streamed_gbs": streamed / (ms * 1e-3) / 1e9,
+        "stage_ms": [round(float(v), 4) for v in per.mean(axis=0)],
+    }
+
+
 def small_bench(P, torch, W, reps=200):
     """The small workload (4096 points uniform in [-1,1]^2, log r, leaf 64,
     ACA 1e-8, FP64, one U[-1,1] right-hand side): the autotuner's choice
@@ -639,6 +683,8 @@ def main():
     ap.add_argument("--no-multi-rhs", action="store_true",
                     help="skip the 32-RHS BF16 matrix-core workload")
     ap.add_argument("--multi-rhs-n", type=int, default=0, help="override its N")
+    ap.add_argument("--no-multi-rhs-fp32", action="store_true",
+                    help="skip the multi-RHS product with FP32 factors")
     ap.add_argument("--no-solve", action="store_true", help="skip the GMRES-IR solve")
     ap.add_argument("--no-small", action="store_true",
                     help="skip the small 2D workload (eager and graph-replayed latency)")
@@ -756,6 +802,8 @@ def main():
     mrhs = None
     if not args.no_multi_rhs:
         mrhs = multi_rhs(P, torch, W, max(3, args.steps // 4), 1, args.multi_rhs_n)
+        if not args.no_multi_rhs_fp32:
+            mrhs["fp32_factors"] = multi_rhs_fp32(P, torch, W, 3, args.multi_rhs_n)
 
     small = None
     if not args.no_small:

@@ -2567,8 +2567,8 @@ void run_matvec(hodlr_t h, const XT* X, int64_t ldx, int nrhs, XT* Y, int64_t ld
         // the near field on the second stream, beside the low-rank stages
         fork();
         const unsigned gnear = near_grid(h, std::min(NR, nrhs - c0), sizeof(S));
-        if constexpr (NR == 1) {
-            // one right-hand side: the kernel function fixed at compile time
+        {
+            // the kernel function fixed at compile time
             switch (h->kp.kind) {
 #define HODLR_NEAR(K)                                                                           \
     case K:                                                                                     \
@@ -2587,10 +2587,6 @@ void run_matvec(hodlr_t h, const XT* X, int64_t ldx, int nrhs, XT* Y, int64_t ld
                 HODLR_NEAR(HODLR_K_INV_SQRT1P)
 #undef HODLR_NEAR
             }
-        } else {
-            k_gather_near<XT, C, NR, -1, kNearOnly><<<gnear, TG, 0, aux>>>(
-                h->near_items, h->n_near_items, h->leaf_seg, h->near_rng, h->kappa, h->pts, N,
-                h->d, h->kp, x, contrib, CT, h->perm, nrhs, c0, Y, ldy, nullptr, yn);
         }
         HIP_CHECK(hipGetLastError());
         if constexpr (NR == 1 && !std::is_same<S, bf16>::value) {

@@ -74,6 +74,9 @@ FP32_CASES = [
     (3, 12000, 64, "inv_r", 1e-10, 1, "uniform", True, 6),
     (2, 6000, 64, "log", 1e-8, 0, "uniform", True, 1),
     (4, 9000, 128, "inv_r2", 1e-8, 1, "uniform", True, 3),
+    # several passes of eight columns, the last one ragged
+    (4, 9000, 128, "inv_r2", 1e-8, 1, "uniform", True, 20),
+    (3, 12000, 64, "inv_r", 1e-10, 1, "uniform", False, 11),
     (3, 6000, 48, "gauss", 1e-6, 0, "mixture", True, 1),
 ]
 

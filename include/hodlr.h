@@ -103,8 +103,8 @@ typedef struct {
      * product.  FP64 storage and FP64 arithmetic only: the pivots on the
      * diagonal of L span the tolerance's range, so the solves cancel unless
      * K(sigma, J) x is accurate to about tol.  One right-hand side per pass;
-     * only the ranks can be exported, nothing imported.  0: store U and V
-     * (default). */
+     * only the ranks can be exported, nothing imported; a block rank above
+     * 1024 fails the build with EUNSUPPORTED.  0: store U and V (default). */
     int skeleton;
 } hodlr_opts;
 

@@ -1362,23 +1362,41 @@ __global__ __launch_bounds__(TG) void k_gather_near(
 // the diagonal, unit upper above), and
 //   K~(A,B) x_B = K(A, tau) U^-1 L^-1 K(sigma, B) x_B,
 //   K~(A,B)^T x_A = K(B, sigma) L^-T U^-T K(tau, A) x_A   (symmetric kernel).
-// One workgroup per block: the four kernel-matrix products are evaluated on
-// the fly (g threads per output, partial sums reduced in the group), the two
-// triangular pairs are solved by waves 0 and 1 in LDS.
-constexpr int kSkelMaxR = 1024;
+// Three launches over all stored blocks: the skeleton projections
+// w = K(sigma, B) x_B and w' = K(tau, A) x_A in source segments of up to
+// kSkelSeg points (many workgroups per large block, partial sums), one
+// workgroup per block summing the partials and solving the two triangular
+// pairs in panels of 32 (panel updates by the whole workgroup, the 32 x 32
+// diagonal blocks from LDS by one wave each), then the expansions
+// K(A, tau) z and K(B, sigma) s in 256-row chunks.  The kernel matrices are
+// evaluated on the fly in every launch.
+constexpr int kSkelMaxR = 1024;   // largest rank of a block in the skeleton form
 
 // out[k] = sum_j K(p_k, q_j) w_j for k < nt, targets p_k = pts[tidx(k)],
-// sources q_j = pts[sidx(j)] with weights wfn(j).  The sources are staged
-// through LDS 256 at a time (coordinates in FP64, weights in C) by the whole
-// workgroup; g threads share a target and split each tile, their partial sums
-// reduced in the group.  Every thread of the workgroup must call it.
+// sources q_j = pts[sidx(j)] with weights wfn(j).  Targets and sources are
+// points of two different boxes (a stored block is never a box with itself),
+// so no pair is a diagonal entry.  The sources are staged through LDS 256 at
+// a time by the whole workgroup, for d <= 3 as one 32-byte record (three
+// coordinates, zero beyond d, and the weight: two LDS reads a pair), else
+// coordinate by coordinate; g threads share a target and split each tile,
+// their partial sums reduced in the group.  Every thread of the workgroup
+// must call it.
 constexpr int kSkelTile = 256;
 
-template <typename C, int KIND, typename TI, typename SI, typename WF, typename OF>
+template <bool P3>
+struct SkelLds {                        // d <= 3: x, y, z, weight per source
+    alignas(16) double rec[kSkelTile][4];
+};
+template <>
+struct SkelLds<false> {                 // d > 3: coordinates and weights
+    double q[kMaxD][kSkelTile];
+    double w[kSkelTile];
+};
+
+template <typename C, int KIND, bool P3, typename TI, typename SI, typename WF, typename OF>
 __device__ __forceinline__ void skel_products(const double* __restrict__ pts, int64_t N, int d,
                                               const KParams& kp, int nt, TI tidx, int ns,
-                                              SI sidx, WF wfn, OF ofn, double (*s_q)[kSkelTile],
-                                              C* s_w, int64_t* s_i) {
+                                              SI sidx, WF wfn, OF ofn, SkelLds<P3>& L) {
     int g = 1;
     while (g < 64 && g * 2 * nt <= (int)blockDim.x) g *= 2;
     const int per = blockDim.x / g;
@@ -1387,9 +1405,9 @@ __device__ __forceinline__ void skel_products(const double* __restrict__ pts, in
         const int k = k0 + (int)threadIdx.x / g;
         const bool act = k < nt;
         double xt[kMaxD];
-        int64_t tp = -1;
+        for (int a = 0; a < kMaxD; ++a) xt[a] = 0.0;
         if (act) {
-            tp = tidx(k);
+            const int64_t tp = tidx(k);
             for (int a = 0; a < d; ++a) xt[a] = pts[a * N + tp];
         }
         C acc = 0;
@@ -1398,26 +1416,34 @@ __device__ __forceinline__ void skel_products(const double* __restrict__ pts, in
             __syncthreads();   // the previous tile is no longer read
             for (int q = threadIdx.x; q < tn; q += blockDim.x) {
                 const int64_t sp = sidx(j0 + q);
-                s_i[q] = sp;
-                for (int a = 0; a < d; ++a) s_q[a][q] = pts[a * N + sp];
-                s_w[q] = wfn(j0 + q);
+                if constexpr (P3) {
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) L.rec[q][a] = a < d ? pts[a * N + sp] : 0.0;
+                    L.rec[q][3] = (double)wfn(j0 + q);
+                } else {
+                    for (int a = 0; a < d; ++a) L.q[a][q] = pts[a * N + sp];
+                    L.w[q] = (double)wfn(j0 + q);
+                }
             }
             __syncthreads();
             if (act) {
 #pragma unroll 4
                 for (int q = sub; q < tn; q += g) {
-                    C kij;
-                    if (s_i[q] == tp) {
-                        kij = (C)kp.diag;
+                    C r2 = 0, wq;
+                    if constexpr (P3) {
+                        const double4 R = *reinterpret_cast<const double4*>(L.rec[q]);
+                        const C dx = (C)(xt[0] - R.x), dy = (C)(xt[1] - R.y),
+                                dz = (C)(xt[2] - R.z);
+                        r2 = dx * dx + dy * dy + dz * dz;
+                        wq = (C)R.w;
                     } else {
-                        C r2 = 0;
                         for (int a = 0; a < d; ++a) {
-                            const C dx = (C)(xt[a] - s_q[a][q]);
+                            const C dx = (C)(xt[a] - L.q[a][q]);
                             r2 += dx * dx;
                         }
-                        kij = kfun_k<KIND>(kp, r2);
+                        wq = (C)L.w[q];
                     }
-                    acc += kij * s_w[q];
+                    acc += kfun_k<KIND>(kp, r2) * wq;
                 }
             }
         }
@@ -1426,77 +1452,209 @@ __device__ __forceinline__ void skel_products(const double* __restrict__ pts, in
     }
 }
 
-template <typename S, typename C, int KIND>
-__global__ __launch_bounds__(256) void k_skel(const BlockDesc* __restrict__ blocks, int sym,
-                                              const double* __restrict__ pts, int64_t N, int d,
-                                              KParams kp, const C* __restrict__ x,
-                                              C* __restrict__ contrib) {
-    __shared__ C s_f[kSkelMaxR], s_t[kSkelMaxR];   // forward: w, then z; transposed: w', then s
-    __shared__ double s_q[kMaxD][kSkelTile];         // staged source coordinates
-    __shared__ C s_w[kSkelTile];
-    __shared__ int64_t s_i[kSkelTile];
-    const BlockDesc b = blocks[blockIdx.x];
-    const int r = b.rank, m = b.m, n = b.n;
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const gptr_t<S> M = as_global<S>(b.U);
+constexpr int kSkelSeg = 4096;      // sources per projection item
+constexpr int kSkelRows = 256;      // rows per expansion item
+
+template <typename S, typename C, int KIND, bool P3>
+__global__ __launch_bounds__(256) void k_skel_proj(const BlockDesc* __restrict__ blocks,
+                                                   const SkelProj* __restrict__ items,
+                                                   const double* __restrict__ pts, int64_t N,
+                                                   int d, KParams kp, const C* __restrict__ x,
+                                                   C* __restrict__ part) {
+    __shared__ SkelLds<P3> L;
+    const SkelProj it = items[blockIdx.x];
+    const BlockDesc b = blocks[it.blk];
     const int32_t* __restrict__ sig = reinterpret_cast<const int32_t*>(b.V);
-    const int32_t* __restrict__ tau = sig + r;
-    const C* __restrict__ xA = x + b.a0;
-    const C* __restrict__ xB = x + b.b0;
-    // w = K(sigma, B) x_B and w' = K(tau, A) x_A
-    skel_products<C, KIND>(
-        pts, N, d, kp, r, [&](int k) { return (int64_t)b.a0 + sig[k]; }, n,
-        [&](int j) { return (int64_t)b.b0 + j; }, [&](int j) { return xB[j]; },
-        [&](int k, C v) { s_f[k] = v; }, s_q, s_w, s_i);
-    if (sym)
-        skel_products<C, KIND>(
-            pts, N, d, kp, r, [&](int k) { return (int64_t)b.b0 + tau[k]; }, m,
-            [&](int i) { return (int64_t)b.a0 + i; }, [&](int i) { return xA[i]; },
-            [&](int k, C v) { s_t[k] = v; }, s_q, s_w, s_i);
+    const int32_t* __restrict__ tau = sig + b.rank;
+    C* out = part + it.dst;
+    if (it.side == 0)   // w += K(sigma, B[lo, lo + cnt)) x_B
+        skel_products<C, KIND, P3>(
+            pts, N, d, kp, b.rank, [&](int k) { return (int64_t)b.a0 + sig[k]; }, it.cnt,
+            [&](int j) { return (int64_t)b.b0 + it.lo + j; },
+            [&](int j) { return x[b.b0 + it.lo + j]; }, [&](int k, C v) { out[k] = v; }, L);
+    else                // w' += K(tau, A[lo, lo + cnt)) x_A
+        skel_products<C, KIND, P3>(
+            pts, N, d, kp, b.rank, [&](int k) { return (int64_t)b.b0 + tau[k]; }, it.cnt,
+            [&](int i) { return (int64_t)b.a0 + it.lo + i; },
+            [&](int i) { return x[b.a0 + it.lo + i]; }, [&](int k, C v) { out[k] = v; }, L);
+}
+
+constexpr int kSkelPanel = 32;   // rows of a triangular panel (lanes of one wave)
+constexpr int kSkelSolveThreads = 128;
+
+// s[i] -= sum_{k0 <= k < k1} M[i][k] s[k] for i0 <= i < i1 (rows of the
+// row-major r x r array M): a wave per row, lanes over k
+template <typename S, typename C>
+__device__ __forceinline__ void skel_row_update(gptr_t<S> M, int r, C* s, int i0, int i1,
+                                                int k0, int k1) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    for (int i = i0 + wv; i < i1; i += nw) {
+        C a = 0;
+        for (int k = k0 + lane; k < k1; k += 64) a += ldf<C>(M, (int64_t)i * r + k) * s[k];
+        a = wsum(a);
+        if (lane == 0) s[i] -= a;
+    }
     __syncthreads();
-    if (wv == 0) {
-        // L z1 = w (rows of L), then U z = z1 (rows of the unit upper part)
-        for (int i = 0; i < r; ++i) {
-            C a = 0;
-            for (int k = lane; k < i; k += 64) a += ldf<C>(M, (int64_t)i * r + k) * s_f[k];
-            a = wsum(a);
-            if (lane == 0) s_f[i] = (s_f[i] - a) / ldf<C>(M, (int64_t)i * r + i);
-            wave_lds_fence();
-        }
-        for (int i = r - 1; i >= 0; --i) {
-            C a = 0;
-            for (int k = i + 1 + lane; k < r; k += 64) a += ldf<C>(M, (int64_t)i * r + k) * s_f[k];
-            a = wsum(a);
-            if (lane == 0) s_f[i] -= a;
-            wave_lds_fence();
-        }
-    } else if (wv == 1 && sym) {
-        // U^T s1 = w' (unit lower: row k of U updates the later entries), then
-        // L^T s = s1 (upper: row k of L updates the earlier entries)
-        for (int k = 0; k < r; ++k) {
-            const C sk = s_t[k];
-            for (int i = k + 1 + lane; i < r; i += 64) s_t[i] -= ldf<C>(M, (int64_t)k * r + i) * sk;
-            wave_lds_fence();
-        }
-        for (int k = r - 1; k >= 0; --k) {
-            const C sk = s_t[k] / ldf<C>(M, (int64_t)k * r + k);
-            wave_lds_fence();
-            if (lane == 0) s_t[k] = sk;
-            for (int i = lane; i < k; i += 64) s_t[i] -= ldf<C>(M, (int64_t)k * r + i) * sk;
-            wave_lds_fence();
+}
+
+// s[i0 + t] -= sum_{k0 <= k < k1} M[k][i0 + t] s[k] for t < pb (columns of
+// M): lanes over t, the waves split k, partials met in LDS
+template <typename S, typename C>
+__device__ __forceinline__ void skel_col_update(gptr_t<S> M, int r, C* s, int i0, int pb,
+                                                int k0, int k1, C (*red)[64]) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    C a = 0;
+    if (lane < pb)
+        for (int k = k0 + wv; k < k1; k += nw) a += ldf<C>(M, (int64_t)k * r + i0 + lane) * s[k];
+    red[wv][lane] = a;
+    __syncthreads();
+    if (wv == 0 && lane < pb) {
+        C t = 0;
+        for (int w = 0; w < nw; ++w) t += red[w][lane];
+        s[i0 + lane] -= t;
+    }
+    __syncthreads();
+}
+
+// the diagonal block M[p .. p+pb)^2 into LDS (D[i][k], rows padded) and the
+// reciprocals of its diagonal
+template <typename S, typename C>
+__device__ __forceinline__ void skel_stage_diag(gptr_t<S> M, int r, int p, int pb, C (*D)[kSkelPanel + 1],
+                                                C* rd) {
+    for (int e = threadIdx.x; e < pb * pb; e += blockDim.x) {
+        const int i = e / pb, k = e - i * pb;
+        D[i][k] = ldf<C>(M, (int64_t)(p + i) * r + p + k);
+    }
+    __syncthreads();
+    if (threadIdx.x < pb) rd[threadIdx.x] = (C)1 / D[threadIdx.x][threadIdx.x];
+    __syncthreads();
+}
+
+// lane k's value, as a scalar
+__device__ __forceinline__ double lane_value(double v, int k) {
+    const long long b = __builtin_bit_cast(long long, v);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), k);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), k);
+    return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned)lo);
+}
+__device__ __forceinline__ float lane_value(float v, int k) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), k));
+}
+
+// Solve of one diagonal block by the calling wave, lane t holding entry
+// p + t of s.  TR: the block is used transposed; LOWER: forward elimination
+// (else backward); UNIT: unit diagonal (else the reciprocals rd).
+template <typename C, bool TR, bool LOWER, bool UNIT>
+__device__ __forceinline__ void skel_diag_solve(C* s, int p, int pb, const C (*D)[kSkelPanel + 1],
+                                                const C* rd) {
+    const int lane = threadIdx.x & 63;
+    C w = lane < pb ? s[p + lane] : (C)0;
+    for (int t = 0; t < pb; ++t) {
+        const int k = LOWER ? t : pb - 1 - t;
+        C zk = lane_value(w, k);
+        if (!UNIT) zk *= rd[k];
+        const bool later = LOWER ? lane > k : lane < k;
+        if (lane == k)
+            w = zk;
+        else if (later && lane < pb)
+            w -= (TR ? D[k][lane] : D[lane][k]) * zk;
+    }
+    if (lane < pb) s[p + lane] = w;
+}
+
+// one workgroup per stored block: the skeleton projections summed over their
+// segments, then z = U^-1 L^-1 w and (symmetric kernel) s = L^-T U^-T w', in
+// panels of kSkelPanel: the panel updates by the whole workgroup (two
+// waves, so that many blocks are solved on a CU at once), then the diagonal
+// block (staged once for both systems, which use its two triangles) solved
+// by wave 0 for z and wave 1 for s at the same time; written to the block's
+// terms of tb (and sb).  LDS: z and s of maxr values each (dynamic).
+template <typename S, typename C>
+__global__ __launch_bounds__(kSkelSolveThreads) void k_skel_solve(const BlockDesc* __restrict__ blocks,
+                                                    const SkelSolve* __restrict__ solves, int sym,
+                                                    const C* __restrict__ part,
+                                                    C* __restrict__ tb, C* __restrict__ sb) {
+    extern __shared__ double dyn_lds[];
+    __shared__ C D[kSkelPanel][kSkelPanel + 1];
+    __shared__ C rd[kSkelPanel];
+    __shared__ C red[kSkelSolveThreads / 64][64];
+    const BlockDesc b = blocks[blockIdx.x];
+    const int r = b.rank;
+    if (r <= 0) return;
+    C* s_f = reinterpret_cast<C*>(dyn_lds);
+    C* s_t = s_f + r;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const SkelSolve q = solves[blockIdx.x];
+    const gptr_t<S> M = as_global<S>(b.U);
+    for (int k = threadIdx.x; k < r; k += blockDim.x) {
+        C a = 0, a2 = 0;
+        for (int g = 0; g < q.nsf; ++g) a += part[q.pf + (int64_t)g * r + k];
+        s_f[k] = a;
+        if (sym) {
+            for (int g = 0; g < q.nsb; ++g) a2 += part[q.pb + (int64_t)g * r + k];
+            s_t[k] = a2;
         }
     }
     __syncthreads();
-    // c_A = K(A, tau) z and c_B = K(B, sigma) s
-    skel_products<C, KIND>(
-        pts, N, d, kp, m, [&](int i) { return (int64_t)b.a0 + i; }, r,
-        [&](int k) { return (int64_t)b.b0 + tau[k]; }, [&](int k) { return s_f[k]; },
-        [&](int i, C v) { contrib[b.cfwd + i] = v; }, s_q, s_w, s_i);
-    if (sym)
-        skel_products<C, KIND>(
-            pts, N, d, kp, n, [&](int j) { return (int64_t)b.b0 + j; }, r,
-            [&](int k) { return (int64_t)b.a0 + sig[k]; }, [&](int k) { return s_t[k]; },
-            [&](int j, C v) { contrib[b.cbwd + j] = v; }, s_q, s_w, s_i);
+    // forward: L z1 = w and U^T s1 = w'
+    int staged = -1;
+    for (int p = 0; p < r; p += kSkelPanel) {
+        const int pb = min(kSkelPanel, r - p);
+        if (p) {
+            skel_row_update<S, C>(M, r, s_f, p, p + pb, 0, p);
+            if (sym) skel_col_update<S, C>(M, r, s_t, p, pb, 0, p, red);
+        }
+        skel_stage_diag<S, C>(M, r, p, pb, D, rd);
+        staged = p;
+        if (wv == 0) skel_diag_solve<C, false, true, false>(s_f, p, pb, D, rd);
+        if (wv == 1 && sym) skel_diag_solve<C, true, true, true>(s_t, p, pb, D, rd);
+        __syncthreads();
+    }
+    // backward: U z = z1 and L^T s = s1
+    for (int p = ((r - 1) / kSkelPanel) * kSkelPanel; p >= 0; p -= kSkelPanel) {
+        const int pb = min(kSkelPanel, r - p);
+        if (p + pb < r) {
+            skel_row_update<S, C>(M, r, s_f, p, p + pb, p + pb, r);
+            if (sym) skel_col_update<S, C>(M, r, s_t, p, pb, p + pb, r, red);
+        }
+        if (p != staged) {
+            skel_stage_diag<S, C>(M, r, p, pb, D, rd);
+            staged = p;
+        }
+        if (wv == 0) skel_diag_solve<C, false, false, true>(s_f, p, pb, D, rd);
+        if (wv == 1 && sym) skel_diag_solve<C, true, false, false>(s_t, p, pb, D, rd);
+        __syncthreads();
+    }
+    for (int k = threadIdx.x; k < r; k += blockDim.x) {
+        tb[b.toff + k] = s_f[k];
+        if (sym) sb[b.toff + k] = s_t[k];
+    }
+}
+
+// c_A = K(A, tau) z (side 0) or c_B = K(B, sigma) s (side 1) on rows
+// [lo, lo + cnt) of the block's target box
+template <typename S, typename C, int KIND, bool P3>
+__global__ __launch_bounds__(256) void k_skel_exp(const BlockDesc* __restrict__ blocks,
+                                                  const WorkItem* __restrict__ items,
+                                                  const double* __restrict__ pts, int64_t N,
+                                                  int d, KParams kp, const C* __restrict__ tb,
+                                                  const C* __restrict__ sb,
+                                                  C* __restrict__ contrib) {
+    __shared__ SkelLds<P3> L;
+    const WorkItem it = items[blockIdx.x];
+    const BlockDesc b = blocks[it.id];
+    const int32_t* __restrict__ sig = reinterpret_cast<const int32_t*>(b.V);
+    const int32_t* __restrict__ tau = sig + b.rank;
+    if (it.level == 0)
+        skel_products<C, KIND, P3>(
+            pts, N, d, kp, it.cnt, [&](int i) { return (int64_t)b.a0 + it.lo + i; }, b.rank,
+            [&](int k) { return (int64_t)b.b0 + tau[k]; }, [&](int k) { return tb[b.toff + k]; },
+            [&](int i, C v) { contrib[b.cfwd + it.lo + i] = v; }, L);
+    else
+        skel_products<C, KIND, P3>(
+            pts, N, d, kp, it.cnt, [&](int j) { return (int64_t)b.b0 + it.lo + j; }, b.rank,
+            [&](int k) { return (int64_t)b.a0 + sig[k]; }, [&](int k) { return sb[b.toff + k]; },
+            [&](int j, C v) { contrib[b.cbwd + it.lo + j] = v; }, L);
 }
 
 // Near field on matrix cores (BF16 factors, several right-hand sides):
@@ -2247,6 +2405,48 @@ void plan_apply(hodlr_t h) {
     upload(rng.data(), sizeof(int2) * rng.size(), (void**)&h->near_rng);
     plan_persistent(h, h->p_seg_side);
     upload(seg.data(), sizeof(SegRef) * seg.size(), (void**)&h->leaf_seg);
+    // skeleton form: projection segments, per-block partial offsets, 256-row
+    // expansion chunks (every block, rank 0 included: its rows get zeros)
+    if (h->opts.skeleton) {
+        std::vector<SkelProj> sp;
+        std::vector<SkelSolve> ss(h->nblocks);
+        std::vector<WorkItem> se;
+        int64_t pt = 0;
+        const bool sym = h->opts.symmetric != 0;
+        for (int64_t b = 0; b < h->nblocks; ++b) {
+            const BlockDesc& bd = h->hblocks[b];
+            SkelSolve q{};
+            if (bd.rank > 0) {
+                q.pf = pt;
+                for (int32_t lo = 0; lo < bd.n; lo += kSkelSeg, pt += bd.rank, ++q.nsf)
+                    sp.push_back(SkelProj{(int32_t)b, 0, lo, std::min(kSkelSeg, bd.n - lo), pt});
+                if (sym) {
+                    q.pb = pt;
+                    for (int32_t lo = 0; lo < bd.m; lo += kSkelSeg, pt += bd.rank, ++q.nsb)
+                        sp.push_back(
+                            SkelProj{(int32_t)b, 1, lo, std::min(kSkelSeg, bd.m - lo), pt});
+                }
+            }
+            ss[b] = q;
+            for (int32_t i = 0; i < bd.m; i += kSkelRows)
+                se.push_back(WorkItem{(int32_t)b, i, std::min(kSkelRows, bd.m - i), 0});
+            if (sym)
+                for (int32_t j = 0; j < bd.n; j += kSkelRows)
+                    se.push_back(WorkItem{(int32_t)b, j, std::min(kSkelRows, bd.n - j), 1});
+        }
+        upload(sp.data(), sizeof(SkelProj) * sp.size(), (void**)&h->skel_proj);
+        upload(ss.data(), sizeof(SkelSolve) * ss.size(), (void**)&h->skel_solve);
+        upload(se.data(), sizeof(WorkItem) * se.size(), (void**)&h->skel_exp);
+        h->n_skel_proj = (int64_t)sp.size();
+        h->n_skel_exp = (int64_t)se.size();
+        h->skel_part_total = pt;
+        h->skel_max_rank = 0;
+        for (int64_t b = 0; b < h->nblocks; ++b)
+            h->skel_max_rank = std::max<int64_t>(h->skel_max_rank, h->hblocks[b].rank);
+        if (h->skel_max_rank > kSkelMaxR)
+            fail(HODLR_EUNSUPPORTED, "skeleton form: a rank above " + std::to_string(kSkelMaxR) +
+                                         " (the solves keep both vectors in LDS)");
+    }
     h->nleaf = nleaf;
     // matrix-core plan for BF16 factors (several right-hand sides)
     if (h->opts.storage == HODLR_BF16) {
@@ -2594,11 +2794,24 @@ void run_matvec(hodlr_t h, const XT* X, int64_t ldx, int nrhs, XT* Y, int64_t ld
                 // skeleton form: every stored block, the kernel evaluated on the fly
                 const C* xc = x + (int64_t)c0 * N;
                 if (h->nblocks) {
+                    C* skp = yn + (int64_t)N * NR;   // partials of the skeleton projections
                     switch (h->kp.kind) {
+#define HODLR_SKEL_P(K, P3)                                                                     \
+    if (h->n_skel_proj)                                                                         \
+        k_skel_proj<S, C, K, P3><<<(unsigned)h->n_skel_proj, 256, 0, s>>>(                      \
+            h->blocks, h->skel_proj, h->pts, N, h->d, h->kp, xc, skp);                          \
+    k_skel_solve<S, C><<<(unsigned)h->nblocks, kSkelSolveThreads,                               \
+                         2 * sizeof(C) * h->skel_max_rank, s>>>(h->blocks, h->skel_solve, sym,  \
+                                                                 skp, tb, sb);                  \
+    k_skel_exp<S, C, K, P3><<<(unsigned)h->n_skel_exp, 256, 0, s>>>(                            \
+        h->blocks, h->skel_exp, h->pts, N, h->d, h->kp, tb, sb, contrib);
 #define HODLR_SKEL(K)                                                                           \
     case K:                                                                                     \
-        k_skel<S, C, K><<<(unsigned)h->nblocks, 256, 0, s>>>(h->blocks, sym, h->pts, N, h->d,   \
-                                                             h->kp, xc, contrib);              \
+        if (h->d <= 3) {                                                                        \
+            HODLR_SKEL_P(K, true)                                                               \
+        } else {                                                                                \
+            HODLR_SKEL_P(K, false)                                                              \
+        }                                                                                       \
         break;
                         HODLR_SKEL(HODLR_K_LOG)
                         HODLR_SKEL(HODLR_K_INV_R)
@@ -2610,6 +2823,7 @@ void run_matvec(hodlr_t h, const XT* X, int64_t ldx, int nrhs, XT* Y, int64_t ld
                         default:
                         HODLR_SKEL(HODLR_K_INV_SQRT1P)
 #undef HODLR_SKEL
+#undef HODLR_SKEL_P
                     }
                     HIP_CHECK(hipGetLastError());
                 }
@@ -2915,10 +3129,11 @@ size_t workspace_need(hodlr_t h, int nrhs, int compute_prec) {
                align256(2 * (size_t)std::max<int64_t>(h->mt_total, 1) * nr) +
                align256(4 * (size_t)std::max<int64_t>(h->mpart_total, 1) * nr) +
                align256(4 * (size_t)N * nr) + 4096;
-    // x, contributions, projections, partials, near-field sums
+    // x, contributions, projections, partials, near-field sums (and the
+    // skeleton projections' partials)
     return cs * ((size_t)N * nrhs + (size_t)CT * nr + 2 * (size_t)TT * nr +
                  2 * (size_t)kProjSegMax * (size_t)std::max(h->n_proj_sums, h->p_n_psum) * nr +
-                 (size_t)N * nr) +
+                 (size_t)N * nr + (h->opts.skeleton ? (size_t)h->skel_part_total : 0)) +
            4096;
 }
 

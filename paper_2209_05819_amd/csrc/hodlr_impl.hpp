@@ -269,6 +269,20 @@ struct WorkItem {   // launch planning record: a block (or box) and a sub-range
     int32_t level;
 };
 
+// Skeleton form: the partial sum of one side's skeleton projection of block
+// blk over the sources [lo, lo + cnt) of the other box (side 0: K(sigma, B)
+// x_B, side 1: K(tau, A) x_A), rank values written at dst
+struct SkelProj {
+    int32_t blk, side, lo, cnt;
+    int64_t dst;
+};
+// and, per block, where its partials are: nsf segments of rank values from
+// pf (side 0), nsb from pb (side 1)
+struct SkelSolve {
+    int64_t pf, pb;
+    int32_t nsf, nsb;
+};
+
 }  // namespace hodlr
 
 struct hodlr_handle_s {
@@ -308,6 +322,15 @@ struct hodlr_handle_s {
     int64_t n_proj_items = 0;
     hodlr::WorkItem* exp_items = nullptr;  // 64-row chunks of those blocks (level = side)
     int64_t n_exp_items = 0;
+    // skeleton form: segmented skeleton projections, per-block solves,
+    // 256-row expansions (level = side)
+    hodlr::SkelProj* skel_proj = nullptr;
+    int64_t n_skel_proj = 0;
+    hodlr::SkelSolve* skel_solve = nullptr;
+    hodlr::WorkItem* skel_exp = nullptr;
+    int64_t n_skel_exp = 0;
+    int64_t skel_part_total = 0;           // partial values of the projections
+    int64_t skel_max_rank = 0;
     hodlr::NearItem* near_items = nullptr; // 64-row chunks of the leaves
     int64_t n_near_items = 0;
     int64_t near_max_ranges = 0;           // most near-list boxes of a leaf

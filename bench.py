@@ -493,6 +493,7 @@ def serve_bench(P, torch, W, full=True):
         "throughput_req_per_s": nreq / wall, "matvec_N_nrhs_per_s": cols / wall,
         "launches": int(st1.launches - st0.launches),
         "batched_requests": int(st1.batched_requests - st0.batched_requests),
+        "multiset_launches": int(st1.multiset_launches - st0.multiset_launches),
         "max_concurrent": int(st1.max_concurrent), "failed": int(st1.failed),
         "build_s": round(build, 1),
     }

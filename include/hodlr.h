@@ -317,6 +317,12 @@ typedef struct {
     int max_concurrent;       /* stream slots: launches in flight at once, 1..64 */
     int max_batch_cols;       /* columns of one batched product = largest nrhs, 1..1024 */
     int64_t max_points;       /* largest set (sizes the batch buffers), >= 1 */
+    /* 1: queued products of several sets with FP64 or FP32 factors (not the
+     * skeleton form) share one persistent launch (hodlr_matvec_batch); 0, the
+     * default: one launch per set (on this GPU the per-class route of each
+     * set is faster than the persistent launch, so the shared launch saves
+     * host launches but not GPU time) */
+    int multiset;
 } hodlr_server_opts;
 
 typedef enum { HODLR_REQ_MATVEC = 0, HODLR_REQ_SOLVE = 1 } hodlr_request_kind;

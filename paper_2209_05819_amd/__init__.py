@@ -77,7 +77,7 @@ class SolveInfo(C.Structure):
 
 class ServerOpts(C.Structure):
     _fields_ = [("mem_budget_bytes", C.c_size_t), ("max_concurrent", C.c_int),
-                ("max_batch_cols", C.c_int), ("max_points", C.c_int64)]
+                ("max_batch_cols", C.c_int), ("max_points", C.c_int64), ("multiset", C.c_int)]
 
 
 class Request(C.Structure):
@@ -527,13 +527,14 @@ class Server:
     until the request completes."""
 
     def __init__(self, mem_budget_bytes=0, max_concurrent=8, max_batch_cols=64,
-                 max_points=1 << 18):
+                 max_points=1 << 18, multiset=False):
         o = ServerOpts()
         lib().hodlr_server_default_opts(C.byref(o))
         o.mem_budget_bytes = int(mem_budget_bytes)
         o.max_concurrent = int(max_concurrent)
         o.max_batch_cols = int(max_batch_cols)
         o.max_points = int(max_points)
+        o.multiset = 1 if multiset else 0
         out = _P()
         _check(lib().hodlr_server_create(C.byref(o), C.byref(out)))
         self.s = out.value

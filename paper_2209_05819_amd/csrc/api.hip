@@ -334,6 +334,7 @@ void hodlr_server_default_opts(hodlr_server_opts* o) {
     o->max_concurrent = 8;
     o->max_batch_cols = 64;
     o->max_points = (int64_t)1 << 18;
+    o->multiset = 0;
 }
 
 hodlr_status hodlr_server_create(const hodlr_server_opts* opts, hodlr_server_t* out) {
@@ -346,6 +347,7 @@ hodlr_status hodlr_server_create(const hodlr_server_opts* opts, hodlr_server_t* 
     if (o.max_batch_cols < 1 || o.max_batch_cols > 1024)
         return set_error(HODLR_EINVAL, "max_batch_cols must be 1..1024");
     if (o.max_points < 1) return set_error(HODLR_EINVAL, "max_points must be >= 1");
+    if (o.multiset != 0 && o.multiset != 1) return set_error(HODLR_EINVAL, "multiset must be 0 or 1");
     return guarded([&] {
         if (o.mem_budget_bytes == 0) {
             size_t fr = 0, tot = 0;

@@ -287,8 +287,8 @@ void scheduler(hodlr_server_s* S) {
                 const size_t cap = (size_t)S->o.max_points * S->o.max_batch_cols;
                 size_t elems = 0;
                 const int prec = st.h->opts.storage;
-                const bool batchable =
-                    (prec == HODLR_FP64 || prec == HODLR_FP32) && !st.h->opts.skeleton;
+                const bool batchable = S->o.multiset && (prec == HODLR_FP64 || prec == HODLR_FP32) &&
+                                       !st.h->opts.skeleton;
                 auto take_set = [&](int set) {
                     const int64_t N = S->sets[set].h->N;
                     int cols = 0;

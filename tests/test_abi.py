@@ -41,7 +41,7 @@ def test_struct_layouts_match_header():
     assert P.Info.mfma_proj_elems.offset + 8 == C.sizeof(P.Info)
     assert C.sizeof(P.SolveOpts) == 8 * 2 + 4 * 4
     assert C.sizeof(P.SolveInfo) == 4 * 3 + 4 + 8 + 8 * 64
-    assert C.sizeof(P.ServerOpts) == 8 + 4 + 4 + 8
+    assert C.sizeof(P.ServerOpts) == 8 + 4 + 4 + 8 + 8
     assert C.sizeof(P.Request) == 4 * 3 + 4 + 8 * 2 + 8 * 3 + 8
     assert C.sizeof(P.ServerStats) == 8 * 7 + 8 * 2 + 4 + 4
     assert C.sizeof(P.Tuning) == 4 + 4 * 8 + 4 + 8 * 8 + 8 * 2 + 8

@@ -71,7 +71,7 @@ def test_results_same_alone_and_in_the_mix(P):
     import torch
     # fewer stream slots than sets: requests queue while others run, and the
     # queued products of idle sets share launches
-    srv = P.Server(max_concurrent=2, max_batch_cols=32, max_points=20000)
+    srv = P.Server(max_concurrent=2, max_batch_cols=32, max_points=20000, multiset=True)
     ids, Ns, precs = _sets(P, srv)
     reqs = _requests(P, Ns, 40, 7)
     X = [_tensor(torch, Ns[s], n, 100 + i) for i, (_, s, n) in enumerate(reqs)]

@@ -208,10 +208,11 @@ def multi_rhs_fp32(P, torch, W, steps, n_override=0):
 def small_bench(P, torch, W, reps=200):
     """The small workload (4096 points uniform in [-1,1]^2, log r, leaf 64,
     ACA 1e-8, FP64, one U[-1,1] right-hand side): the autotuner's choice
-    (tile shapes per block class, per-class launches or one persistent
-    launch), and the per-call latency of the product on both routes,
-    launched eagerly and replayed from a captured HIP graph; the error
-    against the direct N^2 sum on every row."""
+    (tile shapes per block class; per-class launches with the near field on
+    a second stream or all on one stream, or one persistent launch), and
+    the per-call latency of the product on the three routes, launched
+    eagerly and replayed from a captured HIP graph; the error against the
+    direct N^2 sum on every row."""
     import oracle
     w = W.WORKLOADS["uniform2d_log_n4096"]
     pts, q = w.points(), w.rhs()[:, 0]
@@ -242,7 +243,7 @@ def small_bench(P, torch, W, reps=200):
         return t
 
     routes = {}
-    for name, route in (("per_class", 0), ("persistent", 1)):
+    for name, route in (("per_class", 0), ("per_class_one_stream", 2), ("persistent", 1)):
         P.hodlr_set_route(H.h, route)
         side = torch.cuda.Stream()
         side.wait_stream(torch.cuda.current_stream())
@@ -280,10 +281,12 @@ def small_bench(P, torch, W, reps=200):
     return {
         "workload": w.name, "N": N, "d": w.d, "kernel": "log r, diag 0", "leaf": w.leaf,
         "aca_tol": w.tol, "kappa": info.kappa, "dtype": "f64",
-        "autotune": {"route": "persistent" if tune.route == 1 else "per_class",
+        "autotune": {"route": {0: "per_class", 1: "persistent",
+                               2: "per_class_one_stream"}[tune.route],
                      "class_choice": list(tune.class_choice)[:6],
                      "class_ms": [round(v, 5) for v in list(tune.class_ms)[:6]],
                      "per_class_route_ms": tune.class_route_ms,
+                     "per_class_one_stream_ms": tune.one_stream_ms,
                      "persistent_route_ms": tune.persistent_ms},
         "routes": routes,
         "gpu_time": "HIP events between back-to-back calls on the stream",

@@ -185,8 +185,10 @@ hodlr_status hodlr_reserve_workspace(hodlr_t h, int nrhs, int compute_prec);
  * Product" either way): 1 = one persistent launch that walks every stage
  * (permutation, the blocks of every level, the near field, the sums of the
  * segmented blocks, the gather) as an ordered queue of work; 0 = one launch
- * per stage and block size class, the near field on a second stream; -1
- * (default, not chosen) = per-class launches.  The
+ * per stage and block size class, the near field on a second stream; 2 = the
+ * same launches all on the caller's stream (no fork and join: fewer
+ * operations for a launch-bound product); -1 (default, not chosen) = route
+ * 0.  The
  * persistent route applies to FP64 factors in FP64 arithmetic and FP32
  * factors in FP32 arithmetic (not BF16, not the skeleton form); other
  * products take the per-class route whatever is set.  EINVAL for a null
@@ -201,6 +203,7 @@ typedef struct {
     double class_route_ms;  /* product time on the per-class route, ms */
     double persistent_ms;   /* product time on the persistent route, ms (0: not applicable) */
     int seg_side;           /* persistent route: widest block one workgroup streams alone */
+    double one_stream_ms;   /* product time on route 2 (per-class, one stream), ms */
 } hodlr_tuning;
 
 /* Autotuner of this handle's product (Alg. "HODLRdD matrix-vector Product"
@@ -212,9 +215,10 @@ typedef struct {
  * class 3, up to 128: <1,2,4> <1,2,8> <2,1,8>; class 4, up to 1024:
  * <4,4,K> <4,4,2K> <8,2,K>; class 5, up to 4608: <8,9,K'> <8,9,2K'>, with
  * K = 2 and K' = 1 in FP64 arithmetic, 4 and 2 in FP32); then the product
- * is timed on the per-class route and on the persistent route (there with
- * the class-4 blocks wider than 1024, 512 or 256 rows segmented over many
- * workgroups, the fastest of the three kept) and the faster route is kept
+ * is timed on the per-class route (near field on a second stream, or all
+ * on the caller's stream) and on the persistent route (there with the
+ * class-4 blocks wider than 1024, 512 or 256 rows segmented over many
+ * workgroups, the fastest of the three kept) and the fastest route is kept
  * (hodlr_set_route).  Allocates scratch X and Y, reserves
  * the workspace, synchronises stream; out (host) receives the times.
  * Errors: those of hodlr_matvec. */

@@ -62,7 +62,7 @@ class Info(C.Structure):
 class Tuning(C.Structure):
     _fields_ = [("route", C.c_int), ("class_choice", C.c_int * 8), ("class_ms", C.c_double * 8),
                 ("class_route_ms", C.c_double), ("persistent_ms", C.c_double),
-                ("seg_side", C.c_int)]
+                ("seg_side", C.c_int), ("one_stream_ms", C.c_double)]
 
 
 class SolveOpts(C.Structure):

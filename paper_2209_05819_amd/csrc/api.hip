@@ -219,7 +219,7 @@ hodlr_status hodlr_matvec(hodlr_t h, const void* X, int64_t ldx, int nrhs, int x
 
 hodlr_status hodlr_set_route(hodlr_t h, int route) {
     if (!h) return set_error(HODLR_EINVAL, "null handle");
-    if (route < -1 || route > 1) return set_error(HODLR_EINVAL, "route must be -1, 0 or 1");
+    if (route < -1 || route > 2) return set_error(HODLR_EINVAL, "route must be -1, 0, 1 or 2");
     h->use_persistent = route;
     return HODLR_OK;
 }

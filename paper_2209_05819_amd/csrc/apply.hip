@@ -3303,7 +3303,9 @@ void matvec(hodlr_t h, const void* X, int64_t ldx, int nrhs, int x_prec, void* Y
         }
         return;
     }
-    run_product(h, X, ldx, nrhs, x_prec, Y, ldy, compute_prec, (char*)h->ws, ev, nev, s, h->aux);
+    // route 2: the near field on the caller's stream too
+    run_product(h, X, ldx, nrhs, x_prec, Y, ldy, compute_prec, (char*)h->ws, ev, nev, s,
+                h->use_persistent == 2 ? s : h->aux);
 }
 
 namespace {
@@ -3490,6 +3492,10 @@ void autotune(hodlr_t h, int nrhs, int x_prec, int compute_prec, hodlr_tuning* o
         auto product = [&] { matvec(h, X, N, nrhs, x_prec, Y, N, compute_prec, nullptr, 0, s); };
         h->use_persistent = 0;
         out->class_route_ms = time_ms(product, s, reps);
+        h->use_persistent = 2;
+        out->one_stream_ms = time_ms(product, s, reps);
+        const int per_class = out->one_stream_ms < out->class_route_ms ? 2 : 0;
+        const double per_class_ms = std::min(out->one_stream_ms, out->class_route_ms);
         h->use_persistent = 1;
         if (persistent_route(h, x_prec, compute_prec)) {
             // the persistent plan's widest block a workgroup streams alone:
@@ -3510,10 +3516,10 @@ void autotune(hodlr_t h, int nrhs, int x_prec, int compute_prec, hodlr_tuning* o
             if (keep != h->p_seg_side) plan_persistent(h, keep);
             out->persistent_ms = best;
             out->seg_side = keep;
-            out->route = out->persistent_ms < out->class_route_ms ? 1 : 0;
+            out->route = out->persistent_ms < per_class_ms ? 1 : per_class;
         } else {
             out->persistent_ms = 0.0;
-            out->route = 0;
+            out->route = per_class;
         }
         h->use_persistent = out->route;
     } catch (...) {

@@ -44,7 +44,7 @@ def test_struct_layouts_match_header():
     assert C.sizeof(P.ServerOpts) == 8 + 4 + 4 + 8 + 8
     assert C.sizeof(P.Request) == 4 * 3 + 4 + 8 * 2 + 8 * 3 + 8
     assert C.sizeof(P.ServerStats) == 8 * 7 + 8 * 2 + 4 + 4
-    assert C.sizeof(P.Tuning) == 4 + 4 * 8 + 4 + 8 * 8 + 8 * 2 + 8
+    assert C.sizeof(P.Tuning) == 4 + 4 * 8 + 4 + 8 * 8 + 8 * 2 + 8 + 8
 
 
 def test_default_opts_and_errors_without_gpu():

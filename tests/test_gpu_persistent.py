@@ -44,10 +44,12 @@ def _host(Y):
         np.float64)
 
 
-def _both_routes(P, torch, H, q, dt, comp):
+def _routes(P, torch, H, q, dt, comp):
+    """The product on route 0 (per-class, near field on a second stream),
+    1 (persistent) and 2 (per-class, one stream)."""
     X = _dev(torch, q, dt)
     out = []
-    for route in (0, 1):
+    for route in (0, 1, 2):
         P.hodlr_set_route(H.h, route)
         Y = torch.full_like(X, float("nan"))
         H.matvec(X, compute_prec=comp, out=Y)
@@ -85,11 +87,13 @@ def test_persistent_equals_per_class(P, orc, d, N, leaf, kern, h, diag, tol, dis
     for nrhs in (1, 3, 7, 11):
         q = W.rhs_normal(N, nrhs, 61 + nrhs)
         q = q[:, 0] if nrhs == 1 else q
-        yc, yp = _both_routes(P, torch, H, q, dt, comp)
+        yc, yp, y1 = _routes(P, torch, H, q, dt, comp)
         assert np.all(np.isfinite(yp))
         err = _rel(yp, yc)
         _say(f"  nrhs={nrhs}: persistent vs per-class {err:.2e}")
         assert err <= rel
+        # the same launches on one stream: the same sums in the same order
+        assert np.array_equal(y1, yc)
     # the persistent product against the direct sum
     q = W.rhs_normal(N, 1, 70)[:, 0]
     rows = np.sort(W.rng(71).choice(N, min(N, 800), replace=False))
@@ -183,8 +187,11 @@ def test_autotuner_keeps_the_product(P, d, N, kern, tol, st):
     y0 = _host(H.matvec(X, compute_prec=storage))
     t = P.hodlr_autotune(H.h, 1, P.FP64 if st == "fp64" else P.FP32, storage)
     _say(f"[autotune] d={d} N={N} {st}: route {t.route}, shapes {list(t.class_choice)[:6]}, "
-         f"per-class {t.class_route_ms:.4f} ms, persistent {t.persistent_ms:.4f} ms")
-    assert t.route in (0, 1) and t.class_route_ms > 0 and t.persistent_ms > 0
-    assert t.route == (1 if t.persistent_ms < t.class_route_ms else 0)
+         f"per-class {t.class_route_ms:.4f} ms, one stream {t.one_stream_ms:.4f} ms, "
+         f"persistent {t.persistent_ms:.4f} ms")
+    assert t.route in (0, 1, 2) and t.class_route_ms > 0 and t.persistent_ms > 0
+    assert t.one_stream_ms > 0
+    times = {0: t.class_route_ms, 2: t.one_stream_ms, 1: t.persistent_ms}
+    assert times[t.route] == min(times.values())
     y1 = _host(H.matvec(X, compute_prec=storage))
     assert _rel(y1, y0) <= rel

@@ -136,12 +136,21 @@ def multi_rhs(P, torch, W, steps, warmup, n_override=0):
     # dominant pass: projections (stage 2) or expansions (stage 3); bytes
     # are the factor elements that pass reads, once
     if st[2] >= st[1]:
-        kern_name, nb, ms = "k_mexp", exp_b, st[2]
+        pass_name, pass_b, pass_ms = "expansions (k_mexp, every level)", exp_b, st[2]
     else:
-        kern_name, nb, ms = "k_mproj", proj_b, st[1]
+        pass_name, pass_b, pass_ms = "projections (k_mproj, every width, k_mreduce)", proj_b, st[1]
+    # the longest single projection launch (width W = 2, 4, 8 waves; the
+    # width-1 launch's events also hold the x conversion before it): its
+    # factor elements and x slices (BF16, 32 columns) over its event time
+    nrp = 16 * ((nrhs + 15) // 16)
+    cm = cls.mean(axis=0)
+    wi = 1 + int(np.argmax(cm[1:4]))
+    kern_name = f"k_mproj<{1 << wi},{nrp // 16}>"
+    nb = 2 * info.mfma_proj_factor_elems[wi] + 2 * nrp * info.mfma_proj_vector_elems[wi]
+    ms = float(cm[wi])
     ach = nb / (ms * 1e-3) / 1e9
-    mfma_tf = 2.0 * 16 * ((nrhs + 15) // 16) * (fe if kern_name == "k_mproj" else
-                                                  info.mfma_expand_factor_elems) / (ms * 1e-3) / 1e12
+    mfma_tf = 2.0 * nrp * info.mfma_proj_factor_elems[wi] / (ms * 1e-3) / 1e12
+    traffic = measured_traffic(w.name, kern_name, "bf16")
     del H
     return {
         "workload": w.name, "N": N, "d": w.d, "nrhs": nrhs, "kernel": "1/r^2, diag 0",
@@ -154,10 +163,15 @@ def multi_rhs(P, torch, W, steps, warmup, n_override=0):
         "stages": ["permute_in", "projections (pass 1)", "expansions (pass 2)",
                    "near_field+permute_out"],
         "build_s": round(build, 2), "kappa": info.kappa, "factor_bytes": int(2 * fe),
-        "roofline": {"bound": "hbm", "kernel": kern_name, "bytes_per_launch": int(nb),
-                     "avg_ms": float(ms), "achieved": ach, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": ach / HBM_PEAK_GBS, "traffic": None,
+        "roofline": {"bound": "hbm", "kernel": kern_name,
+                     "jobs": int(info.mfma_proj_jobs[wi]), "bytes_per_launch": int(nb),
+                     "avg_ms": ms, "achieved": ach, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": ach / HBM_PEAK_GBS, "traffic": traffic,
                      "mfma_tflops": mfma_tf, "mfma_peak_tflops": 2500.0},
+        "pass_roofline": {"pass": pass_name, "bytes": int(pass_b), "ms": float(pass_ms),
+                          "achieved": pass_b / (pass_ms * 1e-3) / 1e9,
+                          "frac": pass_b / (pass_ms * 1e-3) / 1e9 / HBM_PEAK_GBS},
+        "proj_launch_ms": [round(float(v), 4) for v in cm[:4]],
     }
 
 

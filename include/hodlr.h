@@ -197,7 +197,7 @@ hodlr_status hodlr_set_route(hodlr_t h, int route);
 
 /* What hodlr_autotune measured and chose. */
 typedef struct {
-    int route;              /* product route kept: 0 per-class launches, 1 persistent */
+    int route;              /* product route kept: 0 per-class launches, 1 persistent, 2 per-class on one stream */
     int class_choice[8];    /* tile shape kept per single-RHS block class (index below) */
     double class_ms[8];     /* that shape's time per launch of the class, ms */
     double class_route_ms;  /* product time on the per-class route, ms */
@@ -232,8 +232,12 @@ hodlr_status hodlr_autotune(hodlr_t h, int nrhs, int x_prec, int compute_prec,
  * follows the storage) and appear once each; x_prec is that of every X and
  * Y.  Each handle's workspace grows as hodlr_matvec's would; the call
  * returns after the launch finished.  Calls must not overlap other calls on
- * the same handles.  Errors: EINVAL (arguments, mixed or BF16 storage, the
- * skeleton form, a repeated handle, factors missing), ENOMEM, EDEVICE. */
+ * the same handles.  On this GPU the launch is slower than the handles'
+ * own per-class launches (it saves host launches, not device time).
+ * Errors: EINVAL (arguments, mixed or BF16 storage, the skeleton form, a
+ * repeated handle, factors missing), EUNSUPPORTED (a handle with more than
+ * 1632 columns: the launch holds at most 1024 stages, five per eight
+ * columns), ENOMEM, EDEVICE. */
 hodlr_status hodlr_matvec_batch(int nslots, const hodlr_t* hs, const void* const* X,
                                 const int64_t* ldx, const int* nrhs, int x_prec, void* const* Y,
                                 const int64_t* ldy, void* stream);
@@ -373,10 +377,10 @@ hodlr_status hodlr_server_add_set(hodlr_server_t srv, const double* points, int6
 /* Queue a request; returns at once with its id.  The scheduler starts it when
  * its set is idle, a slot is free and its workspace fits the budget; queued
  * products of one set are applied together as one product of their columns,
- * and queued products of other idle sets with the same factor precision
- * (FP64 or FP32) join the same launch: one persistent launch applies up to
- * 16 sets (as far as the slot's buffer of max_points x max_batch_cols
- * doubles holds their columns).
+ * and, with the server option multiset, queued products of other idle sets
+ * with the same factor precision (FP64 or FP32) join the same launch: one
+ * persistent launch applies up to 16 sets (as far as the slot's buffer of
+ * max_points x max_batch_cols doubles holds their columns).
  * Solves run GMRES with iterative refinement on the set itself (FP64
  * residuals; inner GMRES(30) in FP32 arithmetic, to tol).  X and Y must stay
  * valid until the request completes.  Ordering: an event is recorded on

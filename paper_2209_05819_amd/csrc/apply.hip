@@ -29,7 +29,7 @@ namespace {
 constexpr int TP = 256;   // split projection workgroup (4 waves)
 constexpr int TE = 256;   // split expansion workgroup (4 waves share 64 rows)
 constexpr int KB = 16;    // rows reduced together in the fused projection
-constexpr int kFusedMaxRank = 256;  // projections a fused wave keeps in LDS at once
+constexpr int kFusedMaxRank = 64;   // projections a fused wave keeps in LDS at once
 constexpr int kNumClasses = kApplyClasses;  // block size classes of the one-workgroup kernels
 // class-5 blocks (up to 4608 rows) take the segmented route in the persistent
 // plan: streaming one of them per workgroup needs more registers than the

@@ -219,7 +219,8 @@ typedef struct {
  * on the caller's stream) and on the persistent route (there with the
  * class-4 blocks wider than 1024, 512 or 256 rows segmented over many
  * workgroups, the fastest of the three kept) and the fastest route is kept
- * (hodlr_set_route).  Allocates scratch X and Y, reserves
+ * (hodlr_set_route).  Every time is the least of three timings of five
+ * back-to-back calls.  Allocates scratch X and Y, reserves
  * the workspace, synchronises stream; out (host) receives the times.
  * Errors: those of hodlr_matvec. */
 hodlr_status hodlr_autotune(hodlr_t h, int nrhs, int x_prec, int compute_prec,

@@ -399,7 +399,7 @@ def solve_bench(P, torch, W, n_override=0):
     }
 
 
-def gram_solve(P, torch, W, w, pts, q, H64, build, restart=50, max_outer=4):
+def gram_solve(P, torch, W, w, pts, q, H64, build, restart=50, max_outer=2):
     """The Gaussian-mixture workload's own system: the Gram matrix
     K~ U = F with K(i,i) = 1 + 1e-3 (the SVM-style regularised kernel matrix),
     GMRES with iterative refinement to 1e-10, inner GMRES(restart) in FP64 on

@@ -1483,16 +1483,26 @@ constexpr int kSkelPanel = 32;   // rows of a triangular panel (lanes of one wav
 constexpr int kSkelSolveThreads = 128;
 
 // s[i] -= sum_{k0 <= k < k1} M[i][k] s[k] for i0 <= i < i1 (rows of the
-// row-major r x r array M): a wave per row, lanes over k
+// row-major r x r array M): a wave per row, lanes over k; each wave takes
+// four rows at a time so that their loads are in flight together (the
+// solve is a chain of such steps: their latency is its cost)
 template <typename S, typename C>
 __device__ __forceinline__ void skel_row_update(gptr_t<S> M, int r, C* s, int i0, int i1,
                                                 int k0, int k1) {
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
-    for (int i = i0 + wv; i < i1; i += nw) {
-        C a = 0;
-        for (int k = k0 + lane; k < k1; k += 64) a += ldf<C>(M, (int64_t)i * r + k) * s[k];
-        a = wsum(a);
-        if (lane == 0) s[i] -= a;
+    for (int i = i0 + wv; i < i1; i += 4 * nw) {
+        C a[4] = {0, 0, 0, 0};
+        for (int k = k0 + lane; k < k1; k += 64) {
+            const C sk = s[k];
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                if (i + u * nw < i1) a[u] += ldf<C>(M, (int64_t)(i + u * nw) * r + k) * sk;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const C v = wsum(a[u]);
+            if (lane == 0 && i + u * nw < i1) s[i + u * nw] -= v;
+        }
     }
     __syncthreads();
 }
@@ -1504,8 +1514,10 @@ __device__ __forceinline__ void skel_col_update(gptr_t<S> M, int r, C* s, int i0
                                                 int k0, int k1, C (*red)[64]) {
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
     C a = 0;
-    if (lane < pb)
+    if (lane < pb) {
+#pragma unroll 8
         for (int k = k0 + wv; k < k1; k += nw) a += ldf<C>(M, (int64_t)k * r + i0 + lane) * s[k];
+    }
     red[wv][lane] = a;
     __syncthreads();
     if (wv == 0 && lane < pb) {
@@ -1516,17 +1528,28 @@ __device__ __forceinline__ void skel_col_update(gptr_t<S> M, int r, C* s, int i0
     __syncthreads();
 }
 
-// the diagonal block M[p .. p+pb)^2 into LDS (D[i][k], rows padded) and the
-// reciprocals of its diagonal
+// the diagonal block M[p .. p+pb)^2 into LDS (D[i][k], rows padded, zero
+// past pb) and the reciprocals of its diagonal
 template <typename S, typename C>
 __device__ __forceinline__ void skel_stage_diag(gptr_t<S> M, int r, int p, int pb, C (*D)[kSkelPanel + 1],
                                                 C* rd) {
-    for (int e = threadIdx.x; e < pb * pb; e += blockDim.x) {
-        const int i = e / pb, k = e - i * pb;
-        D[i][k] = ldf<C>(M, (int64_t)(p + i) * r + p + k);
+    // every load issued before the first store (a loop would wait for each)
+    constexpr int kU = kSkelPanel * kSkelPanel / kSkelSolveThreads;
+    C v[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+        const int e = threadIdx.x + u * kSkelSolveThreads;
+        const int i = e / kSkelPanel, k = e % kSkelPanel;
+        v[u] = (i < pb && k < pb) ? ldf<C>(M, (int64_t)(p + i) * r + p + k) : (C)0;
+    }
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+        const int e = threadIdx.x + u * kSkelSolveThreads;
+        D[e / kSkelPanel][e % kSkelPanel] = v[u];
     }
     __syncthreads();
-    if (threadIdx.x < pb) rd[threadIdx.x] = (C)1 / D[threadIdx.x][threadIdx.x];
+    if (threadIdx.x < kSkelPanel)
+        rd[threadIdx.x] = threadIdx.x < pb ? (C)1 / D[threadIdx.x][threadIdx.x] : (C)0;
     __syncthreads();
 }
 

@@ -719,9 +719,8 @@ def main():
                     help="also run a plain device copy of known size (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path "
-              "(the sharding design is described in DESIGN.md); run with --gpus 1.",
-              file=sys.stderr)
+        print("bench.py measures one GPU: the library has no multi-GPU path; "
+              "run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -37,7 +37,7 @@ typedef enum {
     HODLR_EDEVICE = 3,      /* a HIP call failed */
     HODLR_EDUPLICATE = 4,   /* two distinct points coincide under a singular kernel */
     HODLR_ENONFINITE = 5,   /* NaN or Inf in the points, or in a solve's F, guess or residual */
-    HODLR_EUNSUPPORTED = 6  /* valid request this build does not handle */
+    HODLR_EUNSUPPORTED = 6  /* valid request this library does not handle */
 } hodlr_status;
 
 /* Kernel functions of the paper's sec. 3 list (F1 1/r, F2 log r, F5 r,

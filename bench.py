@@ -139,13 +139,16 @@ def multi_rhs(P, torch, W, steps, warmup, n_override=0):
         pass_name, pass_b, pass_ms = "expansions (k_mexp, every level)", exp_b, st[2]
     else:
         pass_name, pass_b, pass_ms = "projections (k_mproj, every width, k_mreduce)", proj_b, st[1]
-    # the longest single projection launch (width W = 2, 4, 8 waves; the
-    # width-1 launch's events also hold the x conversion before it): its
-    # factor elements and x slices (BF16, 32 columns) over its event time
+    # the longest single projection launch (panels up to 128, 256, 512
+    # columns: <waves, column tiles, 64-column groups per wave> = <1,CT,2>,
+    # <2,CT,2>, <2,CT,4>; the events of the launch for panels up to 64 also
+    # hold the x conversion before it): its factor elements and x slices
+    # (BF16, 32 columns) over its event time
     nrp = 16 * ((nrhs + 15) // 16)
     cm = cls.mean(axis=0)
     wi = 1 + int(np.argmax(cm[1:4]))
-    kern_name = f"k_mproj<{1 << wi},{nrp // 16}>"
+    kern_name = "k_mproj<{},{},{}>".format(*{1: (1, nrp // 16, 2), 2: (2, nrp // 16, 2),
+                                             3: (2, nrp // 16, 4)}[wi])
     nb = 2 * info.mfma_proj_factor_elems[wi] + 2 * nrp * info.mfma_proj_vector_elems[wi]
     ms = float(cm[wi])
     ach = nb / (ms * 1e-3) / 1e9

@@ -574,8 +574,10 @@ __global__ __launch_bounds__(256) void k_lr_group(const BlockDesc* __restrict__ 
 // runs in two passes that each read every factor once:
 //   pass 1 (k_mproj): per stored block t = V x_B and, when the block also
 //     stands for its transpose, s = U^T x_A, on 16x16x32 BF16 matrix cores;
-//     a workgroup of W waves takes a panel of at most 64 W columns, 64 per
-//     wave, 16 terms at a time, and sums its waves' partials through LDS.
+//     a workgroup of W waves takes a panel of at most 64 W G columns, 64 G
+//     per wave, 16 terms at a time, and sums its waves' partials through
+//     LDS (panels up to 64 columns: W = 1, G = 1; 128: 1, 2; 256: 2, 2;
+//     512: 2, 4 -- fewer waves with more columns each meet less often).
 //     Blocks wider than 512 are projected in several panels whose FP32
 //     partials k_mreduce adds in panel order.  Projections are stored in
 //     BF16 in the operand layout of pass 2.
@@ -651,12 +653,14 @@ __device__ __forceinline__ int64_t tidx(int64_t base, int k, int c, int nrp) {
     return base + ((int64_t)(k >> 2) * nrp + c) * 4 + (k & 3);
 }
 
-template <int W, int CT>
+// G: 64-column groups per wave (a panel of at most 64 W G columns)
+template <int W, int CT, int G = 1>
 __global__ __launch_bounds__(64 * W) void k_mproj(const MJob* __restrict__ jobs, int64_t njobs,
                                                   const uint16_t* __restrict__ xr,
                                                   uint16_t* __restrict__ tproj,
                                                   float* __restrict__ part) {
     constexpr int NRP = 16 * CT;
+    constexpr int KT = 2 * G;   // 32-column steps per wave
     __shared__ f32x4_t red[W > 1 ? W : 1][CT][64];
     const int64_t jx = xcd_item(njobs);
     if (jx < 0) return;   // padding of the last XCD's range (whole workgroup)
@@ -664,7 +668,7 @@ __global__ __launch_bounds__(64 * W) void k_mproj(const MJob* __restrict__ jobs,
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int a = lane & 15, q = lane >> 4;
     const int64_t ld = fstride<bf16>(J.len);
-    const int col0 = J.p0 + wv * MR;
+    const int col0 = J.p0 + wv * MR * G;
     const int cend = J.p0 + J.plen;
     // Buffer loads throughout: a lane with nothing to read (column past the
     // panel, term past the rank, no next chunk) gets an offset moved past
@@ -676,9 +680,9 @@ __global__ __launch_bounds__(64 * W) void k_mproj(const MJob* __restrict__ jobs,
     // x operand (K = factor column, N = right-hand side): lane holds columns
     // col0 + 32 kt + 8 q + e (e < 8) of right-hand side 16 ct + a
     const __amdgpu_buffer_rsrc_t xrs = rsrc((uint64_t)(xr + (int64_t)J.x0 * NRP));
-    bf16x8_t xs[2][CT];
+    bf16x8_t xs[KT][CT];
 #pragma unroll
-    for (int kt = 0; kt < 2; ++kt)
+    for (int kt = 0; kt < KT; ++kt)
 #pragma unroll
         for (int ct = 0; ct < CT; ++ct) {
             u16x8_t u;
@@ -693,22 +697,22 @@ __global__ __launch_bounds__(64 * W) void k_mproj(const MJob* __restrict__ jobs,
     // factor words of a 16-term chunk: lane holds term k0 + a, columns
     // col0 + 32 kt + 8 q .. + 7
     const __amdgpu_buffer_rsrc_t frs = rsrc(J.F);
-    auto load_chunk = [&](int k0, u32x4 (&w)[2]) {
+    auto load_chunk = [&](int k0, u32x4 (&w)[KT]) {
         const int k = k0 + a;
 #pragma unroll
-        for (int kt = 0; kt < 2; ++kt) {
+        for (int kt = 0; kt < KT; ++kt) {
             const int c8 = col0 + 32 * kt + 8 * q;
             const bool ok = k < J.r && c8 < cend;
             const uint32_t off = (uint32_t)(2 * ((int64_t)k * ld + c8)) + ((uint32_t)!ok << 31);
             w[kt] = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(frs, (int)off, 0, 0));
         }
     };
-    auto process = [&](int k0, const u32x4 (&wc)[2]) {
+    auto process = [&](int k0, const u32x4 (&wc)[KT]) {
         f32x4_t t[CT];
 #pragma unroll
         for (int ct = 0; ct < CT; ++ct) t[ct] = f32x4_t{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int kt = 0; kt < 2; ++kt) {
+        for (int kt = 0; kt < KT; ++kt) {
             const bf16x8_t fv = __builtin_bit_cast(bf16x8_t, wc[kt]);
 #pragma unroll
             for (int ct = 0; ct < CT; ++ct)
@@ -747,7 +751,7 @@ __global__ __launch_bounds__(64 * W) void k_mproj(const MJob* __restrict__ jobs,
     };
     // two register buffers in turn: the next chunk's loads are in flight
     // while the current one is multiplied (no copy between the buffers)
-    u32x4 wa[2], wb[2];
+    u32x4 wa[KT], wb[KT];
     load_chunk(0, wa);
     for (int k0 = 0;;) {
         load_chunk(k0 + 16, wb);
@@ -2748,9 +2752,9 @@ void run_matvec(hodlr_t h, const XT* X, int64_t ldx, int nrhs, XT* Y, int64_t ld
                     const unsigned g = xcd_grid(cnt);
                     switch (w) {
                     case 0: k_mproj<1, CTn><<<g, 64, 0, s>>>(jb, cnt, xr, tproj, part); break;
-                    case 1: k_mproj<2, CTn><<<g, 128, 0, s>>>(jb, cnt, xr, tproj, part); break;
-                    case 2: k_mproj<4, CTn><<<g, 256, 0, s>>>(jb, cnt, xr, tproj, part); break;
-                    default: k_mproj<8, CTn><<<g, 512, 0, s>>>(jb, cnt, xr, tproj, part); break;
+                    case 1: k_mproj<1, CTn, 2><<<g, 64, 0, s>>>(jb, cnt, xr, tproj, part); break;
+                    case 2: k_mproj<2, CTn, 2><<<g, 128, 0, s>>>(jb, cnt, xr, tproj, part); break;
+                    default: k_mproj<2, CTn, 4><<<g, 128, 0, s>>>(jb, cnt, xr, tproj, part); break;
                     }
                     HIP_CHECK(hipGetLastError());
                 }

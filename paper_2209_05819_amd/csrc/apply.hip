@@ -576,8 +576,9 @@ __global__ __launch_bounds__(256) void k_lr_group(const BlockDesc* __restrict__ 
 //     stands for its transpose, s = U^T x_A, on 16x16x32 BF16 matrix cores;
 //     a workgroup of W waves takes a panel of at most 64 W G columns, 64 G
 //     per wave, 16 terms at a time, and sums its waves' partials through
-//     LDS (panels up to 64 columns: W = 1, G = 1; 128: 1, 2; 256: 2, 2;
-//     512: 2, 4 -- fewer waves with more columns each meet less often).
+//     LDS (32 right-hand sides, panels up to 64 columns: W = 1, G = 1;
+//     128: 1, 2; 256: 2, 2; 512: 2, 4 -- fewer waves with more columns each
+//     meet less often; 16 right-hand sides: W = 1, 2, 4, 8 and G = 1).
 //     Blocks wider than 512 are projected in several panels whose FP32
 //     partials k_mreduce adds in panel order.  Projections are stored in
 //     BF16 in the operand layout of pass 2.
@@ -2750,11 +2751,24 @@ void run_matvec(hodlr_t h, const XT* X, int64_t ldx, int nrhs, XT* Y, int64_t ld
                 if (cnt) {
                     const MJob* jb = h->mjobs + n0;
                     const unsigned g = xcd_grid(cnt);
-                    switch (w) {
-                    case 0: k_mproj<1, CTn><<<g, 64, 0, s>>>(jb, cnt, xr, tproj, part); break;
-                    case 1: k_mproj<1, CTn, 2><<<g, 64, 0, s>>>(jb, cnt, xr, tproj, part); break;
-                    case 2: k_mproj<2, CTn, 2><<<g, 128, 0, s>>>(jb, cnt, xr, tproj, part); break;
-                    default: k_mproj<2, CTn, 4><<<g, 128, 0, s>>>(jb, cnt, xr, tproj, part); break;
+                    // 32 columns: fewer waves per job, two or four column
+                    // groups each; 16 columns: one group per wave (its
+                    // near field runs beside this pass and takes more of
+                    // the chip when the pass holds fewer, fuller waves)
+                    if constexpr (CTn == 2) {
+                        switch (w) {
+                        case 0: k_mproj<1, CTn><<<g, 64, 0, s>>>(jb, cnt, xr, tproj, part); break;
+                        case 1: k_mproj<1, CTn, 2><<<g, 64, 0, s>>>(jb, cnt, xr, tproj, part); break;
+                        case 2: k_mproj<2, CTn, 2><<<g, 128, 0, s>>>(jb, cnt, xr, tproj, part); break;
+                        default: k_mproj<2, CTn, 4><<<g, 128, 0, s>>>(jb, cnt, xr, tproj, part); break;
+                        }
+                    } else {
+                        switch (w) {
+                        case 0: k_mproj<1, CTn><<<g, 64, 0, s>>>(jb, cnt, xr, tproj, part); break;
+                        case 1: k_mproj<2, CTn><<<g, 128, 0, s>>>(jb, cnt, xr, tproj, part); break;
+                        case 2: k_mproj<4, CTn><<<g, 256, 0, s>>>(jb, cnt, xr, tproj, part); break;
+                        default: k_mproj<8, CTn><<<g, 512, 0, s>>>(jb, cnt, xr, tproj, part); break;
+                        }
                     }
                     HIP_CHECK(hipGetLastError());
                 }

@@ -2,9 +2,12 @@
 of work) against the per-class launches and the direct sum, alone, under
 graph capture, and for several handles in one launch (needs an MI355X).
 
-Both routes run the same per-item arithmetic except the class-5 blocks wider
-than 2304 rows and columns, which the persistent route applies by segmented
-projections: the products agree to 1e-13 relative (FP64) or 1e-5 (FP32).
+The persistent route applies every class-5 block (blocks of 1025 to 4608
+rows and columns), and the class-4 blocks wider than a side the autotuner
+may choose, by segmented projections; everything else runs the same
+per-item arithmetic on both routes: the products agree to 1e-13 relative
+(FP64) or 1e-5 (FP32).  Route 2, the per-class launches without the second
+stream, gives the same bits as route 0.
 """
 import sys
 
@@ -174,9 +177,9 @@ def test_batch_of_handles_equals_separate_products(P, st):
                                              (3, 30000, "inv_r", 1e-10, "fp64"),
                                              (3, 30000, "inv_r", 1e-8, "fp32")])
 def test_autotuner_keeps_the_product(P, d, N, kern, tol, st):
-    """The autotuner times every tile shape of every block class and both
-    routes and keeps the fastest; the product after tuning equals the default
-    one (the shapes change only the order of the sums)."""
+    """The autotuner times every tile shape of every block class and the
+    three routes and keeps the fastest; the product after tuning equals the
+    default one (the shapes change only the order of the sums)."""
     import torch
     storage = P.FP64 if st == "fp64" else P.FP32
     dt = torch.float64 if st == "fp64" else torch.float32

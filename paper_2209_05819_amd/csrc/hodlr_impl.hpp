@@ -41,15 +41,13 @@ struct KParams {
 };
 
 // 1/sqrt(x), x > 0, in FP64: the hardware estimate refined by two Newton
-// steps y <- y + y (1 - x y^2) / 2, each of which roughly doubles the number
-// of correct bits.
+// steps y <- y (3/2 - (x/2) y^2), each of which roughly doubles the number
+// of correct bits (three operations a step: y^2, one FMA, one product).
 __device__ __forceinline__ double rsqrt_fp64(double x) {
     double y = __builtin_amdgcn_rsq(x);
+    const double hx = 0.5 * x;
 #pragma unroll
-    for (int i = 0; i < 2; ++i) {
-        const double r = fma(-(x * y), y, 1.0);
-        y = fma(0.5 * y, r, y);
-    }
+    for (int i = 0; i < 2; ++i) y *= fma(-hx, y * y, 1.5);
     return y;
 }
 

@@ -270,8 +270,9 @@ def hodlr_matvec_noalloc(h: int, X, Y, compute_prec: int = FP64, stream=None) ->
 
 
 def hodlr_set_route(h: int, route: int) -> None:
-    """1: one persistent launch per product; 0: per-stage, per-class launches;
-    -1: by size (the default)."""
+    """0: per-stage, per-class launches, the near field on a second stream;
+    1: one persistent launch per product; 2: the per-class launches on the
+    caller's stream only; -1: not chosen (route 0, the default)."""
     _check(lib().hodlr_set_route(C.c_void_p(h), int(route)))
 
 

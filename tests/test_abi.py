@@ -71,6 +71,18 @@ def test_default_opts_and_errors_without_gpu():
     assert st == 1 and b"null" in L.hodlr_last_error()
     st = L.hodlr_matvec(None, None, 0, 1, 0, None, 0, 0, None)
     assert st == 1
+    # route and server options are checked before any device work too
+    assert L.hodlr_set_route(None, 1) == 1 and b"null" in L.hodlr_last_error()
+    srv = C.c_void_p()
+    for field, bad in (("multiset", 2), ("max_concurrent", 0), ("max_batch_cols", 1025),
+                       ("max_points", 0)):
+        o = P.ServerOpts()
+        L.hodlr_server_default_opts(C.byref(o))
+        assert o.multiset == 0 and o.max_concurrent == 8
+        setattr(o, field, bad)
+        assert L.hodlr_server_create(C.byref(o), C.byref(srv)) == 1
+        assert field.encode() in L.hodlr_last_error()
+    assert srv.value is None
 
 
 def test_product_path_fails_loudly_without_library(tmp_path, monkeypatch):

@@ -198,3 +198,5 @@ def test_autotuner_keeps_the_product(P, d, N, kern, tol, st):
     assert times[t.route] == min(times.values())
     y1 = _host(H.matvec(X, compute_prec=storage))
     assert _rel(y1, y0) <= rel
+    with pytest.raises(P.HodlrError, match="EINVAL"):
+        P.hodlr_set_route(H.h, 3)
